@@ -1,0 +1,158 @@
+/*
+ * perc.h -- percolation inspection of carbon-nanotube fibers on AMD MI355X (gfx950).
+ *
+ * The method is the Markov-chain inspection of Xu, Xu & Yakobson, "Site-percolation
+ * threshold of carbon nanotube fibers -- fast inspection of percolation with Markov
+ * stochastic theory": a fiber is a modified FCC lattice of tubes (Sec. II.A, Fig. 1;
+ * 12 side contacts + 2 end contacts per tube), each tube metallic with probability p;
+ * a random walker hops to a uniformly chosen metallic contact (Eq. 1-2); probability
+ * mass is injected on the metallic tubes of one end and pushed forward by repeated
+ * sparse matrix-vector products, a detector joined to every metallic tube of the far
+ * end absorbs it (Sec. II.B), and the configuration percolates iff the detector ever
+ * receives non-zero probability (Eq. 3-4: first-passage probabilities).
+ *
+ * Conventions shared by every call:
+ *  - Geometry. W is the hex radius of the hexagonal cross-section in tube spacings
+ *    (3W(W+1)+1 columns); L is the number of (111) layers, stacked A,B,C. Column (q,r)
+ *    (axial coordinates) carries the layers k = (q - r) mod 3, +3, +6, ... < L.
+ *  - Canonical site order: lexicographic (k, q, r); N sites; site s is bit s % 32 of
+ *    word s / 32 of a configuration (LSB first), ceil(N/32) words per configuration,
+ *    configurations back to back. Padding bits past N are ignored.
+ *  - Surfaces: start = the tubes of layers 0..2 (one per column), far = the tubes of
+ *    layers L-3..L-1 (one per column). The start mass is 1/|S0| on each metallic start
+ *    tube; deg counts metallic contacts plus the detector edge of a far tube; a
+ *    metallic tube of degree 0 keeps its mass (self-loop).
+ *  - steps: the number of forward steps the inspection took: d+1 for a percolating
+ *    configuration whose nearest far tube is d contacts from the start set (the first
+ *    step with non-zero detector probability), else the step at which the reached set
+ *    stopped growing; 0 when no start tube is metallic.
+ *  - Device pointers are HIP device memory of the current device; host pointers are
+ *    ordinary memory. `stream` is a hipStream_t (NULL = the default stream). Calls
+ *    marked async enqueue work on `stream` and return; the caller keeps every buffer
+ *    alive until the stream is synchronised.
+ *  - Errors: a negative PERC_E* code; perc_last_error() gives a message (per thread,
+ *    valid until the next call on that thread). No call aborts the process.
+ */
+#ifndef PERC_H
+#define PERC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PERC_OK = 0,
+    PERC_EINVAL = -1,    /* invalid argument */
+    PERC_ENOMEM = -2,    /* device or host allocation failed */
+    PERC_EHIP = -3,      /* a HIP runtime call failed */
+    PERC_EBUSY = -4,     /* server: over the memory budget or queue full */
+    PERC_ECANCELED = -5, /* server: request cancelled */
+    PERC_ECAP = -6       /* the step cap N+1 was reached (impossible for a valid lattice) */
+};
+
+/* Execution forms of an inspection batch (all give identical results). */
+enum {
+    PERC_FORM_AUTO = 0,    /* chosen from the shape and batch size (autotuned if cached) */
+    PERC_FORM_PLAIN = 1,   /* one configuration at a time; the host checks the stop flags
+                              after every step (the paper's per-configuration loop) */
+    PERC_FORM_SPAN = 2,    /* many configurations at once, each spread over workgroups;
+                              one launch per step over a device-built work list, replayed
+                              as a HIP graph */
+    PERC_FORM_PERSIST = 3  /* one workgroup per configuration pulled from a device queue;
+                              the whole inspection (sampling included) in one launch */
+};
+
+typedef struct perc_options {
+    int32_t form;        /* PERC_FORM_* */
+    int32_t depth;       /* unit cells per chunk: 1, 3, 5, 7, 9 or 15; 0 = choose */
+    int32_t block;       /* threads per workgroup, multiple of 64, <= 1024; 0 = choose */
+    int32_t grid;        /* workgroups per launch; 0 = choose */
+    int32_t graph_steps; /* span form: steps per graph replay; 0 = choose */
+} perc_options;
+
+typedef struct perc_lattice perc_lattice;
+
+/* ---- lattice (Sec. II.A, Fig. 1) ------------------------------------------------ */
+
+/* Build the fiber lattice of hex radius W >= 0 and L >= 1 layers. Returns NULL on a
+ * bad argument or more than 2^31-1 sites. Owned by the caller; immutable; safe to use
+ * from several threads and streams at once. */
+perc_lattice* perc_lattice_create(int32_t W, int32_t L);
+void perc_lattice_destroy(perc_lattice* lat); /* NULL-safe */
+
+int64_t perc_lattice_sites(const perc_lattice* lat);   /* N */
+int64_t perc_lattice_words(const perc_lattice* lat);   /* ceil(N/32) */
+int32_t perc_lattice_columns(const perc_lattice* lat); /* 3W(W+1)+1 */
+/* Device bytes one configuration occupies while it is inspected (state and codes). */
+int64_t perc_lattice_state_bytes(const perc_lattice* lat);
+
+/* Coordinates of canonical site s (host). PERC_EINVAL if s is out of range. */
+int perc_site_coord(const perc_lattice* lat, int64_t s, int32_t* q, int32_t* r, int32_t* k);
+
+/* The contacts of canonical site s, ascending (host): side contacts (FCC nearest
+ * neighbours) and end contacts (same column, 3 layers away). nbr must hold 14
+ * entries; *count receives the number written. */
+int perc_site_neighbors(const perc_lattice* lat, int64_t s, int64_t* nbr, int32_t* count);
+
+const char* perc_last_error(void);
+
+/* ---- sampling (Sec. II.A: each tube metallic with probability p) ----------------- */
+
+/* Occupancy bits of configurations cfg0 .. cfg0+n_cfg-1 (device, async). Tube s of
+ * configuration c is metallic iff word s%4 of Philox4x32-10 (Salmon et al., SC'11) with
+ * counter (s/4, c mod 2^32, c / 2^32, W<<16 | L) and key (seed mod 2^32, seed / 2^32)
+ * is below floor(p * 2^32). p in [0, 1]. The stream does not depend on p, so lower p
+ * occupies a subset of the tubes of higher p (common random numbers). */
+int perc_sample(const perc_lattice* lat, double p, uint64_t seed, int64_t cfg0, int64_t n_cfg,
+                uint32_t* occ_bits, void* stream);
+
+/* ---- inspection (Sec. II.B) --------------------------------------------------------- */
+
+/* Decide percolation of n_cfg >= 0 configurations given as canonical occupancy bits
+ * (device, n_cfg * words uint32). perc (device, n_cfg bytes) receives 0/1 and steps
+ * (device, n_cfg int32, may be NULL) the step counts. Async. Work memory is taken
+ * stream-ordered from the device pool and returned before the call's work completes. */
+int perc_inspect(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc,
+                 int32_t* steps, void* stream);
+
+/* As perc_inspect, with the execution form chosen by `opt` (NULL = automatic) and the
+ * optional output hit (device, n_cfg float, may be NULL): the probability that the
+ * walker hits the detector for the first time at step `steps` (0 if not percolating),
+ * computed in FP32 -- it underflows to 0 on long paths, the decision never uses it. */
+int perc_inspect_ex(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc,
+                    int32_t* steps, float* hit, const perc_options* opt, void* stream);
+
+/* ---- percolation probability Pi(p) (Sec. III) ------------------------------------ */
+
+typedef struct perc_pi_out {
+    int64_t n_perc;  /* out: number of percolating configurations */
+    double pi;       /* out: n_perc / n_cfg (0 when n_cfg = 0) */
+    uint8_t* bits;   /* in: device buffer for the n_cfg decisions, or NULL */
+    int32_t* steps;  /* in: device buffer for the n_cfg step counts, or NULL */
+    float* hit;      /* in: device buffer for the n_cfg first-hit probabilities, or NULL */
+} perc_pi_out;
+
+/* Sample configurations 0 .. n_cfg-1 of the Philox stream `seed` at probability p
+ * (as perc_sample) and inspect them. Synchronous: returns after n_perc and pi are
+ * known; the device buffers in `out` are complete on return. */
+int perc_pi(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, perc_pi_out* out, void* stream);
+int perc_pi_ex(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, perc_pi_out* out,
+               const perc_options* opt, void* stream);
+
+/* ---- test hook ------------------------------------------------------------------ */
+
+/* Exactly K >= 0 forward steps of one configuration (occ_bits: device, words uint32)
+ * with no early exit. x_out (device, N+1 floats): the probability of each tube after K
+ * steps in canonical order (0 at insulating tubes), then the detector's accumulated
+ * probability. reach_out (device, N+1 bytes): 1 where the probability is non-zero in
+ * exact arithmetic (the reached set), then the detector. Async. */
+int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t K, float* x_out,
+                     uint8_t* reach_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERC_H */

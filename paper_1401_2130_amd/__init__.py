@@ -1,0 +1,244 @@
+"""perc -- percolation inspection of carbon-nanotube fibers on MI355X (gfx950).
+
+Thin ``ctypes`` binding of the C ABI in ``include/perc.h`` (``libperc.so``). The
+functions keep the C names; arguments are marshalled from torch device tensors,
+which serve only as device memory and streams. Every step of the inspection runs in
+the HIP kernels of the library; there is no Python or CPU fallback: importing the
+package raises when the library has not been built.
+
+Conventions (see ``include/perc.h``): occupancy is ``int32`` tensors holding the
+canonical bit words (``[n_cfg, words]``); decisions are ``uint8``, step counts
+``int32``, first-hit probabilities ``float32``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch  # loaded first so that libperc.so binds to the same HIP runtime
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_build", "libperc.so")
+
+PERC_OK, PERC_EINVAL, PERC_ENOMEM, PERC_EHIP, PERC_EBUSY, PERC_ECANCELED, PERC_ECAP = 0, -1, -2, -3, -4, -5, -6
+FORM_AUTO, FORM_PLAIN, FORM_SPAN, FORM_PERSIST = 0, 1, 2, 3
+_FORMS = {"auto": FORM_AUTO, "plain": FORM_PLAIN, "span": FORM_SPAN, "persist": FORM_PERSIST}
+
+
+class PercError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"perc error {code}: {msg}")
+        self.code = code
+
+
+class perc_options(C.Structure):
+    _fields_ = [("form", C.c_int32), ("depth", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
+                ("graph_steps", C.c_int32)]
+
+
+class perc_pi_out(C.Structure):
+    _fields_ = [("n_perc", C.c_int64), ("pi", C.c_double), ("bits", C.c_void_p), ("steps", C.c_void_p),
+                ("hit", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1401_2130_amd.build` "
+                          "(or __graft_entry__.build()); there is no fallback path")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    lib.perc_lattice_create.restype = vp
+    lib.perc_lattice_create.argtypes = [i32, i32]
+    lib.perc_lattice_destroy.argtypes = [vp]
+    for f in ("perc_lattice_sites", "perc_lattice_words", "perc_lattice_state_bytes"):
+        getattr(lib, f).restype = i64
+        getattr(lib, f).argtypes = [vp]
+    lib.perc_lattice_columns.restype = i32
+    lib.perc_lattice_columns.argtypes = [vp]
+    lib.perc_site_coord.argtypes = [vp, i64, vp, vp, vp]
+    lib.perc_site_neighbors.argtypes = [vp, i64, vp, vp]
+    lib.perc_last_error.restype = C.c_char_p
+    lib.perc_sample.argtypes = [vp, dbl, C.c_uint64, i64, i64, vp, vp]
+    lib.perc_inspect.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.perc_inspect_ex.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(perc_options), vp]
+    lib.perc_pi.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), vp]
+    lib.perc_pi_ex.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), C.POINTER(perc_options), vp]
+    lib.perc_state_after.argtypes = [vp, vp, i32, vp, vp, vp]
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ("perc_lattice_create", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
+            "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
+            "perc_last_error", "perc_sample", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
+            "perc_state_after")
+
+
+def perc_last_error() -> str:
+    return _lib.perc_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != PERC_OK:
+        raise PercError(rc, perc_last_error())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dptr(t: Optional[torch.Tensor], dtype=None, numel=None) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"expected at least {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def _options(form="auto", depth=0, block=0, grid=0, graph_steps=0) -> perc_options:
+    f = _FORMS[form] if isinstance(form, str) else int(form)
+    return perc_options(f, int(depth), int(block), int(grid), int(graph_steps))
+
+
+class Lattice:
+    """Handle of ``perc_lattice_create(W, L)`` (destroyed with the object)."""
+
+    def __init__(self, W: int, L: int):
+        h = _lib.perc_lattice_create(int(W), int(L))
+        if not h:
+            raise PercError(PERC_EINVAL, perc_last_error())
+        self._h = h
+        self.W, self.L = int(W), int(L)
+        self.n = int(_lib.perc_lattice_sites(h))
+        self.words = int(_lib.perc_lattice_words(h))
+        self.columns = int(_lib.perc_lattice_columns(h))
+        self.state_bytes = int(_lib.perc_lattice_state_bytes(h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.perc_lattice_destroy(h)
+            self._h = None
+
+    def __repr__(self):
+        return f"Lattice(W={self.W}, L={self.L}, sites={self.n})"
+
+
+def perc_lattice_create(W: int, L: int) -> Lattice:
+    return Lattice(W, L)
+
+
+def perc_lattice_destroy(lat: Lattice) -> None:
+    h = getattr(lat, "_h", None)
+    if h:
+        _lib.perc_lattice_destroy(h)
+        lat._h = None
+
+
+def perc_lattice_sites(lat: Lattice) -> int:
+    return int(_lib.perc_lattice_sites(lat.handle))
+
+
+def perc_lattice_words(lat: Lattice) -> int:
+    return int(_lib.perc_lattice_words(lat.handle))
+
+
+def perc_lattice_columns(lat: Lattice) -> int:
+    return int(_lib.perc_lattice_columns(lat.handle))
+
+
+def perc_lattice_state_bytes(lat: Lattice) -> int:
+    return int(_lib.perc_lattice_state_bytes(lat.handle))
+
+
+def perc_site_coord(lat: Lattice, s: int):
+    q, r, k = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.perc_site_coord(lat.handle, int(s), C.byref(q), C.byref(r), C.byref(k)))
+    return q.value, r.value, k.value
+
+
+def perc_site_neighbors(lat: Lattice, s: int):
+    buf = (C.c_int64 * 14)()
+    cnt = C.c_int32()
+    _check(_lib.perc_site_neighbors(lat.handle, int(s), buf, C.byref(cnt)))
+    return list(buf[: cnt.value])
+
+
+def perc_sample(lat: Lattice, p: float, seed: int, n_cfg: int, cfg0: int = 0, out: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """Occupancy words [n_cfg, words] (int32 bit patterns) of the Philox stream."""
+    if out is None:
+        out = torch.empty((n_cfg, lat.words), dtype=torch.int32, device="cuda")
+    _check(_lib.perc_sample(lat.handle, float(p), int(seed) & (2**64 - 1), int(cfg0), int(n_cfg),
+                            _dptr(out, torch.int32, n_cfg * lat.words), _stream(stream)))
+    return out
+
+
+def perc_inspect(lat: Lattice, occ: torch.Tensor, n_cfg: Optional[int] = None, perc=None, steps=None,
+                 stream=None):
+    """Decisions (uint8) and step counts (int32) of canonical occupancy words."""
+    return perc_inspect_ex(lat, occ, n_cfg, perc=perc, steps=steps, hit=False, stream=stream)[:2]
+
+
+def perc_inspect_ex(lat: Lattice, occ: torch.Tensor, n_cfg: Optional[int] = None, perc=None, steps=None,
+                    hit=False, form="auto", depth=0, block=0, grid=0, graph_steps=0, stream=None):
+    """As perc_inspect with an execution form and the first-hit probability (float32)."""
+    if n_cfg is None:
+        n_cfg = occ.numel() // lat.words
+    dev = occ.device
+    if perc is None:
+        perc = torch.empty(n_cfg, dtype=torch.uint8, device=dev)
+    if steps is None:
+        steps = torch.empty(n_cfg, dtype=torch.int32, device=dev)
+    hit_t = None
+    if hit is True:
+        hit_t = torch.empty(n_cfg, dtype=torch.float32, device=dev)
+    elif isinstance(hit, torch.Tensor):
+        hit_t = hit
+    opt = _options(form, depth, block, grid, graph_steps)
+    _check(_lib.perc_inspect_ex(lat.handle, _dptr(occ, torch.int32, n_cfg * lat.words), int(n_cfg),
+                                _dptr(perc, torch.uint8, n_cfg), _dptr(steps, torch.int32, n_cfg),
+                                _dptr(hit_t, torch.float32, n_cfg), C.byref(opt), _stream(stream)))
+    return perc, steps, hit_t
+
+
+def perc_pi(lat: Lattice, p: float, n_cfg: int, seed: int, bits=None, steps=None, hit=None, stream=None):
+    """Pi(p) over configurations 0..n_cfg-1 of the Philox stream ``seed`` (synchronous)."""
+    return perc_pi_ex(lat, p, n_cfg, seed, bits=bits, steps=steps, hit=hit, stream=stream)
+
+
+def perc_pi_ex(lat: Lattice, p: float, n_cfg: int, seed: int, bits=None, steps=None, hit=None, form="auto",
+               depth=0, block=0, grid=0, graph_steps=0, stream=None):
+    out = perc_pi_out(0, 0.0, _dptr(bits, torch.uint8, n_cfg), _dptr(steps, torch.int32, n_cfg),
+                      _dptr(hit, torch.float32, n_cfg))
+    opt = _options(form, depth, block, grid, graph_steps)
+    _check(_lib.perc_pi_ex(lat.handle, float(p), int(n_cfg), int(seed) & (2**64 - 1), C.byref(out), C.byref(opt),
+                           _stream(stream)))
+    return int(out.n_perc), float(out.pi)
+
+
+def perc_state_after(lat: Lattice, occ: torch.Tensor, K: int, x=None, reach=None, stream=None):
+    """Exactly K steps of one configuration: probabilities (N+1 float32) and reach (N+1 uint8)."""
+    dev = occ.device
+    if x is None:
+        x = torch.empty(lat.n + 1, dtype=torch.float32, device=dev)
+    if reach is None:
+        reach = torch.empty(lat.n + 1, dtype=torch.uint8, device=dev)
+    _check(_lib.perc_state_after(lat.handle, _dptr(occ, torch.int32, lat.words), int(K),
+                                 _dptr(x, torch.float32, lat.n + 1), _dptr(reach, torch.uint8, lat.n + 1),
+                                 _stream(stream)))
+    return x, reach

@@ -1,0 +1,277 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on the GPU.
+
+Bar: percolation bits, step counts and Pi counts bit-exact; the sampler bit-exact;
+FP32 probabilities within the tolerance derived from the arithmetic:
+  * state after K steps: relative 1e-5 (elementwise on entries >= 2^-100, and in L1)
+    for K <= 16, the rounding bound (6K + 8) 2^-24 being below it;
+  * first-hit probability after m* steps: relative (6 m* + 24) 2^-24.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1401_2130_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+U24 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def perc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1401_2130_amd as p
+    return p
+
+
+def dev(words: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(words).view(np.int32)).cuda()
+
+
+def host_words(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def check_hit(hit_gpu, hit_ref, perc_ref, steps_ref):
+    for i in np.nonzero(perc_ref)[0]:
+        ref = hit_ref[i]
+        if ref < 2.0 ** -100:
+            continue
+        tol = (6 * steps_ref[i] + 24) * U24
+        assert abs(hit_gpu[i] - ref) <= tol * ref, (i, hit_gpu[i], ref, steps_ref[i])
+    assert np.all(hit_gpu[perc_ref == 0] == 0.0)
+
+
+FORMS = [("plain", 1), ("span", 1), ("span", 3), ("span", 9), ("persist", 1), ("persist", 5), ("persist", 15)]
+
+
+# --------------------------------------------------------------------------------
+# sampler
+# --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,L,p,seed,cfg0,n", [(4, 16, 0.1533, 1, 0, 64), (3, 10, 0.5, 7, 1000, 16),
+                                               (16, 256, 0.17, 3, 4090, 6), (5, 11, 0.0, 2, 0, 3),
+                                               (5, 11, 1.0, 2, 0, 3), (2, 7, 0.125, 2 ** 40 + 5, 2 ** 33, 4)])
+def test_sampler_bit_exact(perc, W, L, p, seed, cfg0, n):
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L).sample(p, seed, n, cfg0=cfg0)
+    got = perc.perc_sample(lat, p, seed, n, cfg0=cfg0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host_words(got), ref)
+
+
+# --------------------------------------------------------------------------------
+# inspection: every form and depth against the oracle
+# --------------------------------------------------------------------------------
+
+SHAPES = [(0, 1), (0, 2), (0, 3), (0, 10), (1, 4), (1, 5), (2, 6), (2, 13), (3, 9), (4, 16), (4, 17), (5, 30),
+          (7, 44), (8, 61)]
+
+
+@pytest.mark.parametrize("W,L", SHAPES)
+@pytest.mark.parametrize("form,depth", FORMS)
+def test_inspect_matches_oracle(perc, W, L, form, depth):
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    rows = []
+    for p, seed in ((0.15, 1), (0.3, 2), (0.6, 3), (0.95, 4)):
+        rows.append(workloads.random_occupancy(ref.n, 24, p, seed + 100 * W + L, pad_garbage=(seed == 2)))
+    occ = np.concatenate(rows)
+    pm, sm, hm = ref.inspect_markov(occ)
+    pb, sb = ref.inspect_bfs(occ)
+    assert np.array_equal(pm, pb) and np.array_equal(sm, sb)
+    d_occ = dev(occ)
+    pg, sg, hg = perc.perc_inspect_ex(lat, d_occ, hit=True, form=form, depth=depth)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pg.cpu().numpy(), pm)
+    np.testing.assert_array_equal(sg.cpu().numpy(), sm)
+    check_hit(hg.cpu().numpy().astype(np.float64), hm, pm, sm)
+
+
+def test_forms_agree_bitwise(perc):
+    """Each configuration's bits, steps and FP32 first-hit probability are the same
+    alone (plain), spread (span) and one-per-workgroup (persist), at every depth."""
+    W, L = 6, 40
+    lat = perc.Lattice(W, L)
+    occ = workloads.random_occupancy(lat.n, 200, 0.32, 77)
+    d_occ = dev(occ)
+    results = []
+    for form, depth in FORMS:
+        p, s, h = perc.perc_inspect_ex(lat, d_occ, hit=True, form=form, depth=depth)
+        results.append((p.cpu().numpy(), s.cpu().numpy(), h.cpu().numpy().view(np.uint32)))
+    for r in results[1:]:
+        for a, b in zip(results[0], r):
+            np.testing.assert_array_equal(a, b)
+    # a configuration inspected alone equals the same one inside the batch
+    for i in (0, 57, 199):
+        p1, s1, h1 = perc.perc_inspect_ex(lat, d_occ[i:i + 1].contiguous(), hit=True, form="span")
+        assert p1.item() == results[0][0][i] and s1.item() == results[0][1][i]
+        assert h1.cpu().numpy().view(np.uint32)[0] == results[0][2][i]
+
+
+def test_graph_path_on_a_side_stream(perc):
+    """A non-default stream lets the span form capture and replay a HIP graph."""
+    W, L = 5, 60
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    occ = workloads.random_occupancy(ref.n, 300, 0.35, 5)
+    pm, sm, _ = ref.inspect_markov(occ)
+    d_occ = dev(occ)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for gs in (1, 3, 8, 32):
+            pg, sg, _ = perc.perc_inspect_ex(lat, d_occ, form="span", depth=3, graph_steps=gs, stream=s)
+            s.synchronize()
+            np.testing.assert_array_equal(pg.cpu().numpy(), pm)
+            np.testing.assert_array_equal(sg.cpu().numpy(), sm)
+
+
+def test_edge_cases(perc):
+    W, L = 3, 11
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    n, words = ref.n, ref.words
+    start, far = ref.surfaces()
+    q, r, k = ref.coords()
+    cases = []
+    cases.append(np.zeros(n, bool))                    # all insulating: no start tube
+    cases.append(np.ones(n, bool))                     # all metallic: percolates in one path
+    iso = np.zeros(n, bool); iso[np.nonzero(start)[0][5]] = True
+    cases.append(iso)                                  # one isolated start tube: degree 0 self-loop
+    col = np.zeros(n, bool); col[(q == 0) & (r == 0)] = True
+    cases.append(col)                                  # the central column only: end contacts
+    only_far = far.copy()
+    cases.append(only_far)                             # far surface only: never starts
+    occ = np.stack([np.packbits(np.pad(c, (0, words * 32 - n)).astype(np.uint8), bitorder="little").view(np.uint32)
+                    for c in cases])
+    pm, sm, hm = ref.inspect_markov(occ)
+    assert list(pm) == [0, 1, 0, 1, 0]
+    for form in ("plain", "span", "persist"):
+        pg, sg, hg = perc.perc_inspect_ex(lat, dev(occ), hit=True, form=form)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(pg.cpu().numpy(), pm)
+        np.testing.assert_array_equal(sg.cpu().numpy(), sm)
+        check_hit(hg.cpu().numpy().astype(np.float64), hm, pm, sm)
+    # empty batch
+    e = torch.empty((0, words), dtype=torch.int32, device="cuda")
+    pg, sg = perc.perc_inspect(lat, e, 0)
+    assert pg.numel() == 0
+
+
+# --------------------------------------------------------------------------------
+# state after K steps (the FP32 probabilities themselves)
+# --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,L,p,K", [(3, 13, 0.5, 0), (3, 13, 0.5, 1), (4, 16, 0.35, 16), (6, 31, 0.3, 16),
+                                     (2, 8, 0.9, 16), (8, 50, 0.25, 16)])
+def test_state_after_within_1e5(perc, W, L, p, K):
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    occ = workloads.random_occupancy(ref.n, 1, p, 1000 + K + W)
+    x64, r64 = ref.state_after(occ, K)
+    x32, r32 = perc.perc_state_after(lat, dev(occ[0]), K)
+    torch.cuda.synchronize()
+    x32 = x32.cpu().numpy().astype(np.float64)
+    r32 = r32.cpu().numpy().astype(bool)
+    np.testing.assert_array_equal(r32, r64)
+    big = x64 >= 2.0 ** -100
+    np.testing.assert_allclose(x32[big], x64[big], rtol=1e-5, atol=0)
+    if x64.sum() > 0:
+        assert np.abs(x32 - x64).sum() / np.abs(x64).sum() <= 1e-5
+    assert np.all(x32[~r64] == 0)
+
+
+@pytest.mark.parametrize("K", [64, 256])
+def test_state_after_long_runs_reported(perc, K):
+    """Past K = 16 the tolerance is the derived bound (6K + 8) 2^-24, not 1e-5."""
+    W, L = 5, 60
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    occ = workloads.random_occupancy(ref.n, 1, 0.4, 9)
+    x64, r64 = ref.state_after(occ, K)
+    x32, r32 = perc.perc_state_after(lat, dev(occ[0]), K)
+    torch.cuda.synchronize()
+    x32 = x32.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(r32.cpu().numpy().astype(bool), r64)
+    big = x64 >= 2.0 ** -100
+    rel = np.abs(x32[big] - x64[big]) / x64[big]
+    print(f"K={K}: max elementwise relative error {rel.max():.3e}, bound {(6 * K + 8) * U24:.3e}")
+    assert rel.max() <= (6 * K + 8) * U24
+
+
+# --------------------------------------------------------------------------------
+# Pi(p) through perc_pi (sampling on the device) at the workload sizes
+# --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("form", ["span", "persist", "plain"])
+def test_pi_small_workload_full(perc, form):
+    """W=4, L=16, p=0.1533, seed 1, 1000 configurations: every bit and the count."""
+    wl = workloads.SMALL
+    (W, L), p, seed, n = wl.shapes[0], wl.ps[0], wl.seed, wl.n_cfg
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    occ = ref.sample(p, seed, n)
+    pm, sm, hm = ref.inspect_markov(occ)
+    bits = torch.empty(n, dtype=torch.uint8, device="cuda")
+    steps = torch.empty(n, dtype=torch.int32, device="cuda")
+    hit = torch.empty(n, dtype=torch.float32, device="cuda")
+    n_perc, pi = perc.perc_pi_ex(lat, p, n, seed, bits=bits, steps=steps, hit=hit, form=form)
+    np.testing.assert_array_equal(bits.cpu().numpy(), pm)
+    np.testing.assert_array_equal(steps.cpu().numpy(), sm)
+    check_hit(hit.cpu().numpy().astype(np.float64), hm, pm, sm)
+    assert n_perc == int(pm.sum()) and pi == pm.sum() / n
+
+
+def test_pi_large_workload_sampled(perc):
+    """W=32, L=1024 at p in {0.14, 0.1533, 0.17}, 256 configurations each, in the span
+    launch configuration the benchmark times; every tenth configuration checked
+    against the oracle (BFS for bits and steps, the Markov iteration for two)."""
+    wl = workloads.LARGE
+    (W, L), seed, n = wl.shapes[0], wl.seed, wl.n_cfg
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    for p in wl.ps:
+        print(f"large workload p={p}", flush=True)
+        bits = torch.empty(n, dtype=torch.uint8, device="cuda")
+        steps = torch.empty(n, dtype=torch.int32, device="cuda")
+        n_perc, _ = perc.perc_pi_ex(lat, p, n, seed, bits=bits, steps=steps, form="span")
+        b = bits.cpu().numpy(); s = steps.cpu().numpy()
+        assert n_perc == int(b.sum())
+        idx = np.arange(0, n, 10)
+        for i in idx:
+            occ = ref.sample(p, seed, 1, cfg0=int(i))
+            pb, sb = ref.inspect_bfs(occ)
+            assert (b[i], s[i]) == (pb[0], sb[0]), (p, i)
+        for i in idx[:2]:
+            occ = ref.sample(p, seed, 1, cfg0=int(i))
+            pm, sm, _ = ref.inspect_markov(occ)
+            assert (b[i], s[i]) == (pm[0], sm[0]), (p, i)
+
+
+def test_pi_batched_workload_sampled(perc):
+    """W=16, L=256, 4096 configurations at three of the 21 p values, in the persistent
+    form (one launch); a sample checked against the oracle, and common random numbers
+    make the bits monotone in p."""
+    wl = workloads.BATCH
+    (W, L), seed, n = wl.shapes[0], wl.seed, wl.n_cfg
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    prev = None
+    for p in (wl.ps[0], wl.ps[10], wl.ps[20]):
+        print(f"batched workload p={p}", flush=True)
+        bits = torch.empty(n, dtype=torch.uint8, device="cuda")
+        steps = torch.empty(n, dtype=torch.int32, device="cuda")
+        n_perc, _ = perc.perc_pi_ex(lat, p, n, seed, bits=bits, steps=steps, form="persist")
+        b = bits.cpu().numpy(); s = steps.cpu().numpy()
+        idx = np.arange(0, n, 64)
+        occ = np.concatenate([ref.sample(p, seed, 1, cfg0=int(i)) for i in idx])
+        pb, sb = ref.inspect_bfs(occ)
+        np.testing.assert_array_equal(b[idx], pb)
+        np.testing.assert_array_equal(s[idx], sb)
+        if prev is not None:
+            assert np.all(prev <= b)
+        prev = b
