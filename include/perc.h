@@ -151,6 +151,20 @@ int perc_pi_ex(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, 
 int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t K, float* x_out,
                      uint8_t* reach_out, void* stream);
 
+/* ---- profiling of the step kernel (span and plain forms) ------------------------- */
+
+typedef struct perc_profile {
+    int64_t step_launches; /* step-kernel launches timed */
+    double step_ms;        /* sum of their durations (HIP events on the launching stream) */
+    int64_t tube_steps;    /* tube slots those launches advanced by one step */
+} perc_profile;
+
+/* Process-wide switch; resets the counters. While on, the span form launches its steps
+ * directly (HIP reports no elapsed time for events recorded as graph nodes) with an
+ * event pair around each step launch, on the caller's stream. */
+int perc_profile_enable(int32_t on);
+int perc_profile_read(perc_profile* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,10 @@ class perc_options(C.Structure):
                 ("graph_steps", C.c_int32)]
 
 
+class perc_profile(C.Structure):
+    _fields_ = [("step_launches", C.c_int64), ("step_ms", C.c_double), ("tube_steps", C.c_int64)]
+
+
 class perc_pi_out(C.Structure):
     _fields_ = [("n_perc", C.c_int64), ("pi", C.c_double), ("bits", C.c_void_p), ("steps", C.c_void_p),
                 ("hit", C.c_void_p)]
@@ -44,7 +48,7 @@ class perc_pi_out(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1401_2130_amd.build` "
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1401_2130_amd/build.py` "
                           "(or __graft_entry__.build()); there is no fallback path")
     lib = C.CDLL(LIB_PATH)
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
@@ -65,6 +69,8 @@ def _load():
     lib.perc_pi.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), vp]
     lib.perc_pi_ex.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), C.POINTER(perc_options), vp]
     lib.perc_state_after.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.perc_profile_enable.argtypes = [i32]
+    lib.perc_profile_read.argtypes = [C.POINTER(perc_profile)]
     return lib
 
 
@@ -73,7 +79,7 @@ _lib = _load()
 EXPORTED = ("perc_lattice_create", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
             "perc_last_error", "perc_sample", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
-            "perc_state_after")
+            "perc_state_after", "perc_profile_enable", "perc_profile_read")
 
 
 def perc_last_error() -> str:
@@ -229,6 +235,17 @@ def perc_pi_ex(lat: Lattice, p: float, n_cfg: int, seed: int, bits=None, steps=N
     _check(_lib.perc_pi_ex(lat.handle, float(p), int(n_cfg), int(seed) & (2**64 - 1), C.byref(out), C.byref(opt),
                            _stream(stream)))
     return int(out.n_perc), float(out.pi)
+
+
+def perc_profile_enable(on: bool) -> None:
+    _check(_lib.perc_profile_enable(1 if on else 0))
+
+
+def perc_profile_read() -> dict:
+    out = perc_profile()
+    _check(_lib.perc_profile_read(C.byref(out)))
+    return {"step_launches": int(out.step_launches), "step_ms": float(out.step_ms),
+            "tube_steps": int(out.tube_steps)}
 
 
 def perc_state_after(lat: Lattice, occ: torch.Tensor, K: int, x=None, reach=None, stream=None):

@@ -1,6 +1,7 @@
 """Build ``libperc.so`` (the C-ABI library of include/perc.h) for gfx950 with hipcc.
 
-Run ``python -m paper_1401_2130_amd.build`` (or ``__graft_entry__.build()``). The
+Run ``python paper_1401_2130_amd/build.py`` (or ``__graft_entry__.build()``); the
+script does not import the package, so it works while the library is missing. The
 library lands in ``paper_1401_2130_amd/_build/libperc.so``, in-tree, so that it ships
 with the source tree to the machine that runs it.
 """

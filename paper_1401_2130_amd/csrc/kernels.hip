@@ -19,9 +19,10 @@
 //
 // The state of one configuration is [U cells][CP] words, cell u holding layer 3u + sigma
 // of every column (see perc_internal.hpp). A chunk of D consecutive cells is staged in
-// LDS column-major with one halo cell on each side: word (column c, slot j) at
-// c*(D+2) + j, so the 14 contacts of tube (j, c) are reads at per-column offsets plus
-// the compile-time immediate j -- no address arithmetic per tube.
+// LDS column-major with one halo cell on each side: word (column c, slot j) at byte
+// (c*(D+2) + j)*4, so the 14 contacts of tube (j, c) are LDS reads at per-column byte
+// offsets plus the compile-time immediate -- no address arithmetic per tube. All LDS of
+// these kernels is dynamic (layout: lds_map), so the chunk sits at LDS address 0.
 #include <hip/hip_runtime.h>
 
 #include "perc_internal.hpp"
@@ -31,6 +32,14 @@ namespace perc {
 namespace {
 
 constexpr int kMaxBlock = 1024;
+constexpr int kXcds = 8;  // MI355X: workgroups are dealt round-robin over 8 XCDs
+
+extern __shared__ __align__(16) unsigned char lds[];
+
+__device__ __forceinline__ uint32_t lds_u32(uint32_t off) { return *reinterpret_cast<const uint32_t*>(lds + off); }
+__device__ __forceinline__ float lds_f32(uint32_t off) { return *reinterpret_cast<const float*>(lds + off); }
+__device__ __forceinline__ uint32_t lds_u8(uint32_t off) { return lds[off]; }
+__device__ __forceinline__ void lds_put_u32(uint32_t off, uint32_t v) { *reinterpret_cast<uint32_t*>(lds + off) = v; }
 
 // ------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds; each round takes
@@ -84,16 +93,12 @@ __device__ __forceinline__ void fill_rcp(float* rcp) {
 
 __device__ __forceinline__ float mag(uint32_t w) { return __uint_as_float(w & 0x7fffffffu); }
 
-// Decode the packed contact table entry for LDS layout with SJ slots per column.
-__device__ __forceinline__ int contact_offset(int32_t packed, int SJ) {
-    return (packed >> 2) * SJ + ((packed & 3) - 1);
-}
-
-// Stage cells u0-1 .. u0+D of a state buffer into LDS (column-major); cells beyond
-// the reached front, outside the fiber, and the pad column C read as zero.
+// Stage cells u0-1 .. u0+D of a state buffer (column-major) and the degree codes of
+// cells u0 .. u0+D-1 into LDS. Cells beyond the reached front or outside the fiber and
+// the pad column C read as zero; codes outside the fiber as 15.
 template <int D>
-__device__ __forceinline__ void stage_state(const DevTables& t, const float* __restrict__ y, int u0,
-                                            int front, float* lds) {
+__device__ __forceinline__ void stage_chunk(const DevTables& t, const LdsMap& m, const float* __restrict__ y,
+                                            const uint8_t* __restrict__ code, int u0, int front) {
     constexpr int SJ = D + 2;
     const int C = t.C;
     for (int c = threadIdx.x; c <= C; c += blockDim.x) {
@@ -101,10 +106,20 @@ __device__ __forceinline__ void stage_state(const DevTables& t, const float* __r
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
             const int u = u0 - 1 + j;
-            v[j] = (c < C && u >= 0 && u <= front && u < t.U) ? y[(int64_t)u * t.CP + c] : 0.0f;
+            v[j] = (c < C && u >= 0 && u <= front && u < t.U) ? y[(uint32_t)(u * t.CP + c)] : 0.0f;
+        }
+        uint32_t cd[D];
+#pragma unroll
+        for (int j = 1; j <= D; ++j) {
+            const int u = u0 - 1 + j;
+            cd[j - 1] = (c < C && u < t.U) ? code[(uint32_t)(u * t.CP + c)] : 15u;
         }
 #pragma unroll
-        for (int j = 0; j < SJ; ++j) lds[c * SJ + j] = v[j];
+        for (int j = 0; j < SJ; ++j) lds_put_u32((uint32_t)(c * SJ + j) * 4u, __float_as_uint(v[j]));
+        if (c < C) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) lds[m.code + (uint32_t)(c * D + j)] = (unsigned char)cd[j];
+        }
     }
 }
 
@@ -113,29 +128,44 @@ __device__ __forceinline__ void stage_state(const DevTables& t, const float* __r
 // this thread. The 14 contributions are summed in one fixed pairwise order, so a tube
 // gets the same FP32 result in every execution form and batch composition.
 template <int D>
-__device__ __forceinline__ uint32_t step_chunk(const DevTables& t, const float* lds, const float* rcp,
-                                               const uint8_t* __restrict__ code, float* __restrict__ yout,
+__device__ __forceinline__ uint32_t step_chunk(const DevTables& t, const LdsMap& m, float* __restrict__ yout,
                                                int u0, int front) {
     constexpr int SJ = D + 2;
     const int C = t.C;
     const int ulim = min(t.U, front + 2);
-    uint32_t fl = 0;
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        int o[kSide];
+    uint32_t grew = 0, far = 0, entered = 0;
+    // the contact table entries of the next column are loaded while this one computes
+    uint32_t o_next[kSide];
+    int top_next = -1;
+    if ((int)threadIdx.x < C) {
 #pragma unroll
-        for (int i = 0; i < kSide; ++i) o[i] = contact_offset(t.nb[i * C + c], SJ);
-        const int top = t.top[c];
-        const int oc = c * SJ;
+        for (int i = 0; i < kSide; ++i) o_next[i] = t.nboff[i * C + threadIdx.x];
+        top_next = t.top[threadIdx.x];
+    }
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        uint32_t o[kSide];
+#pragma unroll
+        for (int i = 0; i < kSide; ++i) o[i] = o_next[i];
+        const int top = top_next;
+        const int cn = c + (int)blockDim.x;
+        if (cn < C) {
+#pragma unroll
+            for (int i = 0; i < kSide; ++i) o_next[i] = t.nboff[i * C + cn];
+            top_next = t.top[cn];
+        }
+        const uint32_t oc = (uint32_t)(c * SJ) * 4u;
+        const uint32_t ocd = m.code + (uint32_t)(c * D);
 #pragma unroll
         for (int j = 1; j <= D; ++j) {
             const int u = u0 - 1 + j;
             if (u >= ulim) break;
-            const uint32_t own = __float_as_uint(lds[oc + j]);
-            const uint32_t dn = __float_as_uint(lds[oc + j - 1]);
-            const uint32_t up = __float_as_uint(lds[oc + j + 1]);
+            const uint32_t own = lds_u32(oc + j * 4);
+            const uint32_t dn = lds_u32(oc + (j - 1) * 4);
+            const uint32_t up = lds_u32(oc + (j + 1) * 4);
             uint32_t n[kSide];
 #pragma unroll
-            for (int i = 0; i < kSide; ++i) n[i] = __float_as_uint(lds[o[i] + j]);
+            for (int i = 0; i < kSide; ++i) n[i] = lds_u32(o[i] + (j - 1) * 4);
+            const uint32_t cd = lds_u8(ocd + (j - 1));
             uint32_t any = own | dn | up;
 #pragma unroll
             for (int i = 0; i < kSide; ++i) any |= n[i];
@@ -148,18 +178,18 @@ __device__ __forceinline__ uint32_t step_chunk(const DevTables& t, const float* 
             const float sab = mag(n[10]) + mag(n[11]);
             const float sud = mag(dn) + mag(up);
             const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
-            const int64_t g = (int64_t)u * t.CP + c;
-            const uint32_t cd = code[g];
+            // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps
+            // its own mass
+            const float x = sum + (cd == 0u ? mag(own) : 0.0f);
             const uint32_t newr = (any >> 31) & (cd < 15u ? 1u : 0u);
-            const float x = cd == 0u ? mag(own) : sum;
-            const float yn = x * rcp[cd];
-            yout[g] = __uint_as_float(__float_as_uint(yn) | (newr << 31));
-            fl |= (newr & ~(own >> 31)) ? F_GREW : 0u;
-            fl |= (newr && u == front + 1) ? F_FRONT : 0u;
-            fl |= (newr && u == top) ? F_FAR : 0u;
+            const float yn = x * lds_f32(m.rcp + cd * 4u);
+            yout[(uint32_t)(u * t.CP + c)] = __uint_as_float(__float_as_uint(yn) | (newr << 31));
+            grew |= newr & ~(own >> 31);
+            far |= newr & (u == top ? 1u : 0u);
+            if (u == front + 1) entered |= newr;
         }
     }
-    return fl;
+    return (grew ? F_GREW : 0u) | (far ? F_FAR : 0u) | (entered ? F_FRONT : 0u);
 }
 
 // Number of metallic start tubes (every tube of cell 0) of one configuration.
@@ -174,19 +204,19 @@ __device__ __forceinline__ int count_start(const DevTables& t, const uint32_t* _
     }
     if (threadIdx.x == 0) *red = 0;
     __syncthreads();
-    atomicAdd(red, cnt);
+    if (cnt) atomicAdd(red, cnt);
     __syncthreads();
     const int total = *red;
     __syncthreads();
     return total;
 }
 
-// Degree codes of cells u0 .. u0+D-1 from the occupancy, and the initial state of the
-// start tubes (cell 0): x0 = 1/|S0| on every metallic start tube, reached.
+// Degree codes of cells u0 .. u0+D-1 from the occupancy (staged as 0/1 words in the
+// state area of the LDS), and the initial state of the start tubes (cell 0):
+// x0 = 1/|S0| on every metallic start tube, reached.
 template <int D>
-__device__ __forceinline__ uint32_t init_chunk(const DevTables& t, const uint32_t* __restrict__ bits,
-                                               uint8_t* __restrict__ code, float* __restrict__ y0, int u0,
-                                               uint32_t* occ, const float* rcp, float x0) {
+__device__ __forceinline__ uint32_t init_chunk(const DevTables& t, const LdsMap& m, const uint32_t* __restrict__ bits,
+                                               uint8_t* __restrict__ code, float* __restrict__ y0, int u0, float x0) {
     constexpr int SJ = D + 2;
     const int C = t.C;
     for (int c = threadIdx.x; c <= C; c += blockDim.x) {
@@ -196,31 +226,31 @@ __device__ __forceinline__ uint32_t init_chunk(const DevTables& t, const uint32_
             const int64_t s = (int64_t)u * C + c;
             uint32_t o = 0;
             if (c < C && u >= 0 && u < t.U && s < t.N) o = (bits[s >> 5] >> (s & 31)) & 1u;
-            occ[c * SJ + j] = o;
+            lds_put_u32((uint32_t)(c * SJ + j) * 4u, o);
         }
     }
     __syncthreads();
     uint32_t fl = 0;
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        int o[kSide];
+        uint32_t o[kSide];
 #pragma unroll
-        for (int i = 0; i < kSide; ++i) o[i] = contact_offset(t.nb[i * C + c], SJ);
+        for (int i = 0; i < kSide; ++i) o[i] = t.nboff[i * C + c];
         const int top = t.top[c];
-        const int oc = c * SJ;
+        const uint32_t oc = (uint32_t)(c * SJ) * 4u;
 #pragma unroll
         for (int j = 1; j <= D; ++j) {
             const int u = u0 - 1 + j;
             if (u >= t.U) break;
-            const uint32_t me = occ[oc + j];
-            uint32_t deg = occ[oc + j - 1] + occ[oc + j + 1] + (u == top ? 1u : 0u);
+            const uint32_t me = lds_u32(oc + j * 4);
+            uint32_t deg = lds_u32(oc + (j - 1) * 4) + lds_u32(oc + (j + 1) * 4) + (u == top ? 1u : 0u);
 #pragma unroll
-            for (int i = 0; i < kSide; ++i) deg += occ[o[i] + j];
+            for (int i = 0; i < kSide; ++i) deg += lds_u32(o[i] + (j - 1) * 4);
             const uint32_t cd = me ? deg : 15u;
-            code[(int64_t)u * t.CP + c] = (uint8_t)cd;
+            code[(uint32_t)(u * t.CP + c)] = (uint8_t)cd;
             if (u == 0) {
                 float yv = 0.0f;
                 if (me) {
-                    yv = __uint_as_float(__float_as_uint(x0 * rcp[cd]) | 0x80000000u);
+                    yv = __uint_as_float(__float_as_uint(x0 * lds_f32(m.rcp + cd * 4u)) | 0x80000000u);
                     fl |= F_NONEMPTY;
                     if (u == top) fl |= F_FAR;
                 }
@@ -246,7 +276,7 @@ __device__ __forceinline__ void far_sum(const DevTables& t, const float* __restr
         for (int c = v; c < t.C; c += 256) {
             const int u = t.top[c];
             if (u < 0 || u > front) continue;
-            const uint32_t w = __float_as_uint(y[(int64_t)u * t.CP + c]);
+            const uint32_t w = __float_as_uint(y[(uint32_t)(u * t.CP + c)]);
             s += mag(w);
             r |= w >> 31;
         }
@@ -260,6 +290,19 @@ __device__ __forceinline__ void far_sum(const DevTables& t, const float* __restr
     }
     if (threadIdx.x == 0) *result = part[0];
     __syncthreads();
+}
+
+// Items [0, total) of a launch, dealt so that the workgroups of one XCD take one
+// contiguous range (neighbouring chunks of a configuration then share that XCD's L2).
+struct ItemRange {
+    int64_t begin, end, stride;
+};
+__device__ __forceinline__ ItemRange xcd_items(int64_t total) {
+    const int G = gridDim.x;
+    if (G % kXcds != 0 || total < G) return ItemRange{(int64_t)blockIdx.x, total, (int64_t)G};
+    const int x = blockIdx.x % kXcds, lb = blockIdx.x / kXcds, per = G / kXcds;
+    const int64_t b = total * x / kXcds, e = total * (x + 1) / kXcds;
+    return ItemRange{b + lb, e, (int64_t)per};
 }
 
 // ------------------------------------------------------------------------------
@@ -279,12 +322,11 @@ __global__ void __launch_bounds__(256) k_sample(uint32_t* __restrict__ bits, int
 
 template <int D>
 __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
-    extern __shared__ float lds[];
-    __shared__ float rcp[16];
-    __shared__ int red;
-    __shared__ uint32_t flag_s;
-    fill_rcp(rcp);
     const DevTables& t = a.t;
+    const LdsMap m = lds_map(t.C, D);
+    float* rcp = reinterpret_cast<float*>(lds + m.rcp);
+    uint32_t* misc = reinterpret_cast<uint32_t*>(lds + m.misc);
+    fill_rcp(rcp);
     const int64_t stride = (int64_t)t.U * t.CP;
     const int nchunk = (t.U + D - 1) / D;
     const int64_t total = (int64_t)a.n_slot * nchunk;
@@ -295,17 +337,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
         const uint32_t* bits = a.bits + (int64_t)b * t.words;
         float x0 = 0.0f;
         if (u0 == 0) {
-            const int n0 = count_start(t, bits, &red);
+            const int n0 = count_start(t, bits, reinterpret_cast<int*>(misc + 1));
             x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
         }
-        const uint32_t fl = init_chunk<D>(t, bits, a.code + b * stride, a.ya + b * stride, u0,
-                                          reinterpret_cast<uint32_t*>(lds), rcp, x0);
+        const uint32_t fl = init_chunk<D>(t, m, bits, a.code + b * stride, a.ya + b * stride, u0, x0);
         if (u0 == 0) {
-            if (threadIdx.x == 0) flag_s = 0;
+            if (threadIdx.x == 0) misc[0] = 0;
             __syncthreads();
-            if (fl) atomicOr(&flag_s, fl);
+            if (fl) atomicOr(&misc[0], fl);
             __syncthreads();
-            if (threadIdx.x == 0) a.st[b] = CfgState{0, 0, 0, flag_s};
+            if (threadIdx.x == 0) a.st[b] = CfgState{0, 0, 0, misc[0]};
             __syncthreads();
         }
     }
@@ -354,7 +395,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
     keep_s[tid] = keep;
     chunk_s[tid] = chunks;
     __syncthreads();
-    // exclusive scans over the threads (Hillis-Steele on a copy)
+    // inclusive scans over the threads (Hillis-Steele)
     for (int off = 1; off < nt; off <<= 1) {
         const int32_t kv = tid >= off ? keep_s[tid - off] : 0;
         const int64_t cv = tid >= off ? chunk_s[tid - off] : 0;
@@ -367,6 +408,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
     int64_t cpos = chunk_s[tid] - chunks;
     const int32_t n_keep = keep_s[nt - 1];
     const int64_t n_chunks = chunk_s[nt - 1];
+    unsigned long long cells = 0;
     for (int i = i0; i < i1; ++i) {
         const int b = first ? i : a.active[i];
         const CfgState s = a.st[b];
@@ -375,7 +417,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
         a.chunk_off[kpos] = cpos;
         kpos += 1;
         cpos += (min(U, s.front + 2) + D - 1) / D;
+        cells += (unsigned long long)min(U, s.front + 2);
     }
+    if (a.work && cells) atomicAdd(a.work, cells);
     __syncthreads();
     for (int i = tid; i < n_keep; i += nt) a.active[i] = a.active2[i];
     if (tid == 0) {
@@ -387,15 +431,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
 
 template <int D>
 __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
-    extern __shared__ float lds[];
-    __shared__ float rcp[16];
-    __shared__ uint32_t flag_s;
-    fill_rcp(rcp);
     const DevTables& t = a.t;
+    const LdsMap m = lds_map(t.C, D);
+    uint32_t* misc = reinterpret_cast<uint32_t*>(lds + m.misc);
+    fill_rcp(reinterpret_cast<float*>(lds + m.rcp));
     const int n_act = a.hdr[0];
     const int64_t total = a.hdr[1];
     const int64_t stride = (int64_t)t.U * t.CP;
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const ItemRange it = xcd_items(total);
+    for (int64_t g = it.begin; g < it.end; g += it.stride) {
         // active entry i with chunk_off[i] <= g < chunk_off[i+1]
         int lo = 0, hi = n_act - 1;
         while (lo < hi) {
@@ -407,14 +451,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
         const CfgState s = a.st[b];
         const float* yin = ((s.m & 1) ? a.yb : a.ya) + b * stride;
         float* yout = ((s.m & 1) ? a.ya : a.yb) + b * stride;
-        __syncthreads();  // previous item finished with lds / flag_s
-        if (threadIdx.x == 0) flag_s = 0;
-        stage_state<D>(t, yin, u0, s.front, lds);
+        __syncthreads();  // previous item finished with the LDS
+        if (threadIdx.x == 0) misc[0] = 0;
+        stage_chunk<D>(t, m, yin, a.code + b * stride, u0, s.front);
         __syncthreads();
-        const uint32_t fl = step_chunk<D>(t, lds, rcp, a.code + b * stride, yout, u0, s.front);
-        if (fl) atomicOr(&flag_s, fl);
+        const uint32_t fl = step_chunk<D>(t, m, yout, u0, s.front);
+        if (fl) atomicOr(&misc[0], fl);
         __syncthreads();
-        if (threadIdx.x == 0 && flag_s) atomicOr(&a.st[b].flags, flag_s);
+        if (threadIdx.x == 0 && misc[0]) atomicOr(&a.st[b].flags, misc[0]);
     }
 }
 
@@ -423,13 +467,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
 template <int D>
 __global__ void __launch_bounds__(kMaxBlock) k_chunk_step(DevTables t, const float* yin, float* yout,
                                                           const uint8_t* code, int front) {
-    extern __shared__ float lds[];
-    __shared__ float rcp[16];
-    fill_rcp(rcp);
+    const LdsMap m = lds_map(t.C, D);
+    fill_rcp(reinterpret_cast<float*>(lds + m.rcp));
     const int u0 = blockIdx.x * D;
-    stage_state<D>(t, yin, u0, front, lds);
+    stage_chunk<D>(t, m, yin, code, u0, front);
     __syncthreads();
-    (void)step_chunk<D>(t, lds, rcp, code, yout, u0, front);
+    (void)step_chunk<D>(t, m, yout, u0, front);
 }
 
 // First-hit probability of every configuration that percolated: the detector mass
@@ -455,16 +498,11 @@ __global__ void __launch_bounds__(256) k_span_finish(SpanArgs a) {
 
 template <int D>
 __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
-    extern __shared__ float lds[];
-    __shared__ float rcp[16];
-    __shared__ int red;
-    __shared__ uint32_t flag_s;
-    __shared__ int64_t cfg_s;
-    __shared__ float part[256];
-    __shared__ uint32_t reached;
-    __shared__ float result;
-    fill_rcp(rcp);
     const DevTables& t = a.t;
+    const LdsMap m = lds_map(t.C, D);
+    uint32_t* misc = reinterpret_cast<uint32_t*>(lds + m.misc);
+    float* part = reinterpret_cast<float*>(lds + m.part);
+    fill_rcp(reinterpret_cast<float*>(lds + m.rcp));
     const int64_t stride = (int64_t)t.U * t.CP;
     float* ya = a.ya + blockIdx.x * stride;
     float* yb = a.yb + blockIdx.x * stride;
@@ -472,9 +510,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) cfg_s = (int64_t)atomicAdd(a.queue, 1ull);
+        if (threadIdx.x == 0) {
+            const unsigned long long c = atomicAdd(a.queue, 1ull);
+            misc[2] = (uint32_t)c;
+            misc[3] = (uint32_t)(c >> 32);
+        }
         __syncthreads();
-        const int64_t cfg = cfg_s;
+        const int64_t cfg = (int64_t)(((uint64_t)misc[3] << 32) | misc[2]);
         if (cfg >= a.n_cfg) break;
         const uint32_t* bits;
         if (a.bits) {
@@ -487,39 +529,39 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
             bits = sb;
         }
         // initialisation: codes of every cell, start state in ya
-        const int n0 = count_start(t, bits, &red);
+        const int n0 = count_start(t, bits, reinterpret_cast<int*>(misc + 1));
         const float x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
-        if (threadIdx.x == 0) flag_s = 0;
+        if (threadIdx.x == 0) misc[0] = 0;
         __syncthreads();
         for (int u0 = 0; u0 < t.U; u0 += D) {
-            const uint32_t fl = init_chunk<D>(t, bits, code, ya, u0, reinterpret_cast<uint32_t*>(lds), rcp, x0);
-            if (fl) atomicOr(&flag_s, fl);
+            const uint32_t fl = init_chunk<D>(t, m, bits, code, ya, u0, x0);
+            if (fl) atomicOr(&misc[0], fl);
         }
         __syncthreads();
-        uint32_t f = flag_s;
-        int32_t perc = -1, steps = 0, m = 0, front = 0;
+        uint32_t f = misc[0];
+        int32_t perc = -1, steps = 0, mm = 0, front = 0;
         if (!(f & F_NONEMPTY)) { perc = 0; steps = 0; }
         else if (f & F_FAR) { perc = 1; steps = 1; }
         while (perc < 0) {
-            const float* yin = (m & 1) ? yb : ya;
-            float* yout = (m & 1) ? ya : yb;
+            const float* yin = (mm & 1) ? yb : ya;
+            float* yout = (mm & 1) ? ya : yb;
             __syncthreads();
-            if (threadIdx.x == 0) flag_s = 0;
+            if (threadIdx.x == 0) misc[0] = 0;
             const int ulim = min(t.U, front + 2);
             for (int u0 = 0; u0 < ulim; u0 += D) {
                 __syncthreads();
-                stage_state<D>(t, yin, u0, front, lds);
+                stage_chunk<D>(t, m, yin, code, u0, front);
                 __syncthreads();
-                const uint32_t fl = step_chunk<D>(t, lds, rcp, code, yout, u0, front);
-                if (fl) atomicOr(&flag_s, fl);
+                const uint32_t fl = step_chunk<D>(t, m, yout, u0, front);
+                if (fl) atomicOr(&misc[0], fl);
             }
             __syncthreads();
-            f = flag_s;
-            m += 1;
+            f = misc[0];
+            mm += 1;
             if (f & F_FRONT) front += 1;
-            if (f & F_FAR) { perc = 1; steps = m + 1; }
-            else if (!(f & F_GREW)) { perc = 0; steps = m; }
-            else if (m >= a.cap) { perc = 0; steps = m; if (threadIdx.x == 0) atomicOr(a.err, 1u); }
+            if (f & F_FAR) { perc = 1; steps = mm + 1; }
+            else if (!(f & F_GREW)) { perc = 0; steps = mm; }
+            else if (mm >= a.cap) { perc = 0; steps = mm; if (threadIdx.x == 0) atomicOr(a.err, 1u); }
         }
         if (threadIdx.x == 0) {
             a.out.perc[cfg] = (uint8_t)perc;
@@ -529,8 +571,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
             float h = 0.0f;
             if (perc == 1) {
                 __syncthreads();
-                far_sum(t, ((steps - 1) & 1) ? yb : ya, front, part, &reached, &result);
-                h = result;
+                far_sum(t, ((steps - 1) & 1) ? yb : ya, front, part, misc + 4, reinterpret_cast<float*>(misc + 5));
+                h = __uint_as_float(misc[5]);
             }
             if (threadIdx.x == 0) a.out.hit[cfg] = h;
         }
@@ -606,7 +648,7 @@ hipError_t dispatch_depth(int depth, Args&&... args) {
     }
 }
 
-constexpr size_t kDynLds = 160 * 1024 - 4096;  // dynamic LDS limit set once per device
+constexpr size_t kDynLds = 160 * 1024;  // dynamic LDS limit set once per device
 
 template <typename K>
 hipError_t allow_lds(K kernel) {
@@ -628,14 +670,14 @@ struct PrepDepth {
 template <int D>
 struct ResidentPersist {
     static hipError_t run(int block, int C, int* out) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_persist<D>, block, lds_bytes_for(C, D));
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_persist<D>, block, lds_map(C, D).total);
     }
 };
 
 template <int D>
 struct RunSpanInit {
     static hipError_t run(const SpanArgs& a, hipStream_t s) {
-        const size_t lds = lds_bytes_for(a.t.C, D);
+        const size_t lds = lds_map(a.t.C, D).total;
         const int64_t nchunk = (a.t.U + D - 1) / D;
         const int64_t items = (int64_t)a.n_slot * nchunk;
         const int grid = (int)std::min<int64_t>(items, 65536);
@@ -648,7 +690,7 @@ struct RunSpanInit {
 template <int D>
 struct RunSpanStep {
     static hipError_t run(const SpanArgs& a, hipStream_t s) {
-        const size_t lds = lds_bytes_for(a.t.C, D);
+        const size_t lds = lds_map(a.t.C, D).total;
         hipLaunchKernelGGL(k_span_step<D>, dim3(a.grid), dim3(a.block), lds, s, a);
         return hipGetLastError();
     }
@@ -658,7 +700,7 @@ template <int D>
 struct RunChunkStep {
     static hipError_t run(const DevTables& t, const float* yin, float* yout, const uint8_t* code, int front,
                           int block, hipStream_t s) {
-        const size_t lds = lds_bytes_for(t.C, D);
+        const size_t lds = lds_map(t.C, D).total;
         const int grid = (t.U + D - 1) / D;
         hipLaunchKernelGGL(k_chunk_step<D>, dim3(grid), dim3(block), lds, s, t, yin, yout, code, front);
         return hipGetLastError();
@@ -668,7 +710,7 @@ struct RunChunkStep {
 template <int D>
 struct RunPersist {
     static hipError_t run(const PersistArgs& a, hipStream_t s) {
-        const size_t lds = lds_bytes_for(a.t.C, D);
+        const size_t lds = lds_map(a.t.C, D).total;
         hipLaunchKernelGGL(k_persist<D>, dim3(a.grid), dim3(a.block), lds, s, a);
         return hipGetLastError();
     }
@@ -676,16 +718,13 @@ struct RunPersist {
 
 }  // namespace
 
-size_t lds_bytes_for(int32_t C, int32_t depth) {
-    return (size_t)(C + 1) * (size_t)(depth + 2) * sizeof(float);
-}
+size_t lds_bytes_for(int32_t C, int32_t depth) { return lds_map(C, depth).total; }
 
 int32_t max_depth_for(int32_t C) {
-    const int32_t cand[] = {15, 9, 7, 5, 3, 1};
-    const size_t budget = 160 * 1024 - 4096;  // leave room for the static LDS
-    for (int32_t d : cand)
-        if (lds_bytes_for(C, d) <= budget) return d;
-    return 0;
+    int32_t best = 0;
+    for (int32_t d : kDepthList)
+        if (lds_bytes_for(C, d) <= kDynLds) best = d;
+    return best;
 }
 
 hipError_t prepare_kernels(int device) {
@@ -693,8 +732,7 @@ hipError_t prepare_kernels(int device) {
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return e;
     if (cur != device) return hipErrorInvalidDevice;
-    const int depths[] = {1, 3, 5, 7, 9, 15};
-    for (int d : depths) {
+    for (int d : kDepthList) {
         e = dispatch_depth<PrepDepth>(d);
         if (e != hipSuccess) return e;
     }

@@ -79,4 +79,15 @@ bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
     return true;
 }
 
+std::vector<uint32_t> contact_table(const LatticeDesc& d, int32_t depth) {
+    const uint32_t SJ = (uint32_t)depth + 2u;
+    std::vector<uint32_t> t((size_t)kSide * d.C);
+    for (size_t e = 0; e < t.size(); ++e) {
+        const int32_t v = d.nb[e];
+        const uint32_t col = (uint32_t)(v >> 2), dcp1 = (uint32_t)(v & 3);  // dcell + 1
+        t[e] = (col * SJ + dcp1) * 4u;
+    }
+    return t;
+}
+
 }  // namespace perc

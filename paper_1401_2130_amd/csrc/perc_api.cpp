@@ -62,8 +62,10 @@ int prepare(int dev) {
     return PERC_OK;
 }
 
-int tables_for(const perc_lattice* lat_c, DevTables& t) {
+int tables_for(const perc_lattice* lat_c, int32_t depth, DevTables& t) {
     perc_lattice* lat = const_cast<perc_lattice*>(lat_c);
+    const int di = depth_index(depth);
+    if (di < 0) return fail(PERC_EINVAL, "unsupported chunk depth");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     PERC_TRY(prepare(dev));
@@ -75,16 +77,18 @@ int tables_for(const perc_lattice* lat_c, DevTables& t) {
     if (!ld) {
         LatticeDevice n;
         n.device = dev;
-        const size_t nb_bytes = sizeof(int32_t) * (size_t)kSide * std::max(d.C, 1);
-        const size_t top_bytes = sizeof(int32_t) * (size_t)std::max(d.C, 1);
-        HIP_TRY(hipMalloc(&n.nb, nb_bytes));
-        HIP_TRY(hipMalloc(&n.top, top_bytes));
-        HIP_TRY(hipMemcpy(n.nb, d.nb.data(), sizeof(int32_t) * d.nb.size(), hipMemcpyHostToDevice));
+        const size_t tb = sizeof(uint32_t) * (size_t)kSide * std::max(d.C, 1);
+        for (int i = 0; i < kNumDepths; ++i) {
+            const std::vector<uint32_t> tab = contact_table(d, kDepthList[i]);
+            HIP_TRY(hipMalloc(&n.nboff[i], tb));
+            HIP_TRY(hipMemcpy(n.nboff[i], tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice));
+        }
+        HIP_TRY(hipMalloc(&n.top, sizeof(int32_t) * (size_t)std::max(d.C, 1)));
         HIP_TRY(hipMemcpy(n.top, d.top.data(), sizeof(int32_t) * d.top.size(), hipMemcpyHostToDevice));
         lat->dev.push_back(n);
         ld = &lat->dev.back();
     }
-    t.nb = ld->nb;
+    t.nboff = ld->nboff[di];
     t.top = ld->top;
     t.C = d.C; t.CP = d.CP; t.U = d.U; t.L = d.L;
     t.N = d.N; t.words = d.words;
@@ -132,19 +136,82 @@ struct PinnedHdr {
 thread_local PinnedHdr g_pinned;
 
 // ---------------------------------------------------------------------------------
+// Optional profiling of the span/plain step kernel: HIP events on the launching
+// stream around every step launch (graphs are not used while it is on) and the tube
+// slots the steps processed (cells scheduled by the planner times the columns).
+// ---------------------------------------------------------------------------------
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    int64_t launches = 0;
+    double ms = 0.0;
+    int64_t tube_steps = 0;
+};
+Profiler g_prof;
+
+bool profiling() {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    return g_prof.on;
+}
+
+class StepTimer {
+  public:
+    explicit StepTimer(bool on) : on_(on) {}
+    ~StepTimer() {
+        for (auto& p : pending_) { free_.push_back(p.first); free_.push_back(p.second); }
+        for (hipEvent_t e : free_) (void)hipEventDestroy(e);
+    }
+    hipError_t step(const SpanArgs& a, hipStream_t s) {
+        if (!on_) return launch_span_step(a, s);
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        hipError_t e = take(&ev.first);
+        if (e == hipSuccess) e = take(&ev.second);
+        if (e != hipSuccess) return e;
+        pending_.push_back(ev);
+        e = hipEventRecord(ev.first, s);
+        if (e == hipSuccess) e = launch_span_step(a, s);
+        if (e == hipSuccess) e = hipEventRecord(ev.second, s);
+        return e;
+    }
+    // After the stream has been synchronised: add the durations of the launches since
+    // the last call.
+    hipError_t collect() {
+        if (!on_) return hipSuccess;
+        double ms = 0.0;
+        for (auto& p : pending_) {
+            float t = 0.0f;
+            hipError_t e = hipEventElapsedTime(&t, p.first, p.second);
+            if (e != hipSuccess) return e;
+            ms += t;
+            free_.push_back(p.first);
+            free_.push_back(p.second);
+        }
+        std::lock_guard<std::mutex> g(g_prof.mu);
+        g_prof.launches += (int64_t)pending_.size();
+        g_prof.ms += ms;
+        pending_.clear();
+        return hipSuccess;
+    }
+    bool on() const { return on_; }
+
+  private:
+    hipError_t take(hipEvent_t* e) {
+        if (!free_.empty()) { *e = free_.back(); free_.pop_back(); return hipSuccess; }
+        return hipEventCreate(e);
+    }
+    bool on_;
+    std::vector<hipEvent_t> free_;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_;
+};
+
+// ---------------------------------------------------------------------------------
 // Tuning: explicit options, else cached autotune results, else shape rules.
 // ---------------------------------------------------------------------------------
-const int32_t kDepths[] = {1, 3, 5, 7, 9, 15};
-
-bool valid_depth(int32_t d) {
-    for (int32_t x : kDepths)
-        if (x == d) return true;
-    return false;
-}
+bool valid_depth(int32_t d) { return depth_index(d) >= 0; }
 
 int32_t depth_within(int32_t C, size_t lds_budget, int32_t cap) {
     int32_t best = 0;
-    for (int32_t d : kDepths)
+    for (int32_t d : kDepthList)
         if (d <= cap && lds_bytes_for(C, d) <= lds_budget) best = d;
     return best;
 }
@@ -165,10 +232,12 @@ int resolve(const LatticeDesc& d, int64_t n_cfg, const perc_options* opt, Tuning
         // many configurations of modest size: one workgroup each; otherwise spread
         tu.form = (n_cfg >= 1024 && state_bytes(d) <= (64ll << 20)) ? FORM_PERSIST : FORM_SPAN;
     }
-    const size_t kMaxLds = 160 * 1024 - 4096;
+    const size_t kMaxLds = 160 * 1024;
     if (tu.depth == 0) {
+        // plain: one configuration, as many workgroups per step as possible; span: the
+        // deepest chunk that fits (measured best on W=32); persistent: two per CU
         if (tu.form == FORM_PLAIN) tu.depth = depth_within(d.C, kMaxLds, 1);
-        else if (tu.form == FORM_SPAN) tu.depth = depth_within(d.C, 80 * 1024, 9);
+        else if (tu.form == FORM_SPAN) tu.depth = depth_within(d.C, kMaxLds, 15);
         else tu.depth = depth_within(d.C, 80 * 1024, 15);
         if (tu.depth == 0) tu.depth = depth_within(d.C, kMaxLds, 15);
     }
@@ -176,7 +245,10 @@ int resolve(const LatticeDesc& d, int64_t n_cfg, const perc_options* opt, Tuning
     if (lds_bytes_for(d.C, tu.depth) > kMaxLds)
         return fail(PERC_EINVAL, "chunk of " + std::to_string(tu.depth) + " cells of " + std::to_string(d.C) +
                                      " columns exceeds the LDS of one workgroup");
-    if (tu.block == 0) tu.block = tu.form == FORM_PERSIST ? 512 : 256;
+    if (tu.block == 0) {
+        const int32_t want = tu.form == FORM_PLAIN ? 512 : 1024;
+        tu.block = std::max<int32_t>(64, std::min<int32_t>(want, ((d.C + 63) / 64) * 64));
+    }
     if (tu.block < 64 || tu.block > 1024 || tu.block % 64) return fail(PERC_EINVAL, "block must be 64..1024, multiple of 64");
     if (tu.graph_steps == 0) tu.graph_steps = 8;
     if (tu.graph_steps < 1 || tu.graph_steps > 256) return fail(PERC_EINVAL, "graph_steps must be 1..256");
@@ -228,7 +300,11 @@ int run_span(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int
     a.cap = d.N + 1;
     if (!g_pinned.h) return fail(PERC_ENOMEM, "pinned host buffer");
     int32_t* h = g_pinned.h;
-    const bool use_graph = !plain && s != nullptr;
+    a.work = reinterpret_cast<unsigned long long*>(a.hdr + 8);
+    StepTimer timer(profiling());
+    // HIP gives no elapsed time for events recorded as graph nodes: while profiling,
+    // steps are launched directly with an event pair around each
+    const bool use_graph = !plain && s != nullptr && !timer.on();
     for (int64_t w = 0; w < n_cfg; w += n_slot) {
         const int64_t nb = std::min<int64_t>(n_slot, n_cfg - w);
         a.n_slot = (int32_t)nb;
@@ -240,10 +316,11 @@ int run_span(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int
         HIP_TRY(launch_span_init(a, s));
         if (plain) {
             for (;;) {
-                HIP_TRY(hipMemcpyAsync(h, a.hdr, 16, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(h, a.hdr, 64, hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipStreamSynchronize(s));
+                HIP_TRY(timer.collect());
                 if (h[0] == 0) break;
-                HIP_TRY(launch_span_step(a, s));
+                HIP_TRY(timer.step(a, s));
                 HIP_TRY(launch_span_plan(a, s));
             }
         } else {
@@ -272,15 +349,16 @@ int run_span(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int
                         if (e != hipSuccess) rc = hip_fail(e, "hipGraphLaunch");
                     } else {
                         for (int i = 0; i < tu.graph_steps && rc == PERC_OK; ++i) {
-                            hipError_t e = launch_span_step(a, s);
+                            hipError_t e = timer.step(a, s);
                             if (e == hipSuccess) e = launch_span_plan(a, s);
                             if (e != hipSuccess) rc = hip_fail(e, "span step");
                         }
                     }
                 }
                 if (rc != PERC_OK) break;
-                hipError_t e = hipMemcpyAsync(h, a.hdr, 16, hipMemcpyDeviceToHost, s);
+                hipError_t e = hipMemcpyAsync(h, a.hdr, 64, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e == hipSuccess) e = timer.collect();
                 if (e != hipSuccess) { rc = hip_fail(e, "span poll"); break; }
                 if (h[0] == 0) break;
                 reps = std::min(reps * 2, 8);
@@ -289,6 +367,12 @@ int run_span(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int
             if (rc != PERC_OK) return rc;
         }
         if (h[2]) return fail(PERC_ECAP, "a configuration reached the step cap");
+        if (timer.on()) {
+            unsigned long long cells = 0;
+            std::memcpy(&cells, h + 8, sizeof(cells));
+            std::lock_guard<std::mutex> g(g_prof.mu);
+            g_prof.tube_steps += (int64_t)cells * t.C;
+        }
         HIP_TRY(launch_span_finish(a, s));
     }
     return PERC_OK;
@@ -356,10 +440,10 @@ int inspect_impl(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cf
     if (n_cfg == 0) return PERC_OK;
     if (!occ_bits || !perc) return fail(PERC_EINVAL, "occ_bits and perc must be device pointers");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    DevTables t;
-    PERC_TRY(tables_for(lat, t));
     Tuning tu;
     PERC_TRY(resolve(lat->d, n_cfg, opt, tu));
+    DevTables t;
+    PERC_TRY(tables_for(lat, tu.depth, t));
     Arena ar;
     if (!steps) {
         PERC_TRY(ar.reserve(sizeof(int32_t) * n_cfg, s));
@@ -380,10 +464,10 @@ int pi_impl(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, per
     out->pi = 0.0;
     if (n_cfg == 0) return PERC_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    DevTables t;
-    PERC_TRY(tables_for(lat, t));
     Tuning tu;
     PERC_TRY(resolve(lat->d, n_cfg, opt, tu));
+    DevTables t;
+    PERC_TRY(tables_for(lat, tu.depth, t));
     const uint64_t thr = threshold_of(p);
     Arena ar;
     const size_t bytes = (out->bits ? 0 : Arena::align((size_t)n_cfg)) +
@@ -439,7 +523,7 @@ void perc_lattice_destroy(perc_lattice* lat) {
     const bool have = hipGetDevice(&cur) == hipSuccess;
     for (auto& x : lat->dev) {
         if (hipSetDevice(x.device) == hipSuccess) {
-            (void)hipFree(x.nb);
+            for (uint32_t* p : x.nboff) (void)hipFree(p);
             (void)hipFree(x.top);
         }
     }
@@ -488,6 +572,24 @@ int perc_site_neighbors(const perc_lattice* lat, int64_t s, int64_t* nbr, int32_
 
 const char* perc_last_error(void) { return g_err.c_str(); }
 
+int perc_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    g_prof.on = on != 0;
+    g_prof.launches = 0;
+    g_prof.ms = 0.0;
+    g_prof.tube_steps = 0;
+    return PERC_OK;
+}
+
+int perc_profile_read(perc_profile* out) {
+    if (!out) return fail(PERC_EINVAL, "out is NULL");
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    out->step_launches = g_prof.launches;
+    out->step_ms = g_prof.ms;
+    out->tube_steps = g_prof.tube_steps;
+    return PERC_OK;
+}
+
 int perc_sample(const perc_lattice* lat, double p, uint64_t seed, int64_t cfg0, int64_t n_cfg, uint32_t* occ_bits,
                 void* stream) {
     PERC_TRY(validate_lat(lat));
@@ -496,7 +598,7 @@ int perc_sample(const perc_lattice* lat, double p, uint64_t seed, int64_t cfg0, 
     if (n_cfg == 0) return PERC_OK;
     if (!occ_bits) return fail(PERC_EINVAL, "occ_bits is NULL");
     DevTables t;
-    PERC_TRY(tables_for(lat, t));
+    PERC_TRY(tables_for(lat, 1, t));
     const uint32_t tag = ((uint32_t)lat->d.W << 16) | (uint32_t)lat->d.L;
     HIP_TRY(launch_sample(t, occ_bits, n_cfg, (uint64_t)cfg0, threshold_of(p), seed, tag,
                           reinterpret_cast<hipStream_t>(stream)));
@@ -528,10 +630,10 @@ int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t 
     if (K < 0) return fail(PERC_EINVAL, "K < 0");
     if (!occ_bits || !x_out || !reach_out) return fail(PERC_EINVAL, "NULL device pointer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    DevTables t;
-    PERC_TRY(tables_for(lat, t));
     const LatticeDesc& d = lat->d;
     const int32_t depth = depth_within(d.C, 80 * 1024, 3) ? depth_within(d.C, 80 * 1024, 3) : 1;
+    DevTables t;
+    PERC_TRY(tables_for(lat, depth, t));
     const int64_t cell_words = (int64_t)t.U * t.CP;
     Arena ar;
     PERC_TRY(ar.reserve(Arena::align(sizeof(float) * cell_words) * 2 + Arena::align((size_t)cell_words) +

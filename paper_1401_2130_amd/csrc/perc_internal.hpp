@@ -47,12 +47,54 @@ struct LatticeDesc {
 
 bool build_lattice(int32_t W, int32_t L, LatticeDesc& out, std::string& err);
 
+// Chunk depths (unit cells per workgroup chunk) the kernels are built for.
+constexpr int kNumDepths = 6;
+constexpr int32_t kDepthList[kNumDepths] = {1, 3, 5, 7, 9, 15};
+inline int depth_index(int32_t d) {
+    for (int i = 0; i < kNumDepths; ++i)
+        if (kDepthList[i] == d) return i;
+    return -1;
+}
+
+// Contact table of one chunk depth D: for side contact i of column c, the LDS byte
+// offset ((nb_col * (D + 2) + dcell + 1) * 4) of that contact in a chunk staged
+// column-major with D + 2 slots per column; the tube in slot j reads it at that offset
+// plus (j - 1) * 4.
+std::vector<uint32_t> contact_table(const LatticeDesc& d, int32_t depth);
+
 // Device copies of the per-column tables, one per HIP device that used the lattice.
 struct LatticeDevice {
     int device = -1;
-    int32_t* nb = nullptr;   // [kSide][C]
-    int32_t* top = nullptr;  // [C]
+    uint32_t* nboff[kNumDepths] = {};  // [kSide][C] per depth
+    int32_t* top = nullptr;             // [C]
 };
+
+#if defined(__HIPCC__)
+#define PERC_HD __host__ __device__
+#else
+#define PERC_HD
+#endif
+
+// Dynamic LDS of a chunk kernel (byte offsets; every kernel of the inspection keeps
+// all its LDS here, so the state chunk starts at address 0):
+//   [0, state)   state words, column-major, (C + 1) columns x (D + 2) slots
+//   code         degree codes of the D computed cells, [c][D] bytes
+//   rcp          16 floats, 1/deg per code
+//   misc         16 words of flags and counters
+//   part         256 floats of partial sums
+struct LdsMap {
+    uint32_t code, rcp, misc, part, total;
+};
+PERC_HD inline LdsMap lds_map(int32_t C, int32_t D) {
+    LdsMap m;
+    const uint32_t state = (uint32_t)(C + 1) * (uint32_t)(D + 2) * 4u;
+    m.code = (state + 15u) & ~15u;
+    m.rcp = (m.code + (uint32_t)C * (uint32_t)D + 15u) & ~15u;
+    m.misc = m.rcp + 64u;
+    m.part = m.misc + 64u;
+    m.total = m.part + 1024u;
+    return m;
+}
 
 // ---------------------------------------------------------------------------------
 // Execution forms and tuning knobs.
@@ -97,7 +139,7 @@ struct BatchOut {
 // Kernel launchers (kernels.hip).
 // ---------------------------------------------------------------------------------
 struct DevTables {
-    const int32_t* nb;
+    const uint32_t* nboff;  // contact table of the chunk depth in use
     const int32_t* top;
     int32_t C, CP, U, L;
     int64_t N, words;
@@ -119,6 +161,7 @@ struct SpanArgs {
     int32_t* active2;          // scratch for compaction
     int64_t* chunk_off;        // [n_slot + 1] prefix sums of chunks per active slot
     int32_t* hdr;              // [4]: n_active, total chunks, error flag, spare
+    unsigned long long* work;  // cells scheduled over all steps (planner adds), or null
     BatchOut out;
     int32_t n_slot;
     int32_t depth;             // cells per chunk
