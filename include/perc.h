@@ -66,8 +66,10 @@ enum {
 
 typedef struct perc_options {
     int32_t form;        /* PERC_FORM_* */
-    int32_t depth;       /* unit cells per chunk: 1, 3, 5, 7, 9 or 15; 0 = choose */
-    int32_t block;       /* threads per workgroup, multiple of 64, <= 1024; 0 = choose */
+    int32_t depth;       /* unit cells one workgroup walks per work item, rounded up to a
+                            multiple of 8; 0 = choose */
+    int32_t block;       /* threads per workgroup, multiple of 64, <= 1024, at least the
+                            widest column tile and half its halo range; 0 = choose */
     int32_t grid;        /* workgroups per launch; 0 = choose */
     int32_t graph_steps; /* span form: steps per graph replay; 0 = choose */
 } perc_options;
@@ -140,6 +142,29 @@ typedef struct perc_pi_out {
 int perc_pi(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, perc_pi_out* out, void* stream);
 int perc_pi_ex(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, perc_pi_out* out,
                const perc_options* opt, void* stream);
+
+/* ---- batches of uneven shapes ------------------------------------------------------- */
+
+/* One configuration of a batch. Either occ_bits (device, canonical words of `lat`) or,
+ * when occ_bits is NULL, the Philox draw (p, seed, cfg) as in perc_sample. `group`
+ * selects the Pi count it adds to (0 .. n_groups-1), or -1 for none. */
+typedef struct perc_job {
+    const perc_lattice* lat;
+    const uint32_t* occ_bits;
+    double p;
+    uint64_t seed;
+    int64_t cfg;
+    int32_t group;
+} perc_job;
+
+/* Inspect n_jobs configurations of possibly different lattices in one batch (one
+ * persistent launch, or one span launch per step over every job). perc (device,
+ * n_jobs bytes), steps and hit (device, n_jobs entries, may be NULL) are indexed by job.
+ * group_count (host, n_groups int64) receives the number of percolating jobs of each
+ * group; the call is synchronous when n_groups > 0, else async. The batch is packed
+ * largest-first and run in the form `opt` names (NULL = automatic). */
+int perc_batch(const perc_job* jobs, int64_t n_jobs, uint8_t* perc, int32_t* steps, float* hit,
+               int64_t* group_count, int32_t n_groups, const perc_options* opt, void* stream);
 
 /* ---- test hook ------------------------------------------------------------------ */
 

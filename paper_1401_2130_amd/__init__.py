@@ -41,6 +41,11 @@ class perc_profile(C.Structure):
     _fields_ = [("step_launches", C.c_int64), ("step_ms", C.c_double), ("tube_steps", C.c_int64)]
 
 
+class perc_job(C.Structure):
+    _fields_ = [("lat", C.c_void_p), ("occ_bits", C.c_void_p), ("p", C.c_double), ("seed", C.c_uint64),
+                ("cfg", C.c_int64), ("group", C.c_int32)]
+
+
 class perc_pi_out(C.Structure):
     _fields_ = [("n_perc", C.c_int64), ("pi", C.c_double), ("bits", C.c_void_p), ("steps", C.c_void_p),
                 ("hit", C.c_void_p)]
@@ -69,6 +74,7 @@ def _load():
     lib.perc_pi.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), vp]
     lib.perc_pi_ex.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), C.POINTER(perc_options), vp]
     lib.perc_state_after.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.perc_batch.argtypes = [C.POINTER(perc_job), i64, vp, vp, vp, vp, i32, C.POINTER(perc_options), vp]
     lib.perc_profile_enable.argtypes = [i32]
     lib.perc_profile_read.argtypes = [C.POINTER(perc_profile)]
     return lib
@@ -79,7 +85,7 @@ _lib = _load()
 EXPORTED = ("perc_lattice_create", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
             "perc_last_error", "perc_sample", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
-            "perc_state_after", "perc_profile_enable", "perc_profile_read")
+            "perc_batch", "perc_state_after", "perc_profile_enable", "perc_profile_read")
 
 
 def perc_last_error() -> str:
@@ -124,6 +130,7 @@ class Lattice:
         if not h:
             raise PercError(PERC_EINVAL, perc_last_error())
         self._h = h
+        self._lib = _lib  # kept for the destructor at interpreter shutdown
         self.W, self.L = int(W), int(L)
         self.n = int(_lib.perc_lattice_sites(h))
         self.words = int(_lib.perc_lattice_words(h))
@@ -136,8 +143,9 @@ class Lattice:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            _lib.perc_lattice_destroy(h)
+        lib = getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.perc_lattice_destroy(h)
             self._h = None
 
     def __repr__(self):
@@ -235,6 +243,39 @@ def perc_pi_ex(lat: Lattice, p: float, n_cfg: int, seed: int, bits=None, steps=N
     _check(_lib.perc_pi_ex(lat.handle, float(p), int(n_cfg), int(seed) & (2**64 - 1), C.byref(out), C.byref(opt),
                            _stream(stream)))
     return int(out.n_perc), float(out.pi)
+
+
+def perc_batch(jobs, n_groups: int = 0, perc=None, steps=None, hit=False, form="auto", depth=0, block=0, grid=0,
+               graph_steps=0, stream=None):
+    """Inspect a list of jobs of possibly different lattices in one batch.
+
+    ``jobs``: sequence of (lattice, occ) with occ a device int32 word tensor of one
+    configuration, or (lattice, p, seed, cfg[, group]) for a Philox draw. Returns
+    (perc uint8, steps int32, hit float32 or None, group counts list)."""
+    n = len(jobs)
+    arr = (perc_job * max(n, 1))()
+    keep = []
+    for j, job in enumerate(jobs):
+        lat = job[0]
+        if isinstance(job[1], torch.Tensor):
+            keep.append(job[1])
+            grp = int(job[2]) if len(job) > 2 else -1
+            arr[j] = perc_job(lat.handle, _dptr(job[1], torch.int32, lat.words), 0.0, 0, 0, grp)
+        else:
+            p, seed, cfg = job[1], job[2], job[3]
+            grp = int(job[4]) if len(job) > 4 else -1
+            arr[j] = perc_job(lat.handle, None, float(p), int(seed) & (2**64 - 1), int(cfg), grp)
+    if perc is None:
+        perc = torch.empty(n, dtype=torch.uint8, device="cuda")
+    if steps is None:
+        steps = torch.empty(n, dtype=torch.int32, device="cuda")
+    hit_t = torch.empty(n, dtype=torch.float32, device="cuda") if hit is True else (hit if isinstance(hit, torch.Tensor) else None)
+    counts = (C.c_int64 * max(n_groups, 1))()
+    opt = _options(form, depth, block, grid, graph_steps)
+    _check(_lib.perc_batch(arr, n, _dptr(perc, torch.uint8, n), _dptr(steps, torch.int32, n),
+                           _dptr(hit_t, torch.float32, n), counts if n_groups else None, int(n_groups), C.byref(opt),
+                           _stream(stream)))
+    return perc, steps, hit_t, list(counts[:n_groups])
 
 
 def perc_profile_enable(on: bool) -> None:

@@ -18,11 +18,15 @@
 // absent one. A metallic tube of degree 0 keeps its mass (self-loop, Sec. II.B).
 //
 // The state of one configuration is [U cells][CP] words, cell u holding layer 3u + sigma
-// of every column (see perc_internal.hpp). A chunk of D consecutive cells is staged in
-// LDS column-major with one halo cell on each side: word (column c, slot j) at byte
-// (c*(D+2) + j)*4, so the 14 contacts of tube (j, c) are LDS reads at per-column byte
-// offsets plus the compile-time immediate -- no address arithmetic per tube. All LDS of
-// these kernels is dynamic (layout: lds_map), so the chunk sits at LDS address 0.
+// of every column (see perc_internal.hpp). Work is cut into items: one tile of
+// consecutive columns x a range of cells. A workgroup walks its item along the fiber
+// axis, one thread per column of the tile: the tile's halo range of columns is staged
+// for the cells u-1, u, u+1 in a ring of LDS slots (column-major, kRing words per
+// column, two mirrored slots so that any three consecutive cells sit at consecutive
+// indices), cell u+3 is fetched into registers while cell u computes, and one barrier
+// separates cells. The 14 contacts of a tube are LDS reads at per-column byte offsets
+// held in registers for the whole walk plus a compile-time immediate for the ring
+// phase. All LDS of these kernels is dynamic, so the ring sits at address 0.
 #include <hip/hip_runtime.h>
 
 #include "perc_internal.hpp"
@@ -32,14 +36,24 @@ namespace perc {
 namespace {
 
 constexpr int kMaxBlock = 1024;
-constexpr int kXcds = 8;  // MI355X: workgroups are dealt round-robin over 8 XCDs
+constexpr int kXcds = 8;         // MI355X: workgroups are dealt round-robin over 8 XCDs
+constexpr int kLoadCols = 2;     // staged columns per thread: span <= 2 * blockDim
 
 extern __shared__ __align__(16) unsigned char lds[];
 
-__device__ __forceinline__ uint32_t lds_u32(uint32_t off) { return *reinterpret_cast<const uint32_t*>(lds + off); }
-__device__ __forceinline__ float lds_f32(uint32_t off) { return *reinterpret_cast<const float*>(lds + off); }
-__device__ __forceinline__ uint32_t lds_u8(uint32_t off) { return lds[off]; }
 __device__ __forceinline__ void lds_put_u32(uint32_t off, uint32_t v) { *reinterpret_cast<uint32_t*>(lds + off) = v; }
+
+// Fixed tail of the dynamic LDS of a launch of `total` bytes.
+struct Tail {
+    float* rcp;  // the 16 reciprocals
+    uint32_t* misc;
+    float* part;
+};
+__device__ __forceinline__ Tail lds_tail(int total) {
+    const uint32_t t = (uint32_t)total - kLdsTail;
+    return Tail{reinterpret_cast<float*>(lds + t), reinterpret_cast<uint32_t*>(lds + t + 64),
+                reinterpret_cast<float*>(lds + t + 128)};
+}
 
 // ------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds; each round takes
@@ -82,6 +96,8 @@ __device__ __forceinline__ uint32_t sample_word(int64_t w, int64_t N, uint64_t g
     return out;
 }
 
+__device__ __forceinline__ uint32_t shape_tag(const DevShape& sh) { return ((uint32_t)sh.W << 16) | (uint32_t)sh.L; }
+
 // 1/deg per code: code 0 keeps its mass (factor 1), 1..14 the correctly rounded
 // FP32 reciprocal, 15 (insulating) sends nothing.
 __device__ __forceinline__ void fill_rcp(float* rcp) {
@@ -93,108 +109,341 @@ __device__ __forceinline__ void fill_rcp(float* rcp) {
 
 __device__ __forceinline__ float mag(uint32_t w) { return __uint_as_float(w & 0x7fffffffu); }
 
-// Stage cells u0-1 .. u0+D of a state buffer (column-major) and the degree codes of
-// cells u0 .. u0+D-1 into LDS. Cells beyond the reached front or outside the fiber and
-// the pad column C read as zero; codes outside the fiber as 15.
-template <int D>
-__device__ __forceinline__ void stage_chunk(const DevTables& t, const LdsMap& m, const float* __restrict__ y,
-                                            const uint8_t* __restrict__ code, int u0, int front) {
-    constexpr int SJ = D + 2;
-    const int C = t.C;
-    for (int c = threadIdx.x; c <= C; c += blockDim.x) {
-        float v[SJ];
+struct TileV {
+    int ts, te, hs, he;
+};
+__device__ __forceinline__ TileV load_tile(const DevShape& sh, int k) {
+    const int32_t* p = sh.tile + 4 * k;
+    return TileV{p[0], p[1], p[2], p[3]};
+}
+
+// ------------------------------------------------------------------------------
+// State layout in HBM: the cells of a configuration are taken in groups of four
+// (cells 4g .. 4g+3); word k of the 16-byte quad (g, c) holds cell 4g+k of column c,
+// quads in [group][CP] order, so one 16-byte load or store moves four cells of a
+// column and a wave's 64 columns are 1 KiB contiguous. The degree codes use the same
+// layout with bytes (one 32-bit word per quad).
+// ------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t quad_of(const DevShape& sh, int g, int c) { return (uint32_t)g * sh.CP + c; }
+__device__ __forceinline__ uint32_t word_of(const DevShape& sh, int u, int c) {
+    return quad_of(sh, u >> 2, c) * 4u + (uint32_t)(u & 3);
+}
+
+// ------------------------------------------------------------------------------
+// The ring (per staged column, kRing words): cell u in index (u mod 8) + 1, the slot-7
+// cell also in index 0 and the slot-0 cell also in index 9, so the cells u-1, u, u+1
+// sit at consecutive indices for every u. LDS column 0 is the zero pad column (missing
+// contacts), staged column lc is LDS column lc + 1, and staging lanes beyond the halo
+// range write to dummy columns after it, so that no LDS write is predicated.
+//
+// A walk covers whole groups from an 8-aligned cell, one cell per phase, eight phases
+// unrolled so that every ring slot is a compile-time constant; one barrier per cell.
+// At the second cell of group g the next group g+1 goes from registers into the ring
+// (its slots held group g-1, whose last cell the first cell of g needed) and group
+// g+2 is fetched: four cells of work between the issue of a load and its use. Global
+// loads are never predicated: the group index is clamped into the configuration and
+// the words are masked when written to the ring.
+// ------------------------------------------------------------------------------
+struct Stage {
+    int col[kLoadCols];         // global column of each staged column of this thread (clamped)
+    uint32_t* slot[kLoadCols];  // its LDS column (a dummy column beyond the range)
+    int nj;                     // staged column slots the workgroup needs (uniform)
+};
+
+__device__ __forceinline__ Stage stage_columns(const TileV& tv) {
+    Stage st;
+    const int span = tv.he - tv.hs;
+    st.nj = (span + (int)blockDim.x - 1) / (int)blockDim.x;
+    uint32_t* base = reinterpret_cast<uint32_t*>(lds);
 #pragma unroll
-        for (int j = 0; j < SJ; ++j) {
-            const int u = u0 - 1 + j;
-            v[j] = (c < C && u >= 0 && u <= front && u < t.U) ? y[(uint32_t)(u * t.CP + c)] : 0.0f;
-        }
-        uint32_t cd[D];
+    for (int j = 0; j < kLoadCols; ++j) {
+        const int lc = (int)threadIdx.x + j * (int)blockDim.x;
+        const bool ok = lc < span;
+        st.col[j] = ok ? tv.hs + lc : tv.hs;
+        st.slot[j] = base + (ok ? lc + 1 : span + 1 + (int)(threadIdx.x & (kDummyCols - 1))) * kRing;
+    }
+    return st;
+}
+
+// The pad column holds zeros.
+__device__ __forceinline__ void zero_pad() {
+    if (threadIdx.x < (unsigned)kRing) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = 0u;
+}
+
+// Four ring words v[0..3] of group g into ring slots S0 .. S0+3 (S0 = 0 or 4) of staged
+// column j, with the mirror of the slot-0 or slot-7 cell. Cells outside [0, vmax] hold
+// no mass (their words are not meaningful) and are written as zero.
+template <int S0>
+__device__ __forceinline__ void put_quad(uint32_t* slot, int g, int vmax, uint4 q) {
+    const int u = 4 * g;
+    const uint32_t a = (u >= 0 && u <= vmax) ? q.x : 0u;
+    const uint32_t b = (u + 1 >= 0 && u + 1 <= vmax) ? q.y : 0u;
+    const uint32_t c = (u + 2 >= 0 && u + 2 <= vmax) ? q.z : 0u;
+    const uint32_t d = (u + 3 >= 0 && u + 3 <= vmax) ? q.w : 0u;
+    slot[S0 + 1] = a;
+    slot[S0 + 2] = b;
+    slot[S0 + 3] = c;
+    slot[S0 + 4] = d;
+    if (S0 == 0) slot[kRingCells + 1] = a;
+    if (S0 == 4) slot[0] = d;
+}
+
+// Raw state quads of group g (clamped into [0, vmax / 4]) for the staged columns.
+__device__ __forceinline__ void load_quads(const DevShape& sh, const Stage& st, const float* __restrict__ y, int g,
+                                           int vmax, uint4 (&out)[kLoadCols]) {
+    const uint4* q = reinterpret_cast<const uint4*>(y) + (uint32_t)min(max(g, 0), vmax >> 2) * sh.CP;
 #pragma unroll
-        for (int j = 1; j <= D; ++j) {
-            const int u = u0 - 1 + j;
-            cd[j - 1] = (c < C && u < t.U) ? code[(uint32_t)(u * t.CP + c)] : 15u;
-        }
+    for (int j = 0; j < kLoadCols; ++j) out[j] = j < st.nj ? q[st.col[j]] : make_uint4(0u, 0u, 0u, 0u);
+}
+
+template <int S0>
+__device__ __forceinline__ void put_quads(const Stage& st, int g, int vmax, const uint4 (&q)[kLoadCols]) {
 #pragma unroll
-        for (int j = 0; j < SJ; ++j) lds_put_u32((uint32_t)(c * SJ + j) * 4u, __float_as_uint(v[j]));
-        if (c < C) {
+    for (int j = 0; j < kLoadCols; ++j) {
+        if (j >= st.nj) break;
+        put_quad<S0>(st.slot[j], g, vmax, q[j]);
+    }
+}
+
+// Per-thread view of its own column: the 12 contacts and its own ring words. Threads
+// beyond the tile take the tile's first column: they compute (and store) exactly what
+// thread 0 does, so no compute or store needs a lane predicate.
+struct Own {
+    const uint32_t* nb[kSide];
+    const uint32_t* me;
+    int c, top;
+};
+
+__device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
+    Own w;
+    const bool cmp = (int)threadIdx.x < tv.te - tv.ts;
+    w.c = cmp ? tv.ts + (int)threadIdx.x : tv.ts;
+    const uint32_t* base = reinterpret_cast<const uint32_t*>(lds);
 #pragma unroll
-            for (int j = 0; j < D; ++j) lds[m.code + (uint32_t)(c * D + j)] = (unsigned char)cd[j];
+    for (int i = 0; i < kSide; ++i) w.nb[i] = base + sh.nboff[i * sh.C + w.c];
+    w.me = base + (w.c - tv.hs + 1) * kRing;
+    w.top = sh.top[w.c];
+    return w;
+}
+
+struct StepState {
+    uint4 next[kLoadCols];  // staged quads of the group after the current one
+    uint32_t cq[2];         // code quads, by group parity
+    uint32_t res[4];        // new words of the current group
+    uint32_t grew = 0, far = 0, entered = 0;
+};
+
+// Cell u = u8 + K (ring slot K) of a step walk.
+template <int K>
+__device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, const Own& w, const float* rcp,
+                                          const float* __restrict__ yin, float* __restrict__ yout,
+                                          const uint32_t* __restrict__ code4, int u8, int ue, int front, int vmax,
+                                          StepState& ss) {
+    constexpr int k = K & 3, par = K >> 2;
+    const int u = u8 + K, g = u >> 2;
+    __syncthreads();
+    if (k == 1) {
+        put_quads<(par ^ 1) * 4>(st, g + 1, vmax, ss.next);
+        load_quads(sh, st, yin, g + 2, vmax, ss.next);
+        ss.cq[par ^ 1] = code4[quad_of(sh, min(g + 1, (sh.U + 3) / 4 - 1), w.c)];
+    }
+    const uint32_t cd = (ss.cq[par] >> (8 * k)) & 0xffu;
+    const uint32_t own = w.me[K + 1];
+    const uint32_t dn = w.me[K];
+    const uint32_t up = w.me[K + 2];
+    uint32_t n[kSide];
+#pragma unroll
+    for (int i = 0; i < kSide; ++i) n[i] = w.nb[i][K];
+    uint32_t any = own | dn | up;
+#pragma unroll
+    for (int i = 0; i < kSide; ++i) any |= n[i];
+    // fixed order: in-layer pairs, up/down-layer pairs, then the end contacts
+    const float s01 = mag(n[0]) + mag(n[1]);
+    const float s23 = mag(n[2]) + mag(n[3]);
+    const float s45 = mag(n[4]) + mag(n[5]);
+    const float s67 = mag(n[6]) + mag(n[7]);
+    const float s89 = mag(n[8]) + mag(n[9]);
+    const float sab = mag(n[10]) + mag(n[11]);
+    const float sud = mag(dn) + mag(up);
+    const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
+    // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its
+    // own mass
+    const float x = sum + (cd == 0u ? mag(own) : 0.0f);
+    const uint32_t newr = (any >> 31) & (cd < 15u ? 1u : 0u) & (u < ue ? 1u : 0u);
+    const float yn = x * rcp[cd];
+    ss.res[k] = __float_as_uint(yn) | (newr << 31);
+    ss.grew |= newr & ~(own >> 31);
+    ss.far |= newr & (u == w.top ? 1u : 0u);
+    ss.entered |= newr & (u == front + 1 ? 1u : 0u);
+    if (k == 3)
+        reinterpret_cast<uint4*>(yout)[quad_of(sh, g, w.c)] = make_uint4(ss.res[0], ss.res[1], ss.res[2], ss.res[3]);
+}
+
+// One Jacobi step of the tile's tubes in cells [ub, ue) (cut at min(U, front+2); ub a
+// multiple of 8), reading yin and writing yout. Returns this thread's step flags. The
+// 14 contributions are summed in one fixed pairwise order, so a tube gets the same
+// FP32 result in every execution form, item layout and batch composition. The words
+// written for cells of the last group at or beyond the cut are zero (their inputs are
+// beyond the front) or lie in the padding beyond U: no other item writes them and no
+// reader uses them.
+__device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& tv, const float* rcp,
+                                              const float* __restrict__ yin, float* __restrict__ yout,
+                                              const uint8_t* __restrict__ code, int ub, int ue, int front) {
+    ue = min(ue, min(sh.U, front + 2));
+    if (ub >= ue) return 0u;
+    const int vmax = min(front, sh.U - 1);
+    const uint32_t* code4 = reinterpret_cast<const uint32_t*>(code);
+    const Stage st = stage_columns(tv);
+    const Own w = own_column(sh, tv);
+    const int g0 = ub >> 2;
+    __syncthreads();  // the ring may still be read by a previous item
+    zero_pad();
+    StepState ss;
+    uint4 q[kLoadCols];
+    load_quads(sh, st, yin, g0 - 1, vmax, q);
+    put_quads<4>(st, g0 - 1, vmax, q);
+    load_quads(sh, st, yin, g0, vmax, q);
+    put_quads<0>(st, g0, vmax, q);
+    load_quads(sh, st, yin, g0 + 1, vmax, ss.next);
+    ss.cq[0] = code4[quad_of(sh, g0, w.c)];
+    ss.cq[1] = 0xffffffffu;
+    for (int u8 = ub; u8 < ue; u8 += kRingCells) {
+        step_cell<0>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        step_cell<1>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        step_cell<2>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        step_cell<3>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        if (u8 + 4 >= ue) break;
+        step_cell<4>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        step_cell<5>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        step_cell<6>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        step_cell<7>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+    }
+    return (ss.grew ? F_GREW : 0u) | (ss.far ? F_FAR : 0u) | (ss.entered ? F_FRONT : 0u);
+}
+
+// ------------------------------------------------------------------------------
+// Initialisation walk: the ring holds the occupancy (0/1) of the staged tubes; each
+// tube's degree code is its number of metallic contacts (detector edge included), 15
+// if it is insulating or absent.
+// ------------------------------------------------------------------------------
+
+// Raw occupancy words holding the bits of the four cells of group g (clamped into the
+// configuration; put_occ_quad masks what lies outside).
+__device__ __forceinline__ void load_occ_quad(const DevShape& sh, const Stage& st, const int (&rk)[kLoadCols],
+                                              const uint32_t* __restrict__ bits, int g, uint32_t (&out)[4][kLoadCols]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t vc = (int64_t)min(max(4 * g + k, 0), sh.U - 1) * sh.C;
+#pragma unroll
+        for (int j = 0; j < kLoadCols; ++j) {
+            const int64_t s = vc + rk[j];
+            out[k][j] = j < st.nj ? bits[(s < sh.N ? s : sh.N - 1) >> 5] : 0u;
         }
     }
 }
 
-// One Jacobi step for cells u0 .. u0+D-1 (those below min(U, front+2)), reading the
-// staged input and writing y' to `yout`. Returns the OR of the step flags seen by
-// this thread. The 14 contributions are summed in one fixed pairwise order, so a tube
-// gets the same FP32 result in every execution form and batch composition.
-template <int D>
-__device__ __forceinline__ uint32_t step_chunk(const DevTables& t, const LdsMap& m, float* __restrict__ yout,
-                                               int u0, int front) {
-    constexpr int SJ = D + 2;
-    const int C = t.C;
-    const int ulim = min(t.U, front + 2);
-    uint32_t grew = 0, far = 0, entered = 0;
-    // the contact table entries of the next column are loaded while this one computes
-    uint32_t o_next[kSide];
-    int top_next = -1;
-    if ((int)threadIdx.x < C) {
+template <int S0>
+__device__ __forceinline__ void put_occ_quad(const DevShape& sh, const Stage& st, const int (&rk)[kLoadCols], int g,
+                                             const uint32_t (&raw)[4][kLoadCols]) {
 #pragma unroll
-        for (int i = 0; i < kSide; ++i) o_next[i] = t.nboff[i * C + threadIdx.x];
-        top_next = t.top[threadIdx.x];
-    }
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        uint32_t o[kSide];
+    for (int j = 0; j < kLoadCols; ++j) {
+        if (j >= st.nj) break;
+        uint32_t b[4];
 #pragma unroll
-        for (int i = 0; i < kSide; ++i) o[i] = o_next[i];
-        const int top = top_next;
-        const int cn = c + (int)blockDim.x;
-        if (cn < C) {
-#pragma unroll
-            for (int i = 0; i < kSide; ++i) o_next[i] = t.nboff[i * C + cn];
-            top_next = t.top[cn];
+        for (int k = 0; k < 4; ++k) {
+            const int v = 4 * g + k;
+            const int64_t s = (int64_t)v * sh.C + rk[j];
+            b[k] = (v >= 0 && v < sh.U && s < sh.N) ? (raw[k][j] >> (uint32_t)(s & 31)) & 1u : 0u;
         }
-        const uint32_t oc = (uint32_t)(c * SJ) * 4u;
-        const uint32_t ocd = m.code + (uint32_t)(c * D);
-#pragma unroll
-        for (int j = 1; j <= D; ++j) {
-            const int u = u0 - 1 + j;
-            if (u >= ulim) break;
-            const uint32_t own = lds_u32(oc + j * 4);
-            const uint32_t dn = lds_u32(oc + (j - 1) * 4);
-            const uint32_t up = lds_u32(oc + (j + 1) * 4);
-            uint32_t n[kSide];
-#pragma unroll
-            for (int i = 0; i < kSide; ++i) n[i] = lds_u32(o[i] + (j - 1) * 4);
-            const uint32_t cd = lds_u8(ocd + (j - 1));
-            uint32_t any = own | dn | up;
-#pragma unroll
-            for (int i = 0; i < kSide; ++i) any |= n[i];
-            // fixed order: in-layer pairs, up/down-layer pairs, then the end contacts
-            const float s01 = mag(n[0]) + mag(n[1]);
-            const float s23 = mag(n[2]) + mag(n[3]);
-            const float s45 = mag(n[4]) + mag(n[5]);
-            const float s67 = mag(n[6]) + mag(n[7]);
-            const float s89 = mag(n[8]) + mag(n[9]);
-            const float sab = mag(n[10]) + mag(n[11]);
-            const float sud = mag(dn) + mag(up);
-            const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
-            // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps
-            // its own mass
-            const float x = sum + (cd == 0u ? mag(own) : 0.0f);
-            const uint32_t newr = (any >> 31) & (cd < 15u ? 1u : 0u);
-            const float yn = x * lds_f32(m.rcp + cd * 4u);
-            yout[(uint32_t)(u * t.CP + c)] = __uint_as_float(__float_as_uint(yn) | (newr << 31));
-            grew |= newr & ~(own >> 31);
-            far |= newr & (u == top ? 1u : 0u);
-            if (u == front + 1) entered |= newr;
-        }
+        st.slot[j][S0 + 1] = b[0];
+        st.slot[j][S0 + 2] = b[1];
+        st.slot[j][S0 + 3] = b[2];
+        st.slot[j][S0 + 4] = b[3];
+        if (S0 == 0) st.slot[j][kRingCells + 1] = b[0];
+        if (S0 == 4) st.slot[j][0] = b[3];
     }
-    return (grew ? F_GREW : 0u) | (far ? F_FAR : 0u) | (entered ? F_FRONT : 0u);
+}
+
+struct InitState {
+    uint32_t next[4][kLoadCols];  // raw occupancy words of the group after the current one
+    uint32_t cq = 0;              // codes of the current group
+    float y0 = 0.0f;
+    uint32_t fl = 0;
+};
+
+template <int K>
+__device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, const Own& w,
+                                          const int (&rk)[kLoadCols], const float* rcp,
+                                          const uint32_t* __restrict__ bits, uint32_t* __restrict__ code4,
+                                          float* __restrict__ y0, int u8, int ue, float x0, InitState& is) {
+    constexpr int k = K & 3, par = K >> 2;
+    const int u = u8 + K, g = u >> 2;
+    __syncthreads();
+    if (k == 1) {
+        put_occ_quad<(par ^ 1) * 4>(sh, st, rk, g + 1, is.next);
+        load_occ_quad(sh, st, rk, bits, g + 2, is.next);
+    }
+    const uint32_t me = w.me[K + 1];
+    uint32_t deg = w.me[K] + w.me[K + 2] + (u == w.top ? 1u : 0u);
+#pragma unroll
+    for (int i = 0; i < kSide; ++i) deg += w.nb[i][K];
+    const uint32_t cd = me ? deg : 15u;
+    is.cq |= cd << (8 * k);
+    if (u == 0 && me) {
+        is.y0 = __uint_as_float(__float_as_uint(x0 * rcp[cd]) | 0x80000000u);
+        is.fl |= F_NONEMPTY;
+        if (u == w.top) is.fl |= F_FAR;
+    }
+    if (k == 3) {
+        code4[quad_of(sh, g, w.c)] = is.cq;
+        is.cq = 0;
+        if (g == 0)
+            reinterpret_cast<uint4*>(y0)[quad_of(sh, 0, w.c)] = make_uint4(__float_as_uint(is.y0), 0u, 0u, 0u);
+    }
+}
+
+// Degree codes of the tile's tubes in cells [ub, ue) (whole groups; ub a multiple of
+// 8) from the occupancy, and the start state (group 0): x0 = 1/|S0| on every metallic
+// start tube, reached. Returns the initialisation flags (start set non-empty, a start
+// tube on the far surface).
+__device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& tv, const float* rcp,
+                                              const uint32_t* __restrict__ bits, uint8_t* __restrict__ code,
+                                              float* __restrict__ y0, int ub, int ue, float x0) {
+    ue = min(ue, sh.U);
+    if (ub >= ue) return 0u;
+    uint32_t* code4 = reinterpret_cast<uint32_t*>(code);
+    const Stage st = stage_columns(tv);
+    int rk[kLoadCols];
+#pragma unroll
+    for (int j = 0; j < kLoadCols; ++j) rk[j] = sh.rank[st.col[j]];
+    const Own w = own_column(sh, tv);
+    const int g0 = ub >> 2;
+    __syncthreads();
+    zero_pad();
+    InitState is;
+    uint32_t raw[4][kLoadCols];
+    load_occ_quad(sh, st, rk, bits, g0 - 1, raw);
+    put_occ_quad<4>(sh, st, rk, g0 - 1, raw);
+    load_occ_quad(sh, st, rk, bits, g0, raw);
+    put_occ_quad<0>(sh, st, rk, g0, raw);
+    load_occ_quad(sh, st, rk, bits, g0 + 1, is.next);
+    for (int u8 = ub; u8 < ue; u8 += kRingCells) {
+        init_cell<0>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        init_cell<1>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        init_cell<2>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        init_cell<3>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        if (u8 + 4 >= ue) break;
+        init_cell<4>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        init_cell<5>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        init_cell<6>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        init_cell<7>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+    }
+    return is.fl;
 }
 
 // Number of metallic start tubes (every tube of cell 0) of one configuration.
-__device__ __forceinline__ int count_start(const DevTables& t, const uint32_t* __restrict__ bits, int* red) {
-    const int64_t n0 = min((int64_t)t.C, t.N);
+__device__ __forceinline__ int count_start(const DevShape& sh, const uint32_t* __restrict__ bits, uint32_t* red) {
+    const int64_t n0 = min((int64_t)sh.C, sh.N);
     int cnt = 0;
     for (int64_t w = threadIdx.x; w * 32 < n0; w += blockDim.x) {
         uint32_t b = bits[w];
@@ -202,81 +451,32 @@ __device__ __forceinline__ int count_start(const DevTables& t, const uint32_t* _
         if (rem < 32) b &= (1u << rem) - 1u;
         cnt += __popc(b);
     }
+    __syncthreads();
     if (threadIdx.x == 0) *red = 0;
     __syncthreads();
-    if (cnt) atomicAdd(red, cnt);
+    if (cnt) atomicAdd(red, (uint32_t)cnt);
     __syncthreads();
-    const int total = *red;
+    const int total = (int)*red;
     __syncthreads();
     return total;
-}
-
-// Degree codes of cells u0 .. u0+D-1 from the occupancy (staged as 0/1 words in the
-// state area of the LDS), and the initial state of the start tubes (cell 0):
-// x0 = 1/|S0| on every metallic start tube, reached.
-template <int D>
-__device__ __forceinline__ uint32_t init_chunk(const DevTables& t, const LdsMap& m, const uint32_t* __restrict__ bits,
-                                               uint8_t* __restrict__ code, float* __restrict__ y0, int u0, float x0) {
-    constexpr int SJ = D + 2;
-    const int C = t.C;
-    for (int c = threadIdx.x; c <= C; c += blockDim.x) {
-#pragma unroll
-        for (int j = 0; j < SJ; ++j) {
-            const int u = u0 - 1 + j;
-            const int64_t s = (int64_t)u * C + c;
-            uint32_t o = 0;
-            if (c < C && u >= 0 && u < t.U && s < t.N) o = (bits[s >> 5] >> (s & 31)) & 1u;
-            lds_put_u32((uint32_t)(c * SJ + j) * 4u, o);
-        }
-    }
-    __syncthreads();
-    uint32_t fl = 0;
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        uint32_t o[kSide];
-#pragma unroll
-        for (int i = 0; i < kSide; ++i) o[i] = t.nboff[i * C + c];
-        const int top = t.top[c];
-        const uint32_t oc = (uint32_t)(c * SJ) * 4u;
-#pragma unroll
-        for (int j = 1; j <= D; ++j) {
-            const int u = u0 - 1 + j;
-            if (u >= t.U) break;
-            const uint32_t me = lds_u32(oc + j * 4);
-            uint32_t deg = lds_u32(oc + (j - 1) * 4) + lds_u32(oc + (j + 1) * 4) + (u == top ? 1u : 0u);
-#pragma unroll
-            for (int i = 0; i < kSide; ++i) deg += lds_u32(o[i] + (j - 1) * 4);
-            const uint32_t cd = me ? deg : 15u;
-            code[(uint32_t)(u * t.CP + c)] = (uint8_t)cd;
-            if (u == 0) {
-                float yv = 0.0f;
-                if (me) {
-                    yv = __uint_as_float(__float_as_uint(x0 * lds_f32(m.rcp + cd * 4u)) | 0x80000000u);
-                    fl |= F_NONEMPTY;
-                    if (u == top) fl |= F_FAR;
-                }
-                y0[c] = yv;
-            }
-        }
-    }
-    __syncthreads();
-    return fl;
 }
 
 // Sum over the far-end tubes of |y| (the mass the detector receives next step) and
 // whether any of them is reached. Cells beyond `front` hold no mass and are not read
 // (their words may be stale). Fixed order independent of blockDim: 256 virtual lanes
 // each add their columns in increasing order, then a fixed pairwise tree.
-__device__ __forceinline__ void far_sum(const DevTables& t, const float* __restrict__ y, int front, float* part,
+__device__ __forceinline__ void far_sum(const DevShape& sh, const float* __restrict__ y, int front, float* part,
                                         uint32_t* reached, float* result) {
+    __syncthreads();
     if (threadIdx.x == 0) *reached = 0;
     __syncthreads();
     for (int v = threadIdx.x; v < 256; v += blockDim.x) {
         float s = 0.0f;
         uint32_t r = 0;
-        for (int c = v; c < t.C; c += 256) {
-            const int u = t.top[c];
+        for (int c = v; c < sh.C; c += 256) {
+            const int u = sh.top[c];
             if (u < 0 || u > front) continue;
-            const uint32_t w = __float_as_uint(y[(uint32_t)(u * t.CP + c)]);
+            const uint32_t w = __float_as_uint(y[word_of(sh, u, c)]);
             s += mag(w);
             r |= w >> 31;
         }
@@ -292,17 +492,35 @@ __device__ __forceinline__ void far_sum(const DevTables& t, const float* __restr
     __syncthreads();
 }
 
-// Items [0, total) of a launch, dealt so that the workgroups of one XCD take one
-// contiguous range (neighbouring chunks of a configuration then share that XCD's L2).
+// Items [0, total) of a launch: the workgroups of one XCD share one contiguous range
+// and each takes a contiguous block of it, so a workgroup walks neighbouring tiles and
+// cell ranges of one configuration in turn.
 struct ItemRange {
-    int64_t begin, end, stride;
+    int64_t begin, end;
 };
-__device__ __forceinline__ ItemRange xcd_items(int64_t total) {
+__device__ __forceinline__ ItemRange my_items(int64_t total) {
     const int G = gridDim.x;
-    if (G % kXcds != 0 || total < G) return ItemRange{(int64_t)blockIdx.x, total, (int64_t)G};
+    if (G % kXcds != 0) {
+        const int64_t b = total * blockIdx.x / G, e = total * (blockIdx.x + 1) / G;
+        return ItemRange{b, e};
+    }
     const int x = blockIdx.x % kXcds, lb = blockIdx.x / kXcds, per = G / kXcds;
-    const int64_t b = total * x / kXcds, e = total * (x + 1) / kXcds;
-    return ItemRange{b + lb, e, (int64_t)per};
+    const int64_t xb = total * x / kXcds, xe = total * (x + 1) / kXcds;
+    const int64_t n = xe - xb;
+    return ItemRange{xb + n * lb / per, xb + n * (lb + 1) / per};
+}
+
+__device__ __forceinline__ int items_of(const DevShape& sh, int ncells, int E) {
+    return ((ncells + E - 1) / E) * sh.ntile;
+}
+
+__device__ __forceinline__ int find_entry(const int64_t* off, int n, int64_t g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 // ------------------------------------------------------------------------------
@@ -320,40 +538,83 @@ __global__ void __launch_bounds__(256) k_sample(uint32_t* __restrict__ bits, int
     }
 }
 
-template <int D>
-__global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
-    const DevTables& t = a.t;
-    const LdsMap m = lds_map(t.C, D);
-    float* rcp = reinterpret_cast<float*>(lds + m.rcp);
-    uint32_t* misc = reinterpret_cast<uint32_t*>(lds + m.misc);
-    fill_rcp(rcp);
-    const int64_t stride = (int64_t)t.U * t.CP;
-    const int nchunk = (t.U + D - 1) / D;
-    const int64_t total = (int64_t)a.n_slot * nchunk;
+// Occupancy of the slots whose job samples from Philox, one workgroup per slot, into
+// the slot's bits buffer.
+__global__ void __launch_bounds__(256) k_sample_slots(const DevShape* shapes, const Job* jobs, int32_t n_slot,
+                                                      uint32_t* const* slot_bits) {
+    for (int b = blockIdx.x; b < n_slot; b += gridDim.x) {
+        const Job job = jobs[b];
+        if (job.bits) continue;
+        const DevShape sh = shapes[job.shape];
+        uint32_t* dst = slot_bits[b];
+        const uint32_t k0 = (uint32_t)job.seed, k1 = (uint32_t)(job.seed >> 32);
+        for (int64_t w = threadIdx.x; w < sh.words; w += blockDim.x)
+            dst[w] = sample_word(w, sh.N, job.cfg, job.thr, k0, k1, shape_tag(sh));
+    }
+}
+
+// Item layout of the initialisation (all cells of every slot) and the slot states.
+__global__ void __launch_bounds__(kMaxBlock) k_span_layout(SpanArgs a) {
+    __shared__ int64_t sums[kMaxBlock];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (a.n_slot + nt - 1) / nt;
+    const int i0 = min(a.n_slot, tid * per), i1 = min(a.n_slot, i0 + per);
+    int64_t mine = 0;
+    for (int b = i0; b < i1; ++b) {
+        const DevShape& sh = a.shapes[a.slot_shape[b]];
+        mine += items_of(sh, sh.U, a.depth);
+        a.st[b] = CfgState{0, 0, 0, 0u};
+    }
+    sums[tid] = mine;
     __syncthreads();
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const int b = (int)(g / nchunk);
-        const int u0 = (int)(g - (int64_t)b * nchunk) * D;
-        const uint32_t* bits = a.bits + (int64_t)b * t.words;
+    for (int off = 1; off < nt; off <<= 1) {
+        const int64_t v = tid >= off ? sums[tid - off] : 0;
+        __syncthreads();
+        sums[tid] += v;
+        __syncthreads();
+    }
+    int64_t pos = sums[tid] - mine;
+    for (int b = i0; b < i1; ++b) {
+        a.chunk_off[b] = pos;
+        const DevShape& sh = a.shapes[a.slot_shape[b]];
+        pos += items_of(sh, sh.U, a.depth);
+    }
+    if (tid == nt - 1) a.chunk_off[a.n_slot] = sums[nt - 1];
+}
+
+// Initialisation of every slot: items (slot, cell range, tile) over all cells.
+__global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
+    const Tail tl = lds_tail(a.lds);
+    fill_rcp(tl.rcp);
+    const int E = a.depth;
+    const ItemRange it = my_items(a.chunk_off[a.n_slot]);
+    for (int64_t g = it.begin; g < it.end; ++g) {
+        const int b = find_entry(a.chunk_off, a.n_slot, g);
+        const DevShape sh = a.shapes[a.slot_shape[b]];
+        const int local = (int)(g - a.chunk_off[b]);
+        const int r = local / sh.ntile, k = local - r * sh.ntile;
+        const int ub = r * E;
+        const uint32_t* bits = a.slot_bits[b];
         float x0 = 0.0f;
-        if (u0 == 0) {
-            const int n0 = count_start(t, bits, reinterpret_cast<int*>(misc + 1));
+        if (ub == 0) {
+            const int n0 = count_start(sh, bits, tl.misc + 1);
             x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
         }
-        const uint32_t fl = init_chunk<D>(t, m, bits, a.code + b * stride, a.ya + b * stride, u0, x0);
-        if (u0 == 0) {
-            if (threadIdx.x == 0) misc[0] = 0;
+        const uint32_t fl = walk_init(sh, load_tile(sh, k), tl.rcp, bits, a.code + a.slot_off[b],
+                                      a.ya + a.slot_off[b], ub, ub + E, x0);
+        if (ub == 0) {
             __syncthreads();
-            if (fl) atomicOr(&misc[0], fl);
+            if (threadIdx.x == 0) tl.misc[0] = 0;
             __syncthreads();
-            if (threadIdx.x == 0) a.st[b] = CfgState{0, 0, 0, misc[0]};
+            if (fl) atomicOr(&tl.misc[0], fl);
             __syncthreads();
+            if (threadIdx.x == 0 && tl.misc[0]) atomicOr(&a.st[b].flags, tl.misc[0]);
         }
     }
 }
 
 // Decide every active configuration from the flags of the last launch, write the
-// outputs of those that stopped, and lay out the chunks of the next step for the rest.
+// outputs of those that stopped, and lay out the items of the next step for the rest.
 // did_step = 0 right after initialisation. One workgroup of kMaxBlock threads.
 __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_step, int first) {
     __shared__ int32_t keep_s[kMaxBlock];
@@ -362,11 +623,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
     const int n_act = first ? a.n_slot : a.hdr[0];
     const int per = (n_act + nt - 1) / nt;
     const int i0 = min(n_act, tid * per), i1 = min(n_act, i0 + per);
-    const int D = a.depth, U = a.t.U;
+    const int E = a.depth;
     int32_t keep = 0;
     int64_t chunks = 0;
     for (int i = i0; i < i1; ++i) {
         const int b = first ? i : a.active[i];
+        const DevShape& sh = a.shapes[a.slot_shape[b]];
         CfgState s = a.st[b];
         const uint32_t f = s.flags;
         s.flags = 0;
@@ -380,7 +642,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
             if (f & F_FRONT) s.front += 1;
             if (f & F_FAR) { dec = 1; steps = s.m + 1; }
             else if (!(f & F_GREW)) { dec = 0; steps = s.m; }
-            else if (s.m >= a.cap) { dec = 0; steps = s.m; s.done = 2; a.hdr[2] = 1; }
+            else if (s.m > sh.N) { dec = 0; steps = s.m; s.done = 2; a.hdr[2] = 1; }
         }
         if (dec >= 0) {
             if (s.done == 0) s.done = 1;
@@ -388,7 +650,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
             a.out.steps[b] = steps;
         } else {
             keep += 1;
-            chunks += (min(U, s.front + 2) + D - 1) / D;
+            chunks += items_of(sh, min(sh.U, s.front + 2), E);
         }
         a.st[b] = s;
     }
@@ -408,18 +670,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
     int64_t cpos = chunk_s[tid] - chunks;
     const int32_t n_keep = keep_s[nt - 1];
     const int64_t n_chunks = chunk_s[nt - 1];
-    unsigned long long cells = 0;
+    unsigned long long tubes = 0;
     for (int i = i0; i < i1; ++i) {
         const int b = first ? i : a.active[i];
         const CfgState s = a.st[b];
         if (s.done) continue;
+        const DevShape& sh = a.shapes[a.slot_shape[b]];
         a.active2[kpos] = b;
         a.chunk_off[kpos] = cpos;
         kpos += 1;
-        cpos += (min(U, s.front + 2) + D - 1) / D;
-        cells += (unsigned long long)min(U, s.front + 2);
+        cpos += items_of(sh, min(sh.U, s.front + 2), E);
+        tubes += (unsigned long long)min(sh.U, s.front + 2) * (unsigned long long)sh.C;
     }
-    if (a.work && cells) atomicAdd(a.work, cells);
+    if (a.work && tubes) atomicAdd(a.work, tubes);
     __syncthreads();
     for (int i = tid; i < n_keep; i += nt) a.active[i] = a.active2[i];
     if (tid == 0) {
@@ -429,182 +692,189 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
     }
 }
 
-template <int D>
+// One step over the work list: items (active slot, cell range, tile).
 __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
-    const DevTables& t = a.t;
-    const LdsMap m = lds_map(t.C, D);
-    uint32_t* misc = reinterpret_cast<uint32_t*>(lds + m.misc);
-    fill_rcp(reinterpret_cast<float*>(lds + m.rcp));
+    const Tail tl = lds_tail(a.lds);
+    fill_rcp(tl.rcp);
     const int n_act = a.hdr[0];
-    const int64_t total = a.hdr[1];
-    const int64_t stride = (int64_t)t.U * t.CP;
-    const ItemRange it = xcd_items(total);
-    for (int64_t g = it.begin; g < it.end; g += it.stride) {
-        // active entry i with chunk_off[i] <= g < chunk_off[i+1]
-        int lo = 0, hi = n_act - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.chunk_off[mid] <= g) lo = mid; else hi = mid - 1;
+    const int E = a.depth;
+    const ItemRange it = my_items(a.hdr[1]);
+    if (it.begin >= it.end) return;
+    int lo = find_entry(a.chunk_off, n_act, it.begin);
+    int64_t lo_end = a.chunk_off[lo + 1];
+    for (int64_t g = it.begin; g < it.end; ++g) {
+        while (g >= lo_end) {  // next active slot
+            ++lo;
+            lo_end = a.chunk_off[lo + 1];
         }
         const int b = a.active[lo];
-        const int u0 = (int)(g - a.chunk_off[lo]) * D;
+        const DevShape sh = a.shapes[a.slot_shape[b]];
+        const int local = (int)(g - a.chunk_off[lo]);
+        const int r = local / sh.ntile, k = local - r * sh.ntile;
         const CfgState s = a.st[b];
-        const float* yin = ((s.m & 1) ? a.yb : a.ya) + b * stride;
-        float* yout = ((s.m & 1) ? a.ya : a.yb) + b * stride;
-        __syncthreads();  // previous item finished with the LDS
-        if (threadIdx.x == 0) misc[0] = 0;
-        stage_chunk<D>(t, m, yin, a.code + b * stride, u0, s.front);
+        const int64_t off = a.slot_off[b];
+        const float* yin = ((s.m & 1) ? a.yb : a.ya) + off;
+        float* yout = ((s.m & 1) ? a.ya : a.yb) + off;
+        const uint32_t fl = walk_step(sh, load_tile(sh, k), tl.rcp, yin, yout, a.code + off, r * E, r * E + E,
+                                      s.front);
         __syncthreads();
-        const uint32_t fl = step_chunk<D>(t, m, yout, u0, s.front);
-        if (fl) atomicOr(&misc[0], fl);
+        if (threadIdx.x == 0) tl.misc[0] = 0;
         __syncthreads();
-        if (threadIdx.x == 0 && misc[0]) atomicOr(&a.st[b].flags, misc[0]);
+        if (fl) atomicOr(&tl.misc[0], fl);
+        __syncthreads();
+        if (threadIdx.x == 0 && tl.misc[0]) atomicOr(&a.st[b].flags, tl.misc[0]);
     }
 }
 
-// One step of one configuration over cells [0, U) with an explicit front (test hook):
-// workgroup b handles cells b*D .. b*D+D-1 with the same device code as the batches.
-template <int D>
-__global__ void __launch_bounds__(kMaxBlock) k_chunk_step(DevTables t, const float* yin, float* yout,
-                                                          const uint8_t* code, int front) {
-    const LdsMap m = lds_map(t.C, D);
-    fill_rcp(reinterpret_cast<float*>(lds + m.rcp));
-    const int u0 = blockIdx.x * D;
-    stage_chunk<D>(t, m, yin, code, u0, front);
-    __syncthreads();
-    (void)step_chunk<D>(t, m, yout, u0, front);
+// One step of one configuration over all cells (test hook): workgroup g walks cell
+// range g / ntile of tile g % ntile with the same device code as the batches; every
+// cell is processed (the state buffers are zero where nothing was written).
+__global__ void __launch_bounds__(kMaxBlock) k_chunk_step(DevShape sh, const float* yin, float* yout,
+                                                          const uint8_t* code, int E, int lds_bytes) {
+    const Tail tl = lds_tail(lds_bytes);
+    fill_rcp(tl.rcp);
+    const int r = blockIdx.x / sh.ntile, k = blockIdx.x - r * sh.ntile;
+    (void)walk_step(sh, load_tile(sh, k), tl.rcp, yin, yout, code, r * E, r * E + E, sh.U);
 }
 
-// First-hit probability of every configuration that percolated: the detector mass
-// at the stop equals the far-end sum of the state after steps-1 steps.
+// Per slot: first-hit probability of a percolating configuration (the detector mass at
+// the stop is the far-end sum of the state after steps-1 steps) and the group counts.
 __global__ void __launch_bounds__(256) k_span_finish(SpanArgs a) {
     __shared__ float part[256];
     __shared__ uint32_t reached;
     __shared__ float result;
-    const DevTables& t = a.t;
-    const int64_t stride = (int64_t)t.U * t.CP;
     for (int b = blockIdx.x; b < a.n_slot; b += gridDim.x) {
-        if (!a.out.perc[b]) {
+        const int pc = a.out.perc[b];
+        if (threadIdx.x == 0 && a.out.group_count && a.out.group && pc) {
+            const int grp = a.out.group[b];
+            if (grp >= 0) atomicAdd(&a.out.group_count[grp], 1ull);
+        }
+        if (!a.out.hit) continue;
+        if (!pc) {
             if (threadIdx.x == 0) a.out.hit[b] = 0.0f;
             continue;
         }
+        const DevShape sh = a.shapes[a.slot_shape[b]];
         const int m = a.out.steps[b] - 1;  // state after m steps sits in ya if m even
-        const float* y = ((m & 1) ? a.yb : a.ya) + b * stride;
-        far_sum(t, y, a.st[b].front, part, &reached, &result);
+        const float* y = ((m & 1) ? a.yb : a.ya) + a.slot_off[b];
+        far_sum(sh, y, a.st[b].front, part, &reached, &result);
         if (threadIdx.x == 0) a.out.hit[b] = result;
         __syncthreads();
     }
 }
 
-template <int D>
 __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
-    const DevTables& t = a.t;
-    const LdsMap m = lds_map(t.C, D);
-    uint32_t* misc = reinterpret_cast<uint32_t*>(lds + m.misc);
-    float* part = reinterpret_cast<float*>(lds + m.part);
-    fill_rcp(reinterpret_cast<float*>(lds + m.rcp));
-    const int64_t stride = (int64_t)t.U * t.CP;
-    float* ya = a.ya + blockIdx.x * stride;
-    float* yb = a.yb + blockIdx.x * stride;
-    uint8_t* code = a.code + blockIdx.x * stride;
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const Tail tl = lds_tail(a.lds);
+    fill_rcp(tl.rcp);
+    const int E = a.depth;
+    float* ya = a.ya + blockIdx.x * a.state_stride;
+    float* yb = a.yb + blockIdx.x * a.state_stride;
+    uint8_t* code = a.code + blockIdx.x * a.state_stride;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) {
             const unsigned long long c = atomicAdd(a.queue, 1ull);
-            misc[2] = (uint32_t)c;
-            misc[3] = (uint32_t)(c >> 32);
+            tl.misc[2] = (uint32_t)c;
+            tl.misc[3] = (uint32_t)(c >> 32);
         }
         __syncthreads();
-        const int64_t cfg = (int64_t)(((uint64_t)misc[3] << 32) | misc[2]);
-        if (cfg >= a.n_cfg) break;
+        const int64_t j = (int64_t)(((uint64_t)tl.misc[3] << 32) | tl.misc[2]);
+        if (j >= a.n_jobs) break;
+        const Job job = a.jobs[j];
+        const DevShape sh = a.shapes[job.shape];
         const uint32_t* bits;
-        if (a.bits) {
-            bits = a.bits + cfg * t.words;
+        if (job.bits) {
+            bits = job.bits;
         } else {
-            uint32_t* sb = a.bits_scratch + blockIdx.x * t.words;
-            for (int64_t w = threadIdx.x; w < t.words; w += blockDim.x)
-                sb[w] = sample_word(w, t.N, a.cfg0 + (uint64_t)cfg, a.threshold, k0, k1, a.tag);
+            uint32_t* sb = a.bits_scratch + blockIdx.x * a.bits_stride;
+            const uint32_t k0 = (uint32_t)job.seed, k1 = (uint32_t)(job.seed >> 32);
+            for (int64_t w = threadIdx.x; w < sh.words; w += blockDim.x)
+                sb[w] = sample_word(w, sh.N, job.cfg, job.thr, k0, k1, shape_tag(sh));
             __syncthreads();
             bits = sb;
         }
         // initialisation: codes of every cell, start state in ya
-        const int n0 = count_start(t, bits, reinterpret_cast<int*>(misc + 1));
+        const int n0 = count_start(sh, bits, tl.misc + 1);
         const float x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
-        if (threadIdx.x == 0) misc[0] = 0;
+        uint32_t f = 0;
+        for (int ub = 0; ub < sh.U; ub += E)
+            for (int k = 0; k < sh.ntile; ++k) f |= walk_init(sh, load_tile(sh, k), tl.rcp, bits, code, ya, ub, ub + E, x0);
         __syncthreads();
-        for (int u0 = 0; u0 < t.U; u0 += D) {
-            const uint32_t fl = init_chunk<D>(t, m, bits, code, ya, u0, x0);
-            if (fl) atomicOr(&misc[0], fl);
-        }
+        if (threadIdx.x == 0) tl.misc[0] = 0;
         __syncthreads();
-        uint32_t f = misc[0];
+        if (f) atomicOr(&tl.misc[0], f);
+        __syncthreads();
+        f = tl.misc[0];
         int32_t perc = -1, steps = 0, mm = 0, front = 0;
         if (!(f & F_NONEMPTY)) { perc = 0; steps = 0; }
         else if (f & F_FAR) { perc = 1; steps = 1; }
         while (perc < 0) {
             const float* yin = (mm & 1) ? yb : ya;
             float* yout = (mm & 1) ? ya : yb;
+            const int ulim = min(sh.U, front + 2);
+            uint32_t fl = 0;
+            for (int ub = 0; ub < ulim; ub += E)
+                for (int k = 0; k < sh.ntile; ++k)
+                    fl |= walk_step(sh, load_tile(sh, k), tl.rcp, yin, yout, code, ub, ub + E, front);
             __syncthreads();
-            if (threadIdx.x == 0) misc[0] = 0;
-            const int ulim = min(t.U, front + 2);
-            for (int u0 = 0; u0 < ulim; u0 += D) {
-                __syncthreads();
-                stage_chunk<D>(t, m, yin, code, u0, front);
-                __syncthreads();
-                const uint32_t fl = step_chunk<D>(t, m, yout, u0, front);
-                if (fl) atomicOr(&misc[0], fl);
-            }
+            if (threadIdx.x == 0) tl.misc[0] = 0;
             __syncthreads();
-            f = misc[0];
+            if (fl) atomicOr(&tl.misc[0], fl);
+            __syncthreads();
+            f = tl.misc[0];
             mm += 1;
             if (f & F_FRONT) front += 1;
             if (f & F_FAR) { perc = 1; steps = mm + 1; }
             else if (!(f & F_GREW)) { perc = 0; steps = mm; }
-            else if (mm >= a.cap) { perc = 0; steps = mm; if (threadIdx.x == 0) atomicOr(a.err, 1u); }
+            else if (mm > sh.N) { perc = 0; steps = mm; if (threadIdx.x == 0) atomicOr(a.err, 1u); }
         }
         if (threadIdx.x == 0) {
-            a.out.perc[cfg] = (uint8_t)perc;
-            a.out.steps[cfg] = steps;
+            a.out.perc[j] = (uint8_t)perc;
+            a.out.steps[j] = steps;
+            if (a.out.group_count && job.group >= 0 && perc == 1) atomicAdd(&a.out.group_count[job.group], 1ull);
         }
         if (a.out.hit) {
             float h = 0.0f;
             if (perc == 1) {
-                __syncthreads();
-                far_sum(t, ((steps - 1) & 1) ? yb : ya, front, part, misc + 4, reinterpret_cast<float*>(misc + 5));
-                h = __uint_as_float(misc[5]);
+                far_sum(sh, ((steps - 1) & 1) ? yb : ya, front, tl.part, tl.misc + 4,
+                        reinterpret_cast<float*>(tl.misc + 5));
+                h = __uint_as_float(tl.misc[5]);
             }
-            if (threadIdx.x == 0) a.out.hit[cfg] = h;
+            if (threadIdx.x == 0) a.out.hit[j] = h;
         }
     }
 }
 
 // Test hook support: far-end sum added to the detector mass, reach of the detector.
-__global__ void __launch_bounds__(256) k_far_acc(DevTables t, const float* y, float* det_mass,
+__global__ void __launch_bounds__(256) k_far_acc(DevShape sh, const float* y, float* det_mass,
                                                  uint32_t* det_reached) {
     __shared__ float part[256];
     __shared__ uint32_t reached;
     __shared__ float result;
-    far_sum(t, y, t.U, part, &reached, &result);
+    far_sum(sh, y, sh.U, part, &reached, &result);
     if (threadIdx.x == 0) {
         *det_mass = *det_mass + result;
         if (reached) *det_reached = 1u;
     }
 }
 
-__global__ void __launch_bounds__(256) k_export(DevTables t, const float* __restrict__ y,
+// x = |y| deg and the reach bit of every tube, scattered to canonical order.
+__global__ void __launch_bounds__(256) k_export(DevShape sh, const float* __restrict__ y,
                                                 const uint8_t* __restrict__ code, const float* det_mass,
                                                 const uint32_t* det_reached, float* __restrict__ x_out,
                                                 uint8_t* __restrict__ reach_out) {
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s <= t.N;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        if (s == t.N) {
-            x_out[s] = *det_mass;
-            reach_out[s] = (uint8_t)(*det_reached ? 1 : 0);
+    const int64_t total = (int64_t)sh.U * sh.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i == total) {
+            x_out[sh.N] = *det_mass;
+            reach_out[sh.N] = (uint8_t)(*det_reached ? 1 : 0);
             continue;
         }
-        const int64_t u = s / t.C, c = s - u * t.C;
-        const int64_t g = u * t.CP + c;
+        const int64_t u = i / sh.C, c = i - u * sh.C;
+        const int64_t s = u * sh.C + sh.rank[c];
+        if (s >= sh.N) continue;
+        const uint32_t g = word_of(sh, (int)u, (int)c);
         const uint32_t w = __float_as_uint(y[g]);
         const uint32_t cd = code[g];
         float x = 0.0f;
@@ -632,22 +902,6 @@ __global__ void __launch_bounds__(256) k_count(const uint8_t* __restrict__ perc,
     if (threadIdx.x == 0 && red) atomicAdd(count, red);
 }
 
-// ------------------------------------------------------------------------------
-// Depth dispatch
-// ------------------------------------------------------------------------------
-template <template <int> class F, typename... Args>
-hipError_t dispatch_depth(int depth, Args&&... args) {
-    switch (depth) {
-        case 1: return F<1>::run(args...);
-        case 3: return F<3>::run(args...);
-        case 5: return F<5>::run(args...);
-        case 7: return F<7>::run(args...);
-        case 9: return F<9>::run(args...);
-        case 15: return F<15>::run(args...);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 constexpr size_t kDynLds = 160 * 1024;  // dynamic LDS limit set once per device
 
 template <typename K>
@@ -656,92 +910,23 @@ hipError_t allow_lds(K kernel) {
                                (int)kDynLds);
 }
 
-template <int D>
-struct PrepDepth {
-    static hipError_t run() {
-        hipError_t e = allow_lds(k_span_init<D>);
-        if (e == hipSuccess) e = allow_lds(k_span_step<D>);
-        if (e == hipSuccess) e = allow_lds(k_chunk_step<D>);
-        if (e == hipSuccess) e = allow_lds(k_persist<D>);
-        return e;
-    }
-};
-
-template <int D>
-struct ResidentPersist {
-    static hipError_t run(int block, int C, int* out) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_persist<D>, block, lds_map(C, D).total);
-    }
-};
-
-template <int D>
-struct RunSpanInit {
-    static hipError_t run(const SpanArgs& a, hipStream_t s) {
-        const size_t lds = lds_map(a.t.C, D).total;
-        const int64_t nchunk = (a.t.U + D - 1) / D;
-        const int64_t items = (int64_t)a.n_slot * nchunk;
-        const int grid = (int)std::min<int64_t>(items, 65536);
-        if (grid <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k_span_init<D>, dim3(grid), dim3(a.block), lds, s, a);
-        return hipGetLastError();
-    }
-};
-
-template <int D>
-struct RunSpanStep {
-    static hipError_t run(const SpanArgs& a, hipStream_t s) {
-        const size_t lds = lds_map(a.t.C, D).total;
-        hipLaunchKernelGGL(k_span_step<D>, dim3(a.grid), dim3(a.block), lds, s, a);
-        return hipGetLastError();
-    }
-};
-
-template <int D>
-struct RunChunkStep {
-    static hipError_t run(const DevTables& t, const float* yin, float* yout, const uint8_t* code, int front,
-                          int block, hipStream_t s) {
-        const size_t lds = lds_map(t.C, D).total;
-        const int grid = (t.U + D - 1) / D;
-        hipLaunchKernelGGL(k_chunk_step<D>, dim3(grid), dim3(block), lds, s, t, yin, yout, code, front);
-        return hipGetLastError();
-    }
-};
-
-template <int D>
-struct RunPersist {
-    static hipError_t run(const PersistArgs& a, hipStream_t s) {
-        const size_t lds = lds_map(a.t.C, D).total;
-        hipLaunchKernelGGL(k_persist<D>, dim3(a.grid), dim3(a.block), lds, s, a);
-        return hipGetLastError();
-    }
-};
-
 }  // namespace
-
-size_t lds_bytes_for(int32_t C, int32_t depth) { return lds_map(C, depth).total; }
-
-int32_t max_depth_for(int32_t C) {
-    int32_t best = 0;
-    for (int32_t d : kDepthList)
-        if (lds_bytes_for(C, d) <= kDynLds) best = d;
-    return best;
-}
 
 hipError_t prepare_kernels(int device) {
     int cur = 0;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return e;
     if (cur != device) return hipErrorInvalidDevice;
-    for (int d : kDepthList) {
-        e = dispatch_depth<PrepDepth>(d);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    e = allow_lds(k_span_init);
+    if (e == hipSuccess) e = allow_lds(k_span_step);
+    if (e == hipSuccess) e = allow_lds(k_chunk_step);
+    if (e == hipSuccess) e = allow_lds(k_persist);
+    return e;
 }
 
-int persist_resident_per_cu(int depth, int block, int C) {
+int persist_resident_per_cu(int block, int lds_bytes) {
     int n = 0;
-    if (dispatch_depth<ResidentPersist>(depth, block, C, &n) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persist, block, lds_bytes) != hipSuccess) return 1;
     return n;
 }
 
@@ -752,28 +937,44 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sample(const DevTables& t, uint32_t* bits, int64_t n_cfg, uint64_t cfg0, uint64_t threshold,
-                         uint64_t seed, uint32_t tag, hipStream_t s) {
-    const int64_t total = n_cfg * t.words;
+hipError_t launch_sample(const DevShape& sh, uint32_t* bits, int64_t n_cfg, uint64_t cfg0, uint64_t threshold,
+                         uint64_t seed, hipStream_t s) {
+    const int64_t total = n_cfg * sh.words;
     if (total <= 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_sample, dim3(grid), dim3(256), 0, s, bits, t.words, t.N, n_cfg, cfg0, threshold,
+    const uint32_t tag = ((uint32_t)sh.W << 16) | (uint32_t)sh.L;
+    hipLaunchKernelGGL(k_sample, dim3(grid), dim3(256), 0, s, bits, sh.words, sh.N, n_cfg, cfg0, threshold,
                        (uint32_t)seed, (uint32_t)(seed >> 32), tag);
     return hipGetLastError();
 }
 
+hipError_t launch_sample_slots(const DevShape* shapes, const Job* jobs, int32_t n_slot, uint32_t* const* slot_bits,
+                               hipStream_t s) {
+    if (n_slot <= 0) return hipSuccess;
+    const int grid = std::min(n_slot, 65536);
+    hipLaunchKernelGGL(k_sample_slots, dim3(grid), dim3(256), 0, s, shapes, jobs, n_slot, slot_bits);
+    return hipGetLastError();
+}
+
 hipError_t launch_span_init_only(const SpanArgs& a, hipStream_t s) {
-    return dispatch_depth<RunSpanInit>(a.depth, a, s);
+    hipLaunchKernelGGL(k_span_layout, dim3(1), dim3(kMaxBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_span_init, dim3(a.grid), dim3(a.block), a.lds, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_span_init(const SpanArgs& a, hipStream_t s) {
-    hipError_t e = dispatch_depth<RunSpanInit>(a.depth, a, s);
+    hipError_t e = launch_span_init_only(a, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_span_plan, dim3(1), dim3(kMaxBlock), 0, s, a, 0, 1);
     return hipGetLastError();
 }
 
-hipError_t launch_span_step(const SpanArgs& a, hipStream_t s) { return dispatch_depth<RunSpanStep>(a.depth, a, s); }
+hipError_t launch_span_step(const SpanArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_span_step, dim3(a.grid), dim3(a.block), a.lds, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_span_plan(const SpanArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_span_plan, dim3(1), dim3(kMaxBlock), 0, s, a, 1, 0);
@@ -781,30 +982,36 @@ hipError_t launch_span_plan(const SpanArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_span_finish(const SpanArgs& a, hipStream_t s) {
-    if (!a.out.hit) return hipSuccess;
+    if (!a.out.hit && !a.out.group_count) return hipSuccess;
     const int grid = std::min(a.n_slot, 4096);
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_span_finish, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_step(const DevTables& t, const float* yin, float* yout, const uint8_t* code, int front,
-                             int depth, int block, hipStream_t s) {
-    return dispatch_depth<RunChunkStep>(depth, t, yin, yout, code, front, block, s);
-}
-
-hipError_t launch_persist(const PersistArgs& a, hipStream_t s) { return dispatch_depth<RunPersist>(a.depth, a, s); }
-
-hipError_t launch_far_sum(const DevTables& t, const float* y, float* det_mass, uint32_t* det_reached,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_far_acc, dim3(1), dim3(256), 0, s, t, y, det_mass, det_reached);
+hipError_t launch_chunk_step(const DevShape& sh, const float* yin, float* yout, const uint8_t* code, int depth,
+                             int block, hipStream_t s) {
+    const int lds = (int)lds_total(sh.span_max);
+    const int grid = ((sh.U + depth - 1) / depth) * sh.ntile;
+    hipLaunchKernelGGL(k_chunk_step, dim3(grid), dim3(block), lds, s, sh, yin, yout, code, depth, lds);
     return hipGetLastError();
 }
 
-hipError_t launch_export(const DevTables& t, const float* y, const uint8_t* code, const float* det_mass,
+hipError_t launch_persist(const PersistArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_persist, dim3(a.grid), dim3(a.block), a.lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_far_sum(const DevShape& sh, const float* y, float* det_mass, uint32_t* det_reached,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_far_acc, dim3(1), dim3(256), 0, s, sh, y, det_mass, det_reached);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const DevShape& sh, const float* y, const uint8_t* code, const float* det_mass,
                          const uint32_t* det_reached, float* x_out, uint8_t* reach_out, hipStream_t s) {
-    const int grid = (int)std::min<int64_t>((t.N + 1 + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_export, dim3(grid), dim3(256), 0, s, t, y, code, det_mass, det_reached, x_out, reach_out);
+    const int grid = (int)std::min<int64_t>(((int64_t)sh.U * sh.C + 1 + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_export, dim3(grid), dim3(256), 0, s, sh, y, code, det_mass, det_reached, x_out, reach_out);
     return hipGetLastError();
 }
 

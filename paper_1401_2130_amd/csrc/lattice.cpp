@@ -30,31 +30,34 @@ bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
     if (L < 1 || L > (1 << 22)) { err = "L must be in [1, 4194304]"; return false; }
     d = LatticeDesc{};
     d.W = W; d.L = L;
-    struct Col { int sig, q, r; };
-    std::vector<Col> cols;
+    // internal column order: (q, r) lexicographic, so that every contact of a column
+    // lies within two q-rows of it
     for (int q = -W; q <= W; ++q)
         for (int r = -W; r <= W; ++r)
-            if (hexdist(q, r) <= W) cols.push_back({mod3(q - r), q, r});
-    std::sort(cols.begin(), cols.end(), [](const Col& a, const Col& b) {
-        if (a.sig != b.sig) return a.sig < b.sig;
-        if (a.q != b.q) return a.q < b.q;
-        return a.r < b.r;
-    });
-    const int C = (int)cols.size();
+            if (hexdist(q, r) <= W) { d.q.push_back(q); d.r.push_back(r); d.sig.push_back(mod3(q - r)); }
+    const int C = (int)d.q.size();
     d.C = C;
     d.U = (L + 2) / 3;
-    d.CP = ((C + 1 + 31) / 32) * 32;
-    d.q.resize(C); d.r.resize(C); d.sig.resize(C); d.top.resize(C);
-    const int S = 2 * W + 1;
-    std::vector<int32_t> index((size_t)S * S, -1);
+    d.CP = std::max(32, ((C + 31) / 32) * 32);
+    // canonical rank: (sigma, q, r) order inside a cell = lexicographic (k, q, r) overall
+    std::vector<int32_t> by_canon(C);
+    for (int c = 0; c < C; ++c) by_canon[c] = c;
+    std::stable_sort(by_canon.begin(), by_canon.end(), [&](int a, int b) {
+        if (d.sig[a] != d.sig[b]) return d.sig[a] < d.sig[b];
+        if (d.q[a] != d.q[b]) return d.q[a] < d.q[b];
+        return d.r[a] < d.r[b];
+    });
+    d.rank.assign(C, 0);
+    d.by_rank = by_canon;
+    for (int k = 0; k < C; ++k) d.rank[by_canon[k]] = k;
+    d.top.resize(C);
     for (int c = 0; c < C; ++c) {
-        d.q[c] = cols[c].q; d.r[c] = cols[c].r; d.sig[c] = cols[c].sig;
-        d.nsig[cols[c].sig]++;
-        index[(size_t)(cols[c].q + W) * S + (cols[c].r + W)] = c;
+        d.nsig[d.sig[c]]++;
         // far-end tube: the highest layer k < L with k = sig (mod 3)
-        d.top[c] = cols[c].sig < L ? (L - 1 - cols[c].sig) / 3 : -1;
+        d.top[c] = d.sig[c] < L ? (L - 1 - d.sig[c]) / 3 : -1;
     }
-    // sites: every column of every full cell, then the prefix of the last cell
+    // sites: every column of every full cell, then the columns of the last cell whose
+    // layer exists (a prefix in canonical rank)
     int64_t n = (int64_t)(d.U - 1) * C;
     const int k_last = 3 * (d.U - 1);
     for (int c = 0; c < C; ++c)
@@ -62,13 +65,18 @@ bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
     d.N = n;
     d.words = (n + 31) / 32;
     if (n > (int64_t)INT32_MAX) { err = "lattice exceeds 2^31 - 1 sites"; return false; }
+    // state arrays are indexed with 32-bit offsets inside one configuration
+    if (state_words(d) > (int64_t)INT32_MAX) { err = "lattice state exceeds 2^31 - 1 words"; return false; }
+    const int S = 2 * W + 1;
+    std::vector<int32_t> index((size_t)S * S, -1);
+    for (int c = 0; c < C; ++c) index[(size_t)(d.q[c] + W) * S + (d.r[c] + W)] = c;
     d.nb.assign((size_t)kSide * C, 0);
     for (int c = 0; c < C; ++c) {
         for (int i = 0; i < kSide; ++i) {
             const int q2 = d.q[c] + kSideOff[i][0], r2 = d.r[c] + kSideOff[i][1];
             const int s2 = d.sig[c] + kSideOff[i][2];  // in -1..3
             const int dcell = s2 < 0 ? -1 : (s2 > 2 ? 1 : 0);
-            int col = C, dc = 0;  // outside the hexagon: the zero pad column
+            int col = C, dc = 0;  // outside the hexagon: no tube
             if (hexdist(q2, r2) <= W) {
                 col = index[(size_t)(q2 + W) * S + (r2 + W)];
                 dc = dcell;
@@ -76,16 +84,43 @@ bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
             d.nb[(size_t)i * C + c] = (col << 2) | (dc + 1);
         }
     }
+    // column tiles of about kTileCols columns, each with the range of columns its
+    // contacts reach (the halo)
+    const int nt = std::max(1, (C + kTileCols - 1) / kTileCols);
+    d.ntile = nt;
+    d.tile.assign((size_t)nt * 4, 0);
+    d.span_max = 0;
+    d.tile_max = 0;
+    for (int k = 0; k < nt; ++k) {
+        const int ts = (int)((int64_t)C * k / nt), te = (int)((int64_t)C * (k + 1) / nt);
+        int hs = ts, he = te;
+        for (int c = ts; c < te; ++c)
+            for (int i = 0; i < kSide; ++i) {
+                const int col = d.nb[(size_t)i * C + c] >> 2;
+                if (col < C) { hs = std::min(hs, col); he = std::max(he, col + 1); }
+            }
+        d.tile[(size_t)k * 4 + 0] = ts; d.tile[(size_t)k * 4 + 1] = te;
+        d.tile[(size_t)k * 4 + 2] = hs; d.tile[(size_t)k * 4 + 3] = he;
+        d.span_max = std::max(d.span_max, he - hs);
+        d.tile_max = std::max(d.tile_max, te - ts);
+    }
     return true;
 }
 
-std::vector<uint32_t> contact_table(const LatticeDesc& d, int32_t depth) {
-    const uint32_t SJ = (uint32_t)depth + 2u;
+std::vector<uint32_t> contact_table(const LatticeDesc& d) {
     std::vector<uint32_t> t((size_t)kSide * d.C);
-    for (size_t e = 0; e < t.size(); ++e) {
-        const int32_t v = d.nb[e];
-        const uint32_t col = (uint32_t)(v >> 2), dcp1 = (uint32_t)(v & 3);  // dcell + 1
-        t[e] = (col * SJ + dcp1) * 4u;
+    for (int k = 0; k < d.ntile; ++k) {
+        const int ts = d.tile[k * 4 + 0], te = d.tile[k * 4 + 1];
+        const int hs = d.tile[k * 4 + 2];
+        for (int c = ts; c < te; ++c)
+            for (int i = 0; i < kSide; ++i) {
+                const int32_t v = d.nb[(size_t)i * d.C + c];
+                const int32_t col = v >> 2, dcp1 = v & 3;  // dcell + 1
+                // LDS column of the contact: 1 + its place in the staged range, or the
+                // zero pad column 0 for a missing contact
+                const int32_t lcol = col < d.C ? col - hs + 1 : 0;
+                t[(size_t)i * d.C + c] = (uint32_t)(lcol * kRing + dcp1);
+            }
     }
     return t;
 }

@@ -1,6 +1,7 @@
 // C ABI (include/perc.h) and the host runtime behind it: lattice handles with
-// per-device tables, stream-ordered work memory, the three execution forms and the
-// test hook. Every step of the inspection runs in the HIP kernels of kernels.hip.
+// per-device tables, stream-ordered work memory, the job batches of the three
+// execution forms, the tuning cache and the test hook. Every step of the inspection
+// runs in the HIP kernels of kernels.hip.
 #include "perc.h"
 
 #include <hip/hip_runtime_api.h>
@@ -8,8 +9,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "perc_internal.hpp"
@@ -36,17 +39,19 @@ int hip_fail(hipError_t e, const char* what) {
     return PERC_EHIP;
 }
 
-#define HIP_TRY(expr)                                         \
-    do {                                                      \
-        hipError_t e_ = (expr);                               \
-        if (e_ != hipSuccess) return hip_fail(e_, #expr);     \
+#define HIP_TRY(expr)                                     \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
     } while (0)
 
-#define PERC_TRY(expr)                 \
-    do {                               \
-        int rc_ = (expr);              \
+#define PERC_TRY(expr)                  \
+    do {                                \
+        int rc_ = (expr);               \
         if (rc_ != PERC_OK) return rc_; \
     } while (0)
+
+constexpr size_t kMaxLds = 160 * 1024;
 
 // ---------------------------------------------------------------------------------
 // Per-device lattice tables and one-time kernel preparation.
@@ -62,10 +67,15 @@ int prepare(int dev) {
     return PERC_OK;
 }
 
-int tables_for(const perc_lattice* lat_c, int32_t depth, DevTables& t) {
+template <typename T>
+int upload(T** dst, const std::vector<T>& src) {
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(dst), sizeof(T) * std::max<size_t>(src.size(), 1)));
+    if (!src.empty()) HIP_TRY(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return PERC_OK;
+}
+
+int shape_for(const perc_lattice* lat_c, DevShape& sh) {
     perc_lattice* lat = const_cast<perc_lattice*>(lat_c);
-    const int di = depth_index(depth);
-    if (di < 0) return fail(PERC_EINVAL, "unsupported chunk depth");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     PERC_TRY(prepare(dev));
@@ -77,21 +87,20 @@ int tables_for(const perc_lattice* lat_c, int32_t depth, DevTables& t) {
     if (!ld) {
         LatticeDevice n;
         n.device = dev;
-        const size_t tb = sizeof(uint32_t) * (size_t)kSide * std::max(d.C, 1);
-        for (int i = 0; i < kNumDepths; ++i) {
-            const std::vector<uint32_t> tab = contact_table(d, kDepthList[i]);
-            HIP_TRY(hipMalloc(&n.nboff[i], tb));
-            HIP_TRY(hipMemcpy(n.nboff[i], tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice));
-        }
-        HIP_TRY(hipMalloc(&n.top, sizeof(int32_t) * (size_t)std::max(d.C, 1)));
-        HIP_TRY(hipMemcpy(n.top, d.top.data(), sizeof(int32_t) * d.top.size(), hipMemcpyHostToDevice));
+        PERC_TRY(upload(&n.nboff, contact_table(d)));
+        PERC_TRY(upload(&n.tile, d.tile));
+        PERC_TRY(upload(&n.rank, d.rank));
+        PERC_TRY(upload(&n.top, d.top));
         lat->dev.push_back(n);
         ld = &lat->dev.back();
     }
-    t.nboff = ld->nboff[di];
-    t.top = ld->top;
-    t.C = d.C; t.CP = d.CP; t.U = d.U; t.L = d.L;
-    t.N = d.N; t.words = d.words;
+    sh.nboff = ld->nboff;
+    sh.tile = ld->tile;
+    sh.rank = ld->rank;
+    sh.top = ld->top;
+    sh.C = d.C; sh.CP = d.CP; sh.U = d.U; sh.L = d.L;
+    sh.ntile = d.ntile; sh.span_max = d.span_max; sh.tile_max = d.tile_max; sh.W = d.W;
+    sh.N = d.N; sh.words = d.words;
     return PERC_OK;
 }
 
@@ -112,8 +121,8 @@ struct Arena {
         hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base), size, s);
         if (e != hipSuccess) {
             base = nullptr;
-            return fail(PERC_ENOMEM, std::string("work memory of ") + std::to_string(size) +
-                                         " bytes: " + hipGetErrorString(e));
+            return fail(PERC_ENOMEM, std::string("work memory of ") + std::to_string(size) + " bytes: " +
+                                         hipGetErrorString(e));
         }
         return PERC_OK;
     }
@@ -137,8 +146,9 @@ thread_local PinnedHdr g_pinned;
 
 // ---------------------------------------------------------------------------------
 // Optional profiling of the span/plain step kernel: HIP events on the launching
-// stream around every step launch (graphs are not used while it is on) and the tube
-// slots the steps processed (cells scheduled by the planner times the columns).
+// stream around every step launch (graphs are not used while it is on: HIP reports no
+// elapsed time for events recorded as graph nodes) and the tube slots the steps
+// processed (counted by the planner).
 // ---------------------------------------------------------------------------------
 struct Profiler {
     std::mutex mu;
@@ -173,8 +183,7 @@ class StepTimer {
         if (e == hipSuccess) e = hipEventRecord(ev.second, s);
         return e;
     }
-    // After the stream has been synchronised: add the durations of the launches since
-    // the last call.
+    // after the stream has been synchronised: add the durations since the last call
     hipError_t collect() {
         if (!on_) return hipSuccess;
         double ms = 0.0;
@@ -205,20 +214,52 @@ class StepTimer {
 };
 
 // ---------------------------------------------------------------------------------
-// Tuning: explicit options, else cached autotune results, else shape rules.
+// Tuning: explicit options, else the autotune cache, else shape rules.
 // ---------------------------------------------------------------------------------
-bool valid_depth(int32_t d) { return depth_index(d) >= 0; }
+struct TuneKey {
+    int32_t W, L, bucket;
+    bool operator<(const TuneKey& o) const { return std::tie(W, L, bucket) < std::tie(o.W, o.L, o.bucket); }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuning> g_tune;
 
-int32_t depth_within(int32_t C, size_t lds_budget, int32_t cap) {
-    int32_t best = 0;
-    for (int32_t d : kDepthList)
-        if (d <= cap && lds_bytes_for(C, d) <= lds_budget) best = d;
-    return best;
+int32_t size_bucket(int64_t n) {
+    int32_t b = 0;
+    while (n > 1 && b < 40) { n >>= 1; ++b; }
+    return b;
 }
 
-int64_t state_bytes(const LatticeDesc& d) { return (int64_t)d.U * d.CP * 9; }
+struct ShapeNeed {
+    int32_t span_max = 0, tile_max = 0, C = 0;
+    int64_t items = 0;  // column tiles x cells of the largest shape
+};
 
-int resolve(const LatticeDesc& d, int64_t n_cfg, const perc_options* opt, Tuning& tu) {
+// Threads per workgroup for these shapes: one per column of the widest tile, and the
+// staged halo range must fit two columns per thread.
+int32_t block_for(const ShapeNeed& nd) {
+    const int32_t b = std::max<int32_t>(64, ((nd.tile_max + 63) / 64) * 64);
+    return std::max<int32_t>(b, ((nd.span_max + 2 * 64 - 1) / (2 * 64)) * 64);
+}
+
+// Default cells walked per work item (a multiple of 8): long walks amortise the
+// staged groups of the prologue; a single configuration needs short ones to give
+// every CU work.
+int32_t cells_for(const ShapeNeed& nd, int32_t form) {
+    if (form == FORM_PLAIN) return (int32_t)(std::max<int64_t>(1, std::min<int64_t>(4, nd.items / 8192)) * 8);
+    return 64;
+}
+
+int check_walk(const ShapeNeed& nd, int32_t block) {
+    if (block < nd.tile_max)
+        return fail(PERC_EINVAL, "block must be at least the widest column tile (" + std::to_string(nd.tile_max) + ")");
+    if (nd.span_max > 2 * block || lds_total(nd.span_max) > kMaxLds)
+        return fail(PERC_EINVAL, "the fiber cross-section is too wide for one workgroup tile (halo range " +
+                                     std::to_string(nd.span_max) + " columns)");
+    return PERC_OK;
+}
+
+int resolve(const ShapeNeed& nd, int64_t state_words, int64_t n_jobs, const perc_options* opt, Tuning& tu,
+            const TuneKey* key) {
     tu = Tuning{};
     if (opt) {
         tu.form = opt->form;
@@ -228,28 +269,28 @@ int resolve(const LatticeDesc& d, int64_t n_cfg, const perc_options* opt, Tuning
         tu.graph_steps = opt->graph_steps;
     }
     if (tu.form < FORM_AUTO || tu.form > FORM_PERSIST) return fail(PERC_EINVAL, "unknown execution form");
+    if (tu.form == FORM_AUTO && key) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(*key);
+        if (it != g_tune.end()) {
+            const Tuning c = it->second;
+            tu.form = c.form;
+            if (!tu.depth) tu.depth = c.depth;
+            if (!tu.block) tu.block = c.block;
+            if (!tu.grid) tu.grid = c.grid;
+        }
+    }
     if (tu.form == FORM_AUTO) {
-        // many configurations of modest size: one workgroup each; otherwise spread
-        tu.form = (n_cfg >= 1024 && state_bytes(d) <= (64ll << 20)) ? FORM_PERSIST : FORM_SPAN;
+        // many configurations of modest size: one workgroup each; else spread
+        tu.form = (n_jobs >= 2048 && state_words * 9 <= (64ll << 20)) ? FORM_PERSIST : FORM_SPAN;
     }
-    const size_t kMaxLds = 160 * 1024;
-    if (tu.depth == 0) {
-        // plain: one configuration, as many workgroups per step as possible; span: the
-        // deepest chunk that fits (measured best on W=32); persistent: two per CU
-        if (tu.form == FORM_PLAIN) tu.depth = depth_within(d.C, kMaxLds, 1);
-        else if (tu.form == FORM_SPAN) tu.depth = depth_within(d.C, kMaxLds, 15);
-        else tu.depth = depth_within(d.C, 80 * 1024, 15);
-        if (tu.depth == 0) tu.depth = depth_within(d.C, kMaxLds, 15);
-    }
-    if (!valid_depth(tu.depth)) return fail(PERC_EINVAL, "depth must be one of 1, 3, 5, 7, 9, 15");
-    if (lds_bytes_for(d.C, tu.depth) > kMaxLds)
-        return fail(PERC_EINVAL, "chunk of " + std::to_string(tu.depth) + " cells of " + std::to_string(d.C) +
-                                     " columns exceeds the LDS of one workgroup");
-    if (tu.block == 0) {
-        const int32_t want = tu.form == FORM_PLAIN ? 512 : 1024;
-        tu.block = std::max<int32_t>(64, std::min<int32_t>(want, ((d.C + 63) / 64) * 64));
-    }
-    if (tu.block < 64 || tu.block > 1024 || tu.block % 64) return fail(PERC_EINVAL, "block must be 64..1024, multiple of 64");
+    if (tu.depth == 0) tu.depth = cells_for(nd, tu.form);
+    if (tu.depth < 1 || tu.depth > (1 << 20)) return fail(PERC_EINVAL, "depth (cells per work item) must be 1..2^20");
+    tu.depth = (tu.depth + 7) & ~7;  // items are whole pairs of cell groups
+    if (tu.block == 0) tu.block = block_for(nd);
+    if (tu.block < 64 || tu.block > 1024 || tu.block % 64)
+        return fail(PERC_EINVAL, "block must be 64..1024, a multiple of 64");
+    PERC_TRY(check_walk(nd, tu.block));
     if (tu.graph_steps == 0) tu.graph_steps = 8;
     if (tu.graph_steps < 1 || tu.graph_steps > 256) return fail(PERC_EINVAL, "graph_steps must be 1..256");
     if (tu.grid < 0) return fail(PERC_EINVAL, "grid must be >= 0");
@@ -257,8 +298,56 @@ int resolve(const LatticeDesc& d, int64_t n_cfg, const perc_options* opt, Tuning
 }
 
 // ---------------------------------------------------------------------------------
-// Span and plain forms.
+// Jobs: one configuration each (a lattice shape, and caller bits or a Philox draw).
 // ---------------------------------------------------------------------------------
+struct HostJob {
+    const perc_lattice* lat;
+    const uint32_t* bits;
+    uint64_t seed, cfg, thr;
+    int32_t group;
+};
+
+uint64_t threshold_of(double p) {
+    if (p >= 1.0) return (uint64_t)1 << 32;
+    return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+struct Shapes {
+    std::vector<const perc_lattice*> lats;
+    std::vector<DevShape> dev;
+    std::vector<int32_t> of_job;
+    ShapeNeed need;
+    int64_t max_state = 0, max_words = 0;
+};
+
+void collect_shapes(const std::vector<HostJob>& jobs, Shapes& S) {
+    std::map<const perc_lattice*, int32_t> idx;
+    S.of_job.resize(jobs.size());
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        auto it = idx.find(jobs[j].lat);
+        if (it == idx.end()) {
+            it = idx.emplace(jobs[j].lat, (int32_t)S.lats.size()).first;
+            S.lats.push_back(jobs[j].lat);
+        }
+        S.of_job[j] = it->second;
+    }
+    for (const perc_lattice* l : S.lats) {
+        const LatticeDesc& d = l->d;
+        S.need.span_max = std::max(S.need.span_max, d.span_max);
+        S.need.tile_max = std::max(S.need.tile_max, d.tile_max);
+        S.need.C = std::max(S.need.C, d.C);
+        S.need.items = std::max<int64_t>(S.need.items, (int64_t)d.U * d.ntile);
+        S.max_state = std::max<int64_t>(S.max_state, state_words(d));
+        S.max_words = std::max<int64_t>(S.max_words, d.words);
+    }
+}
+
+int device_shapes(Shapes& S) {
+    S.dev.resize(S.lats.size());
+    for (size_t i = 0; i < S.lats.size(); ++i) PERC_TRY(shape_for(S.lats[i], S.dev[i]));
+    return PERC_OK;
+}
+
 bool stream_capturing(hipStream_t s) {
     if (!s) return false;
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -266,53 +355,104 @@ bool stream_capturing(hipStream_t s) {
     return st != hipStreamCaptureStatusNone;
 }
 
-int run_span(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int64_t n_cfg, BatchOut out,
-             const Tuning& tu, hipStream_t s) {
-    if (n_cfg == 0) return PERC_OK;
+int64_t slot_words(const LatticeDesc& d) { return (state_words(d) + 63) & ~(int64_t)63; }
+int64_t bits_words(const LatticeDesc& d) { return (d.words + 63) & ~(int64_t)63; }
+
+// Span and plain forms: waves of slots sized to the memory budget.
+int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, const Tuning& tu, hipStream_t s) {
+    const int64_t n = (int64_t)jobs.size();
+    if (n == 0) return PERC_OK;
     if (stream_capturing(s)) return fail(PERC_EINVAL, "the span and plain forms synchronise; not capturable");
     const bool plain = tu.form == FORM_PLAIN;
-    const int64_t cell_words = (int64_t)t.U * t.CP;
-    const int64_t per_cfg = cell_words * 9 + 64;
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    const int64_t budget = std::max<int64_t>(per_cfg, std::min<int64_t>((int64_t)(free_b / 2), 48ll << 30));
-    int64_t n_slot = plain ? 1 : std::min<int64_t>(n_cfg, std::max<int64_t>(1, budget / per_cfg));
-    n_slot = std::min<int64_t>(n_slot, 1 << 20);
-    Arena ar;
-    const size_t bytes = Arena::align(sizeof(float) * n_slot * cell_words) * 2 +
-                         Arena::align((size_t)n_slot * cell_words) + Arena::align(sizeof(CfgState) * n_slot) +
-                         Arena::align(sizeof(int32_t) * n_slot) * 2 + Arena::align(sizeof(int64_t) * (n_slot + 1)) +
-                         Arena::align(64);
-    PERC_TRY(ar.reserve(bytes, s));
-    SpanArgs a{};
-    a.t = t;
-    a.ya = ar.take<float>(n_slot * cell_words);
-    a.yb = ar.take<float>(n_slot * cell_words);
-    a.code = ar.take<uint8_t>(n_slot * cell_words);
-    a.st = ar.take<CfgState>(n_slot);
-    a.active = ar.take<int32_t>(n_slot);
-    a.active2 = ar.take<int32_t>(n_slot);
-    a.chunk_off = ar.take<int64_t>(n_slot + 1);
-    a.hdr = ar.take<int32_t>(16);
-    a.depth = tu.depth;
-    a.block = tu.block;
-    a.grid = tu.grid ? tu.grid : 2048;
-    a.cap = d.N + 1;
+    const int64_t budget = std::min<int64_t>((int64_t)(free_b / 2), 48ll << 30);
     if (!g_pinned.h) return fail(PERC_ENOMEM, "pinned host buffer");
     int32_t* h = g_pinned.h;
-    a.work = reinterpret_cast<unsigned long long*>(a.hdr + 8);
+    const int lds = (int)lds_total(S.need.span_max);
+    Arena shape_ar;
+    PERC_TRY(shape_ar.reserve(sizeof(DevShape) * S.dev.size(), s));
+    DevShape* d_shapes = shape_ar.take<DevShape>(S.dev.size());
+    HIP_TRY(hipMemcpyAsync(d_shapes, S.dev.data(), sizeof(DevShape) * S.dev.size(), hipMemcpyHostToDevice, s));
     StepTimer timer(profiling());
-    // HIP gives no elapsed time for events recorded as graph nodes: while profiling,
-    // steps are launched directly with an event pair around each
     const bool use_graph = !plain && s != nullptr && !timer.on();
-    for (int64_t w = 0; w < n_cfg; w += n_slot) {
-        const int64_t nb = std::min<int64_t>(n_slot, n_cfg - w);
-        a.n_slot = (int32_t)nb;
-        a.bits = bits + w * t.words;
-        a.out.perc = out.perc + w;
-        a.out.steps = out.steps + w;
-        a.out.hit = out.hit ? out.hit + w : nullptr;
+    int64_t w0 = 0;
+    while (w0 < n) {
+        // slots of this wave: as many jobs as the budget holds (one for the plain form)
+        int64_t w1 = w0, words = 0, bitw = 0;
+        while (w1 < n) {
+            const LatticeDesc& d = jobs[w1].lat->d;
+            const int64_t sw = slot_words(d);
+            const int64_t bw = jobs[w1].bits ? 0 : bits_words(d);
+            const int64_t bytes = (words + sw) * 9 + (bitw + bw) * 4 + (w1 - w0 + 1) * 96;
+            if (w1 > w0 && (bytes > budget || plain || w1 - w0 >= (1 << 20))) break;
+            words += sw;
+            bitw += bw;
+            ++w1;
+        }
+        const int32_t nb = (int32_t)(w1 - w0);
+        std::vector<int32_t> h_shape(nb), h_group(nb);
+        std::vector<int64_t> h_off(nb), h_boff(nb, -1);
+        std::vector<Job> h_jobs(nb);
+        int64_t off = 0, boff = 0;
+        for (int32_t b = 0; b < nb; ++b) {
+            const HostJob& hj = jobs[w0 + b];
+            const LatticeDesc& d = hj.lat->d;
+            h_shape[b] = S.of_job[w0 + b];
+            h_off[b] = off;
+            off += slot_words(d);
+            if (!hj.bits) {
+                h_boff[b] = boff;
+                boff += bits_words(d);
+            }
+            h_jobs[b] = Job{hj.bits, hj.seed, hj.cfg, hj.thr, h_shape[b], hj.group};
+            h_group[b] = hj.group;
+        }
+        Arena ar;
+        const size_t bytes = Arena::align(sizeof(float) * off) * 2 + Arena::align((size_t)off) +
+                             Arena::align(sizeof(uint32_t) * boff) + Arena::align(sizeof(CfgState) * nb) +
+                             Arena::align(sizeof(int32_t) * nb) * 4 + Arena::align(sizeof(int64_t) * (nb + 1)) * 2 +
+                             Arena::align(sizeof(void*) * nb) + Arena::align(sizeof(Job) * nb) + Arena::align(64);
+        PERC_TRY(ar.reserve(bytes, s));
+        SpanArgs a{};
+        a.shapes = d_shapes;
+        a.ya = ar.take<float>(off);
+        a.yb = ar.take<float>(off);
+        a.code = ar.take<uint8_t>(off);
+        uint32_t* scratch_bits = ar.take<uint32_t>(boff);
+        a.st = ar.take<CfgState>(nb);
+        a.active = ar.take<int32_t>(nb);
+        a.active2 = ar.take<int32_t>(nb);
+        int32_t* d_shape = ar.take<int32_t>(nb);
+        int32_t* d_group = ar.take<int32_t>(nb);
+        a.chunk_off = ar.take<int64_t>(nb + 1);
+        int64_t* d_off = ar.take<int64_t>(nb + 1);
+        uint32_t** d_bits = ar.take<uint32_t*>(nb);
+        Job* d_jobs = ar.take<Job>(nb);
+        a.hdr = ar.take<int32_t>(16);
+        std::vector<const uint32_t*> h_bits(nb);
+        for (int32_t b = 0; b < nb; ++b) h_bits[b] = h_jobs[b].bits ? h_jobs[b].bits : scratch_bits + h_boff[b];
+        HIP_TRY(hipMemcpyAsync(d_shape, h_shape.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_group, h_group.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_off, h_off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_bits, h_bits.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs.data(), sizeof(Job) * nb, hipMemcpyHostToDevice, s));
+        a.slot_shape = d_shape;
+        a.slot_off = d_off;
+        a.slot_bits = d_bits;
+        a.work = reinterpret_cast<unsigned long long*>(a.hdr + 8);
+        a.out.perc = out.perc + w0;
+        a.out.steps = out.steps + w0;
+        a.out.hit = out.hit ? out.hit + w0 : nullptr;
+        a.out.group_count = out.group_count;
+        a.out.group = out.group_count ? d_group : nullptr;
+        a.n_slot = nb;
+        a.depth = tu.depth;
+        a.block = tu.block;
+        a.grid = tu.grid ? tu.grid : 2048;
+        a.lds = lds;
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.hdr), 16, 0u, s));
+        if (boff) HIP_TRY(launch_sample_slots(d_shapes, d_jobs, nb, d_bits, s));
         HIP_TRY(launch_span_init(a, s));
         if (plain) {
             for (;;) {
@@ -334,7 +474,10 @@ int run_span(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int
                     if (ce == hipSuccess) ce = launch_span_plan(a, s);
                 }
                 hipError_t ee = hipStreamEndCapture(s, &graph);
-                if (ce != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return hip_fail(ce, "capture"); }
+                if (ce != hipSuccess) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return hip_fail(ce, "capture");
+                }
                 if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
                 hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(graph);
@@ -359,7 +502,10 @@ int run_span(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int
                 hipError_t e = hipMemcpyAsync(h, a.hdr, 64, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 if (e == hipSuccess) e = timer.collect();
-                if (e != hipSuccess) { rc = hip_fail(e, "span poll"); break; }
+                if (e != hipSuccess) {
+                    rc = hip_fail(e, "span poll");
+                    break;
+                }
                 if (h[0] == 0) break;
                 reps = std::min(reps * 2, 8);
             }
@@ -368,56 +514,64 @@ int run_span(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int
         }
         if (h[2]) return fail(PERC_ECAP, "a configuration reached the step cap");
         if (timer.on()) {
-            unsigned long long cells = 0;
-            std::memcpy(&cells, h + 8, sizeof(cells));
+            unsigned long long tubes = 0;
+            std::memcpy(&tubes, h + 8, sizeof(tubes));
             std::lock_guard<std::mutex> g(g_prof.mu);
-            g_prof.tube_steps += (int64_t)cells * t.C;
+            g_prof.tube_steps += (int64_t)tubes;
         }
         HIP_TRY(launch_span_finish(a, s));
+        w0 = w1;
     }
     return PERC_OK;
 }
 
-// ---------------------------------------------------------------------------------
-// Persistent form.
-// ---------------------------------------------------------------------------------
-int run_persist(const LatticeDesc& d, const DevTables& t, const uint32_t* bits, int64_t n_cfg, uint64_t cfg0,
-                uint64_t thr, uint64_t seed, BatchOut out, const Tuning& tu, hipStream_t s) {
-    if (n_cfg == 0) return PERC_OK;
+// Persistent form: every job in one launch; scratch per resident workgroup.
+int run_persist(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, const Tuning& tu, hipStream_t s) {
+    const int64_t n = (int64_t)jobs.size();
+    if (n == 0) return PERC_OK;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int lds = (int)lds_total(S.need.span_max);
     int grid = tu.grid;
-    if (grid == 0) {
-        const int per_cu = std::max(1, persist_resident_per_cu(tu.depth, tu.block, t.C));
-        grid = cus * per_cu;
+    if (grid == 0) grid = cus * std::max(1, persist_resident_per_cu(tu.block, lds));
+    grid = (int)std::min<int64_t>(grid, n);
+    const int64_t sw = (S.max_state + 63) & ~(int64_t)63;
+    const int64_t bw = (S.max_words + 63) & ~(int64_t)63;
+    bool any_sample = false;
+    std::vector<Job> h_jobs(n);
+    for (int64_t j = 0; j < n; ++j) {
+        const HostJob& hj = jobs[j];
+        h_jobs[j] = Job{hj.bits, hj.seed, hj.cfg, hj.thr, S.of_job[j], hj.group};
+        any_sample |= hj.bits == nullptr;
     }
-    grid = (int)std::min<int64_t>(grid, n_cfg);
-    const int64_t cell_words = (int64_t)t.U * t.CP;
     Arena ar;
-    const size_t bytes = Arena::align(sizeof(float) * grid * cell_words) * 2 + Arena::align((size_t)grid * cell_words) +
-                         (bits ? 0 : Arena::align(sizeof(uint32_t) * grid * t.words)) + Arena::align(64);
+    const size_t bytes = Arena::align(sizeof(float) * grid * sw) * 2 + Arena::align((size_t)grid * sw) +
+                         (any_sample ? Arena::align(sizeof(uint32_t) * grid * bw) : 0) + Arena::align(sizeof(Job) * n) +
+                         Arena::align(sizeof(DevShape) * S.dev.size()) + Arena::align(64);
     PERC_TRY(ar.reserve(bytes, s));
     PersistArgs a{};
-    a.t = t;
-    a.bits = bits;
-    a.ya = ar.take<float>(grid * cell_words);
-    a.yb = ar.take<float>(grid * cell_words);
-    a.code = ar.take<uint8_t>(grid * cell_words);
-    a.bits_scratch = bits ? nullptr : ar.take<uint32_t>(grid * t.words);
+    a.ya = ar.take<float>(grid * sw);
+    a.yb = ar.take<float>(grid * sw);
+    a.code = ar.take<uint8_t>(grid * sw);
+    a.state_stride = sw;
+    a.bits_scratch = any_sample ? ar.take<uint32_t>(grid * bw) : nullptr;
+    a.bits_stride = bw;
+    Job* d_jobs = ar.take<Job>(n);
+    DevShape* d_shapes = ar.take<DevShape>(S.dev.size());
     a.queue = ar.take<unsigned long long>(2);
     a.err = reinterpret_cast<uint32_t*>(a.queue + 1);
-    a.n_cfg = n_cfg;
-    a.cfg0 = cfg0;
-    a.threshold = thr;
-    a.seed = seed;
-    a.tag = ((uint32_t)d.W << 16) | (uint32_t)d.L;
+    HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_shapes, S.dev.data(), sizeof(DevShape) * S.dev.size(), hipMemcpyHostToDevice, s));
+    a.shapes = d_shapes;
+    a.jobs = d_jobs;
+    a.n_jobs = n;
     a.out = out;
     a.depth = tu.depth;
     a.block = tu.block;
     a.grid = grid;
-    a.cap = d.N + 1;
+    a.lds = lds;
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.queue), 4, 0u, s));
     HIP_TRY(launch_persist(a, s));
     return PERC_OK;
@@ -428,9 +582,18 @@ int validate_lat(const perc_lattice* lat) {
     return PERC_OK;
 }
 
-uint64_t threshold_of(double p) {
-    if (p >= 1.0) return (uint64_t)1 << 32;
-    return (uint64_t)std::floor(p * 4294967296.0);
+// Run a list of jobs with outputs indexed by job (device pointers; steps required).
+int run_jobs(const std::vector<HostJob>& jobs, BatchOut out, const perc_options* opt, hipStream_t s) {
+    Shapes S;
+    collect_shapes(jobs, S);
+    TuneKey key{0, 0, 0};
+    const bool one = S.lats.size() == 1;
+    if (one) key = TuneKey{S.lats[0]->d.W, S.lats[0]->d.L, size_bucket((int64_t)jobs.size())};
+    Tuning tu;
+    PERC_TRY(resolve(S.need, S.max_state, (int64_t)jobs.size(), opt, tu, one ? &key : nullptr));
+    PERC_TRY(device_shapes(S));
+    if (tu.form == FORM_PERSIST) return run_persist(jobs, S, out, tu, s);
+    return run_span(jobs, S, out, tu, s);
 }
 
 int inspect_impl(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc, int32_t* steps,
@@ -440,18 +603,18 @@ int inspect_impl(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cf
     if (n_cfg == 0) return PERC_OK;
     if (!occ_bits || !perc) return fail(PERC_EINVAL, "occ_bits and perc must be device pointers");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    Tuning tu;
-    PERC_TRY(resolve(lat->d, n_cfg, opt, tu));
-    DevTables t;
-    PERC_TRY(tables_for(lat, tu.depth, t));
     Arena ar;
     if (!steps) {
         PERC_TRY(ar.reserve(sizeof(int32_t) * n_cfg, s));
         steps = ar.take<int32_t>(n_cfg);
     }
-    BatchOut out{perc, steps, hit};
-    if (tu.form == FORM_PERSIST) return run_persist(lat->d, t, occ_bits, n_cfg, 0, 0, 0, out, tu, s);
-    return run_span(lat->d, t, occ_bits, n_cfg, out, tu, s);
+    std::vector<HostJob> jobs(n_cfg);
+    for (int64_t i = 0; i < n_cfg; ++i) jobs[i] = HostJob{lat, occ_bits + i * lat->d.words, 0, 0, 0, -1};
+    BatchOut out;
+    out.perc = perc;
+    out.steps = steps;
+    out.hit = hit;
+    return run_jobs(jobs, out, opt, s);
 }
 
 int pi_impl(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, perc_pi_out* out,
@@ -464,30 +627,19 @@ int pi_impl(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, per
     out->pi = 0.0;
     if (n_cfg == 0) return PERC_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    Tuning tu;
-    PERC_TRY(resolve(lat->d, n_cfg, opt, tu));
-    DevTables t;
-    PERC_TRY(tables_for(lat, tu.depth, t));
     const uint64_t thr = threshold_of(p);
     Arena ar;
     const size_t bytes = (out->bits ? 0 : Arena::align((size_t)n_cfg)) +
-                         (out->steps ? 0 : Arena::align(sizeof(int32_t) * n_cfg)) +
-                         (tu.form == FORM_PERSIST ? 0 : Arena::align(sizeof(uint32_t) * n_cfg * t.words)) +
-                         Arena::align(64);
+                         (out->steps ? 0 : Arena::align(sizeof(int32_t) * n_cfg)) + Arena::align(64);
     PERC_TRY(ar.reserve(bytes, s));
     BatchOut bo;
     bo.perc = out->bits ? out->bits : ar.take<uint8_t>(n_cfg);
     bo.steps = out->steps ? out->steps : ar.take<int32_t>(n_cfg);
     bo.hit = out->hit;
     unsigned long long* count = ar.take<unsigned long long>(1);
-    if (tu.form == FORM_PERSIST) {
-        PERC_TRY(run_persist(lat->d, t, nullptr, n_cfg, 0, thr, seed, bo, tu, s));
-    } else {
-        uint32_t* bits = ar.take<uint32_t>(n_cfg * t.words);
-        const uint32_t tag = ((uint32_t)lat->d.W << 16) | (uint32_t)lat->d.L;
-        HIP_TRY(launch_sample(t, bits, n_cfg, 0, thr, seed, tag, s));
-        PERC_TRY(run_span(lat->d, t, bits, n_cfg, bo, tu, s));
-    }
+    std::vector<HostJob> jobs(n_cfg);
+    for (int64_t i = 0; i < n_cfg; ++i) jobs[i] = HostJob{lat, nullptr, seed, (uint64_t)i, thr, -1};
+    PERC_TRY(run_jobs(jobs, bo, opt, s));
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(count), 2, 0u, s));
     HIP_TRY(launch_count(bo.perc, n_cfg, count, s));
     unsigned long long host_count = 0;
@@ -507,7 +659,10 @@ extern "C" {
 
 perc_lattice* perc_lattice_create(int32_t W, int32_t L) {
     perc_lattice* lat = new (std::nothrow) perc_lattice();
-    if (!lat) { g_err = "out of host memory"; return nullptr; }
+    if (!lat) {
+        g_err = "out of host memory";
+        return nullptr;
+    }
     std::string err;
     if (!build_lattice(W, L, lat->d, err)) {
         g_err = err;
@@ -523,7 +678,9 @@ void perc_lattice_destroy(perc_lattice* lat) {
     const bool have = hipGetDevice(&cur) == hipSuccess;
     for (auto& x : lat->dev) {
         if (hipSetDevice(x.device) == hipSuccess) {
-            for (uint32_t* p : x.nboff) (void)hipFree(p);
+            (void)hipFree(x.nboff);
+            (void)hipFree(x.tile);
+            (void)hipFree(x.rank);
             (void)hipFree(x.top);
         }
     }
@@ -534,13 +691,14 @@ void perc_lattice_destroy(perc_lattice* lat) {
 int64_t perc_lattice_sites(const perc_lattice* lat) { return lat ? lat->d.N : -1; }
 int64_t perc_lattice_words(const perc_lattice* lat) { return lat ? lat->d.words : -1; }
 int32_t perc_lattice_columns(const perc_lattice* lat) { return lat ? lat->d.C : -1; }
-int64_t perc_lattice_state_bytes(const perc_lattice* lat) { return lat ? state_bytes(lat->d) : -1; }
+int64_t perc_lattice_state_bytes(const perc_lattice* lat) { return lat ? slot_words(lat->d) * 9 : -1; }
 
 int perc_site_coord(const perc_lattice* lat, int64_t s, int32_t* q, int32_t* r, int32_t* k) {
     PERC_TRY(validate_lat(lat));
     const LatticeDesc& d = lat->d;
     if (s < 0 || s >= d.N) return fail(PERC_EINVAL, "site index out of range");
-    const int64_t u = s / d.C, c = s - u * d.C;
+    const int64_t u = s / d.C;
+    const int32_t c = d.by_rank[s - u * d.C];
     if (q) *q = d.q[c];
     if (r) *r = d.r[c];
     if (k) *k = (int32_t)(3 * u + d.sig[c]);
@@ -551,11 +709,12 @@ int perc_site_neighbors(const perc_lattice* lat, int64_t s, int64_t* nbr, int32_
     PERC_TRY(validate_lat(lat));
     const LatticeDesc& d = lat->d;
     if (s < 0 || s >= d.N || !nbr || !count) return fail(PERC_EINVAL, "bad site or NULL output");
-    const int64_t u = s / d.C, c = s - u * d.C;
+    const int64_t u = s / d.C;
+    const int32_t c = d.by_rank[s - u * d.C];
     std::vector<int64_t> out;
-    auto add = [&](int64_t uu, int64_t cc) {
+    auto add = [&](int64_t uu, int32_t cc) {
         if (uu < 0 || uu >= d.U || cc >= d.C) return;
-        const int64_t t = uu * d.C + cc;
+        const int64_t t = uu * d.C + d.rank[cc];
         if (t < d.N) out.push_back(t);
     };
     for (int i = 0; i < kSide; ++i) {
@@ -597,10 +756,9 @@ int perc_sample(const perc_lattice* lat, double p, uint64_t seed, int64_t cfg0, 
     if (n_cfg < 0 || cfg0 < 0) return fail(PERC_EINVAL, "n_cfg and cfg0 must be >= 0");
     if (n_cfg == 0) return PERC_OK;
     if (!occ_bits) return fail(PERC_EINVAL, "occ_bits is NULL");
-    DevTables t;
-    PERC_TRY(tables_for(lat, 1, t));
-    const uint32_t tag = ((uint32_t)lat->d.W << 16) | (uint32_t)lat->d.L;
-    HIP_TRY(launch_sample(t, occ_bits, n_cfg, (uint64_t)cfg0, threshold_of(p), seed, tag,
+    DevShape sh;
+    PERC_TRY(shape_for(lat, sh));
+    HIP_TRY(launch_sample(sh, occ_bits, n_cfg, (uint64_t)cfg0, threshold_of(p), seed,
                           reinterpret_cast<hipStream_t>(stream)));
     return PERC_OK;
 }
@@ -624,6 +782,48 @@ int perc_pi_ex(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, 
     return pi_impl(lat, p, n_cfg, seed, out, opt, stream);
 }
 
+int perc_batch(const perc_job* jobs, int64_t n_jobs, uint8_t* perc, int32_t* steps, float* hit, int64_t* group_count,
+               int32_t n_groups, const perc_options* opt, void* stream) {
+    if (n_jobs < 0 || n_groups < 0) return fail(PERC_EINVAL, "n_jobs and n_groups must be >= 0");
+    if (n_groups > 0 && !group_count) return fail(PERC_EINVAL, "group_count is NULL");
+    if (n_jobs == 0) {
+        for (int32_t g = 0; g < n_groups; ++g) group_count[g] = 0;
+        return PERC_OK;
+    }
+    if (!jobs || !perc) return fail(PERC_EINVAL, "jobs and perc must not be NULL");
+    std::vector<HostJob> hj(n_jobs);
+    for (int64_t j = 0; j < n_jobs; ++j) {
+        const perc_job& x = jobs[j];
+        PERC_TRY(validate_lat(x.lat));
+        if (!x.occ_bits && !(x.p >= 0.0 && x.p <= 1.0)) return fail(PERC_EINVAL, "job p must be in [0, 1]");
+        if (x.cfg < 0) return fail(PERC_EINVAL, "job cfg must be >= 0");
+        if (x.group >= n_groups) return fail(PERC_EINVAL, "job group out of range");
+        hj[j] = HostJob{x.lat, x.occ_bits, x.seed, (uint64_t)x.cfg, x.occ_bits ? 0 : threshold_of(x.p),
+                        x.group < 0 ? -1 : x.group};
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Arena ar;
+    PERC_TRY(ar.reserve(Arena::align(sizeof(int32_t) * n_jobs) + Arena::align(8 * (size_t)std::max(n_groups, 1)), s));
+    BatchOut out;
+    out.perc = perc;
+    int32_t* own_steps = ar.take<int32_t>(n_jobs);
+    out.steps = steps ? steps : own_steps;
+    out.hit = hit;
+    unsigned long long* d_groups = ar.take<unsigned long long>(std::max(n_groups, 1));
+    if (n_groups > 0) {
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_groups), 2 * (int64_t)n_groups, 0u, s));
+        out.group_count = d_groups;
+    }
+    PERC_TRY(run_jobs(hj, out, opt, s));
+    if (n_groups > 0) {
+        std::vector<unsigned long long> h(n_groups);
+        HIP_TRY(hipMemcpyAsync(h.data(), d_groups, 8 * (size_t)n_groups, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int32_t g = 0; g < n_groups; ++g) group_count[g] = (int64_t)h[g];
+    }
+    return PERC_OK;
+}
+
 int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t K, float* x_out, uint8_t* reach_out,
                      void* stream) {
     PERC_TRY(validate_lat(lat));
@@ -631,41 +831,66 @@ int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t 
     if (!occ_bits || !x_out || !reach_out) return fail(PERC_EINVAL, "NULL device pointer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const LatticeDesc& d = lat->d;
-    const int32_t depth = depth_within(d.C, 80 * 1024, 3) ? depth_within(d.C, 80 * 1024, 3) : 1;
-    DevTables t;
-    PERC_TRY(tables_for(lat, depth, t));
-    const int64_t cell_words = (int64_t)t.U * t.CP;
+    ShapeNeed nd;
+    nd.span_max = d.span_max;
+    nd.tile_max = d.tile_max;
+    nd.C = d.C;
+    nd.items = (int64_t)d.U * d.ntile;
+    const int32_t block = block_for(nd);
+    PERC_TRY(check_walk(nd, block));
+    const int32_t depth = cells_for(nd, FORM_PLAIN);
+    DevShape sh;
+    PERC_TRY(shape_for(lat, sh));
+    const int64_t cw = slot_words(d);
     Arena ar;
-    PERC_TRY(ar.reserve(Arena::align(sizeof(float) * cell_words) * 2 + Arena::align((size_t)cell_words) +
-                            Arena::align(sizeof(CfgState)) + Arena::align(64) * 4, s));
-    float* ya = ar.take<float>(cell_words);
-    float* yb = ar.take<float>(cell_words);
-    uint8_t* code = ar.take<uint8_t>(cell_words);
+    PERC_TRY(ar.reserve(Arena::align(sizeof(float) * cw) * 2 + Arena::align((size_t)cw) +
+                            Arena::align(sizeof(CfgState)) + Arena::align(sizeof(DevShape)) + Arena::align(64) * 8,
+                        s));
+    float* ya = ar.take<float>(cw);
+    float* yb = ar.take<float>(cw);
+    uint8_t* code = ar.take<uint8_t>(cw);
     CfgState* st = ar.take<CfgState>(1);
+    DevShape* d_shape = ar.take<DevShape>(1);
     float* det = ar.take<float>(2);
     uint32_t* det_r = reinterpret_cast<uint32_t*>(det + 1);
     int32_t* hdr = ar.take<int32_t>(16);
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ya), cell_words, 0u, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(yb), cell_words, 0u, s));
+    int32_t* slot_shape = ar.take<int32_t>(1);
+    int64_t* slot_off = ar.take<int64_t>(2);
+    const uint32_t** slot_bits = ar.take<const uint32_t*>(1);
+    int64_t* chunk_off = ar.take<int64_t>(2);
+    HIP_TRY(hipMemcpyAsync(d_shape, &sh, sizeof(DevShape), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot_bits, &occ_bits, sizeof(void*), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ya), cw, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(yb), cw, 0u, s));
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(det), 2, 0u, s));
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(hdr), 16, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(slot_shape), 1, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(slot_off), 4, 0u, s));
     SpanArgs a{};
-    a.t = t;
-    a.bits = occ_bits;
-    a.ya = ya; a.yb = yb; a.code = code; a.st = st;
+    a.shapes = d_shape;
+    a.slot_shape = slot_shape;
+    a.slot_off = slot_off;
+    a.slot_bits = slot_bits;
+    a.ya = ya;
+    a.yb = yb;
+    a.code = code;
+    a.st = st;
+    a.chunk_off = chunk_off;
     a.hdr = hdr;
     a.n_slot = 1;
     a.depth = depth;
-    a.block = 256;
+    a.block = block;
+    a.grid = (int)std::min<int64_t>(((d.U + depth - 1) / depth) * (int64_t)d.ntile, 65536);
+    a.lds = (int)lds_total(d.span_max);
     HIP_TRY(launch_span_init_only(a, s));
     float* cur = ya;
     float* nxt = yb;
     for (int32_t m = 0; m < K; ++m) {
-        HIP_TRY(launch_far_sum(t, cur, det, det_r, s));
-        HIP_TRY(launch_chunk_step(t, cur, nxt, code, t.U, depth, 256, s));
+        HIP_TRY(launch_far_sum(sh, cur, det, det_r, s));
+        HIP_TRY(launch_chunk_step(sh, cur, nxt, code, depth, block, s));
         std::swap(cur, nxt);
     }
-    HIP_TRY(launch_export(t, cur, code, det, det_r, x_out, reach_out, s));
+    HIP_TRY(launch_export(sh, cur, code, det, det_r, x_out, reach_out, s));
     return PERC_OK;
 }
 

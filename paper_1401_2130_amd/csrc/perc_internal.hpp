@@ -1,5 +1,5 @@
-// Internal declarations shared by the host runtime (lattice.cpp, engine.cpp, api.cpp)
-// and the device code (kernels.hip). Not part of the public C ABI (include/perc.h).
+// Internal declarations shared by the host runtime (lattice.cpp, perc_api.cpp) and
+// the device code (kernels.hip). Not part of the public C ABI (include/perc.h).
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -17,57 +17,65 @@ namespace perc {
 // Columns (q, r) are the points of the projected triangular net (axial coordinates,
 // spacing = one tube spacing) inside the hexagon of hex radius W. Column (q, r) holds
 // the tubes of the (111) layers k with k = sigma (mod 3), sigma = (q - r) mod 3 (ABC
-// stacking). Columns are numbered c = 0..C-1 in (sigma, q, r) order, so that the
-// "unit cell" u (layers 3u, 3u+1, 3u+2) holds every column exactly once, tube (u, c)
-// sits on layer k = 3u + sigma(c), and the canonical site index is s = u*C + c. This
-// equals lexicographic (k, q, r) order; the last cell holds only the columns with
-// 3u + sigma < L, which are a prefix of the column order, so N = sites with s < N.
+// stacking). The "unit cell" u (layers 3u, 3u+1, 3u+2) holds every column exactly once:
+// tube (u, c) sits on layer k = 3u + sigma(c), and all 14 contacts of a tube lie in
+// cells u-1, u, u+1.
+//
+// Internally columns are numbered c = 0..C-1 in (q, r) order, so that the contacts of
+// a column lie within two q-rows of it and a tile of consecutive columns needs only a
+// narrow halo. The canonical site order of the ABI is lexicographic (k, q, r): tube
+// (u, c) has canonical index u*C + rank[c], with rank the (sigma, q, r) order; the tubes
+// of the last, partial cell are a prefix of that order, so a tube exists iff its
+// canonical index is below N.
 //
 // The 12 side contacts of a tube are the FCC nearest neighbours: 6 in its layer,
 // 3 in the layer above and 3 below; the 2 end contacts are the tubes of the same
-// column in cells u-1 and u+1. A side contact of column c lies in column nb_col and
-// cell u + nb_dcell (dcell in {-1, 0, +1}).
+// column in cells u-1 and u+1.
 // ---------------------------------------------------------------------------------
 constexpr int kSide = 12;
+constexpr int kTileCols = 512;  // target columns per tile
 
 struct LatticeDesc {
     int32_t W = 0, L = 0;
     int32_t C = 0;       // columns
     int32_t U = 0;       // unit cells, ceil(L / 3)
-    int32_t CP = 0;      // padded row length of the state arrays: multiple of 32, >= C + 1
+    int32_t CP = 0;      // row length of the state arrays: multiple of 32, >= C
     int64_t N = 0;       // sites
     int64_t words = 0;   // ceil(N / 32)
     int32_t nsig[3] = {0, 0, 0};
-    std::vector<int32_t> q, r, sig;  // per column
+    std::vector<int32_t> q, r, sig;  // per internal column
+    std::vector<int32_t> rank;       // canonical rank of internal column c
+    std::vector<int32_t> by_rank;    // internal column of canonical rank k
     std::vector<int32_t> top;        // per column: cell of its far-end tube, -1 if empty
     // per side contact i (0..11) and column c: packed (nb_col << 2) | (dcell + 1);
-    // a contact outside the hexagon points at column C (a zero pad).
+    // a contact outside the hexagon has nb_col = C
     std::vector<int32_t> nb;         // [kSide][C]
+    int32_t ntile = 1;
+    std::vector<int32_t> tile;       // [ntile][4]: first col, end col, halo first, halo end
+    int32_t span_max = 0;            // widest halo range
+    int32_t tile_max = 0;            // widest tile
 };
 
 bool build_lattice(int32_t W, int32_t L, LatticeDesc& out, std::string& err);
 
-// Chunk depths (unit cells per workgroup chunk) the kernels are built for.
-constexpr int kNumDepths = 6;
-constexpr int32_t kDepthList[kNumDepths] = {1, 3, 5, 7, 9, 15};
-inline int depth_index(int32_t d) {
-    for (int i = 0; i < kNumDepths; ++i)
-        if (kDepthList[i] == d) return i;
-    return -1;
-}
+// Words of one configuration's state (and bytes of its degree codes): the cells in
+// groups of four, each group a [CP] row of 4-word quads (word k of quad (g, c) is cell
+// 4g+k of column c).
+inline int64_t state_words(const LatticeDesc& d) { return (int64_t)((d.U + 3) / 4) * 4 * d.CP; }
 
-// Contact table of one chunk depth D: for side contact i of column c, the LDS byte
-// offset ((nb_col * (D + 2) + dcell + 1) * 4) of that contact in a chunk staged
-// column-major with D + 2 slots per column; the tube in slot j reads it at that offset
-// plus (j - 1) * 4.
-std::vector<uint32_t> contact_table(const LatticeDesc& d, int32_t depth);
+// LDS words per staged column: a ring of eight cell slots at indices 1..8 (cell u in
+// slot (u mod 8) + 1), with index 0 mirroring the slot-7 cell and index 9 the slot-0
+// cell, so that the four cells u-1 .. u+2 around any even cell u sit at consecutive
+// indices; stride 11 (odd) keeps consecutive columns on different LDS banks.
+constexpr int kRing = 11;
+constexpr int kRingCells = 8;
+constexpr int kDummyCols = 64;  // staging lanes beyond the halo range write here
 
-// Device copies of the per-column tables, one per HIP device that used the lattice.
-struct LatticeDevice {
-    int device = -1;
-    uint32_t* nboff[kNumDepths] = {};  // [kSide][C] per depth
-    int32_t* top = nullptr;             // [C]
-};
+// Contact table: for side contact i of column c (in tile k), the LDS word index
+// lcol * kRing + 1 + dcell of that contact for a tube in ring slot 0, lcol being 1 +
+// its column within the tile's staged range [halo first, halo end), or 0 (the zero pad
+// column) for a missing contact; a tube in slot s reads it at that index plus s.
+std::vector<uint32_t> contact_table(const LatticeDesc& d);
 
 #if defined(__HIPCC__)
 #define PERC_HD __host__ __device__
@@ -75,25 +83,33 @@ struct LatticeDevice {
 #define PERC_HD
 #endif
 
-// Dynamic LDS of a chunk kernel (byte offsets; every kernel of the inspection keeps
-// all its LDS here, so the state chunk starts at address 0):
-//   [0, state)   state words, column-major, (C + 1) columns x (D + 2) slots
-//   code         degree codes of the D computed cells, [c][D] bytes
-//   rcp          16 floats, 1/deg per code
-//   misc         16 words of flags and counters
-//   part         256 floats of partial sums
-struct LdsMap {
-    uint32_t code, rcp, misc, part, total;
+// One lattice shape as the kernels see it (device pointers).
+struct DevShape {
+    const uint32_t* nboff;  // [kSide][C] contact table
+    const int32_t* tile;    // [ntile][4]
+    const int32_t* rank;    // [C]
+    const int32_t* top;     // [C]
+    int32_t C, CP, U, L;
+    int32_t ntile, span_max, tile_max, W;
+    int64_t N, words;
 };
-PERC_HD inline LdsMap lds_map(int32_t C, int32_t D) {
-    LdsMap m;
-    const uint32_t state = (uint32_t)(C + 1) * (uint32_t)(D + 2) * 4u;
-    m.code = (state + 15u) & ~15u;
-    m.rcp = (m.code + (uint32_t)C * (uint32_t)D + 15u) & ~15u;
-    m.misc = m.rcp + 64u;
-    m.part = m.misc + 64u;
-    m.total = m.part + 1024u;
-    return m;
+
+// Device copies of the per-lattice tables, one set per HIP device that used it.
+struct LatticeDevice {
+    int device = -1;
+    uint32_t* nboff = nullptr;
+    int32_t* tile = nullptr;
+    int32_t* rank = nullptr;
+    int32_t* top = nullptr;
+};
+
+// Dynamic LDS of the walking kernels: the ring from address 0, (1 + span + kDummyCols)
+// columns x kRing words (pad column, staged range, dummy columns), then a fixed tail
+// (the last kLdsTail bytes of the launch's allocation): rcp (16 floats, 1/deg per
+// code), misc (16 words), part (256 floats).
+constexpr uint32_t kLdsTail = 64u + 64u + 1024u;
+PERC_HD inline uint32_t lds_total(int32_t span) {
+    return (((uint32_t)(span + 1 + kDummyCols) * (uint32_t)kRing * 4u + 15u) & ~15u) + kLdsTail;
 }
 
 // ---------------------------------------------------------------------------------
@@ -109,10 +125,10 @@ enum Form : int32_t {
 
 struct Tuning {
     int32_t form = FORM_AUTO;
-    int32_t depth = 0;      // cells per chunk (odd: 1, 3, 5, 7, 9, ...); 0 = choose
-    int32_t block = 0;      // threads per workgroup (64..1024); 0 = choose
+    int32_t depth = 0;        // cells per work item (a tile walks them in one pass); 0 = choose
+    int32_t block = 0;        // threads per workgroup (64..1024); 0 = choose
     int32_t graph_steps = 0;  // steps per graph replay (span form); 0 = choose
-    int32_t grid = 0;       // workgroups per launch (span step / persistent); 0 = choose
+    int32_t grid = 0;         // workgroups per launch (span step / persistent); 0 = choose
 };
 
 // Per-configuration device state of the span and plain forms.
@@ -128,92 +144,102 @@ constexpr uint32_t F_FRONT = 2u;     // the reached set entered cell front+1
 constexpr uint32_t F_FAR = 4u;       // a far-end tube is reached: detector next step
 constexpr uint32_t F_NONEMPTY = 8u;  // (initialisation) some start tube is metallic
 
-// Outputs of a batch, device pointers (any may be null except perc/steps).
+// Outputs, device pointers indexed by slot (span) or job (persistent).
 struct BatchOut {
     uint8_t* perc = nullptr;
     int32_t* steps = nullptr;
-    float* hit = nullptr;  // first-passage probability of the detector at the stop
+    float* hit = nullptr;                       // first-passage probability at the stop
+    unsigned long long* group_count = nullptr;  // percolating count per job group
+    const int32_t* group = nullptr;             // group of each slot (span form), or null
+};
+
+// A configuration to inspect: its shape, and either caller bits or a Philox draw.
+struct Job {
+    const uint32_t* bits;  // canonical occupancy (device), or null: sample from Philox
+    uint64_t seed;         // Philox key
+    uint64_t cfg;          // Philox configuration index
+    uint64_t thr;          // floor(p * 2^32)
+    int32_t shape;         // index into the shape array
+    int32_t group;         // output group (Pi count), or -1
 };
 
 // ---------------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).
 // ---------------------------------------------------------------------------------
-struct DevTables {
-    const uint32_t* nboff;  // contact table of the chunk depth in use
-    const int32_t* top;
-    int32_t C, CP, U, L;
-    int64_t N, words;
-};
 
 // Philox4x32-10 occupancy for configurations cfg0..cfg0+n_cfg-1 (canonical bits).
-hipError_t launch_sample(const DevTables& t, uint32_t* bits, int64_t n_cfg, uint64_t cfg0,
-                         uint64_t threshold, uint64_t seed, uint32_t tag, hipStream_t s);
+hipError_t launch_sample(const DevShape& sh, uint32_t* bits, int64_t n_cfg, uint64_t cfg0, uint64_t threshold,
+                         uint64_t seed, hipStream_t s);
 
-// Span/plain forms: state arrays are [n_slot][U][CP]; slot b inspects bits + b*words.
+// Philox occupancy of the slots whose job has no caller bits (jobs indexed by slot).
+hipError_t launch_sample_slots(const DevShape* shapes, const Job* jobs, int32_t n_slot, uint32_t* const* slot_bits,
+                               hipStream_t s);
+
+// Span/plain forms. Slot b holds one configuration: shape slot_shape[b], state words at
+// slot_off[b] in ya/yb/code, occupancy bits slot_bits[b] (device pointer).
 struct SpanArgs {
-    DevTables t;
-    const uint32_t* bits;      // [n_slot][words]
-    float* ya;                 // [n_slot][U][CP]
+    const DevShape* shapes;
+    const int32_t* slot_shape;
+    const int64_t* slot_off;
+    const uint32_t* const* slot_bits;
+    float* ya;
     float* yb;
-    uint8_t* code;             // [n_slot][U][CP]
+    uint8_t* code;
     CfgState* st;              // [n_slot]
-    int32_t* active;           // [n_slot] active slot list (first entry count in hdr)
+    int32_t* active;           // [n_slot] active slots
     int32_t* active2;          // scratch for compaction
-    int64_t* chunk_off;        // [n_slot + 1] prefix sums of chunks per active slot
-    int32_t* hdr;              // [4]: n_active, total chunks, error flag, spare
-    unsigned long long* work;  // cells scheduled over all steps (planner adds), or null
+    int64_t* chunk_off;        // [n_slot + 1] prefix sums of items per active slot
+    int32_t* hdr;              // [16]: n_active, total items, error flag
+    unsigned long long* work;  // tube slots scheduled over all steps (planner adds)
     BatchOut out;
     int32_t n_slot;
-    int32_t depth;             // cells per chunk
+    int32_t depth;             // cells per work item
     int32_t block;
     int32_t grid;
-    int64_t cap;               // step cap (never reached for a correct lattice)
+    int32_t lds;               // dynamic LDS bytes of the walking kernels
 };
 
-hipError_t launch_span_init(const SpanArgs& a, hipStream_t s);     // codes, y0, first plan
+hipError_t launch_span_init(const SpanArgs& a, hipStream_t s);       // codes, y0, first plan
 hipError_t launch_span_init_only(const SpanArgs& a, hipStream_t s);  // codes and y0 only
-hipError_t launch_span_step(const SpanArgs& a, hipStream_t s);     // one step over work list
-hipError_t launch_span_plan(const SpanArgs& a, hipStream_t s);     // decide, compact, plan
-hipError_t launch_span_finish(const SpanArgs& a, hipStream_t s);   // first-hit probabilities
+hipError_t launch_span_step(const SpanArgs& a, hipStream_t s);       // one step over the work list
+hipError_t launch_span_plan(const SpanArgs& a, hipStream_t s);       // decide, compact, plan
+hipError_t launch_span_finish(const SpanArgs& a, hipStream_t s);     // first-hit probabilities, counts
 
-// Persistent form: one workgroup per configuration, scratch per resident workgroup.
+// Persistent form: one workgroup per job, scratch per resident workgroup.
 struct PersistArgs {
-    DevTables t;
-    const uint32_t* bits;      // caller's bits [n_cfg][words], or null to sample
-    uint32_t* bits_scratch;    // [grid][words] when sampling
-    float* ya;                 // [grid][U][CP]
+    const DevShape* shapes;
+    const Job* jobs;           // [n_jobs]
+    int64_t n_jobs;
+    uint32_t* bits_scratch;    // [grid][bits_stride]
+    int64_t bits_stride;
+    float* ya;                 // [grid][state_stride]
     float* yb;
-    uint8_t* code;             // [grid][U][CP]
-    unsigned long long* queue; // next configuration to take
-    uint32_t* err;             // set when a configuration reached the step cap
-    int64_t n_cfg;
-    uint64_t cfg0;
-    uint64_t threshold;
-    uint64_t seed;
-    uint32_t tag;
+    uint8_t* code;
+    int64_t state_stride;
+    unsigned long long* queue;  // next job to take
+    uint32_t* err;              // set when a configuration reached the step cap
     BatchOut out;
     int32_t depth;
     int32_t block;
     int32_t grid;
-    int64_t cap;
+    int32_t lds;
 };
 hipError_t launch_persist(const PersistArgs& a, hipStream_t s);
 
-// Test hook: export x = |y| deg (canonical order) and the reach bits, detector last.
-hipError_t launch_export(const DevTables& t, const float* y, const uint8_t* code, const float* det_mass,
-                         const uint32_t* det_reached, float* x_out, uint8_t* reach_out, hipStream_t s);
-hipError_t launch_chunk_step(const DevTables& t, const float* yin, float* yout, const uint8_t* code, int front,
-                             int depth, int block, hipStream_t s);
-hipError_t launch_far_sum(const DevTables& t, const float* y, float* det_mass, uint32_t* det_reached,
+// Test hook: one step of one configuration over all cells; detector accumulation;
+// export of x = |y| deg (canonical order) and the reach bits, detector last.
+hipError_t launch_chunk_step(const DevShape& sh, const float* yin, float* yout, const uint8_t* code, int depth,
+                             int block, hipStream_t s);
+hipError_t launch_far_sum(const DevShape& sh, const float* y, float* det_mass, uint32_t* det_reached,
                           hipStream_t s);
+hipError_t launch_export(const DevShape& sh, const float* y, const uint8_t* code, const float* det_mass,
+                         const uint32_t* det_reached, float* x_out, uint8_t* reach_out, hipStream_t s);
 
 // Count of percolating configurations (integer, deterministic).
 hipError_t launch_count(const uint8_t* perc, int64_t n, unsigned long long* count, hipStream_t s);
-
-size_t lds_bytes_for(int32_t C, int32_t depth);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
-int persist_resident_per_cu(int depth, int block, int C);
+
+int persist_resident_per_cu(int block, int lds_bytes);
 hipError_t prepare_kernels(int device);
-int32_t max_depth_for(int32_t C);
 
 }  // namespace perc

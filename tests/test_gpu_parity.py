@@ -46,7 +46,8 @@ def check_hit(hit_gpu, hit_ref, perc_ref, steps_ref):
     assert np.all(hit_gpu[perc_ref == 0] == 0.0)
 
 
-FORMS = [("plain", 1), ("span", 1), ("span", 3), ("span", 9), ("persist", 1), ("persist", 5), ("persist", 15)]
+# (form, cells per work item); 5 is rounded up to 8 by the library
+FORMS = [("plain", 8), ("span", 8), ("span", 5), ("span", 24), ("persist", 8), ("persist", 16), ("persist", 64)]
 
 
 # --------------------------------------------------------------------------------
@@ -65,7 +66,7 @@ def test_sampler_bit_exact(perc, W, L, p, seed, cfg0, n):
 
 
 # --------------------------------------------------------------------------------
-# inspection: every form and depth against the oracle
+# inspection: every form and item length against the oracle
 # --------------------------------------------------------------------------------
 
 SHAPES = [(0, 1), (0, 2), (0, 3), (0, 10), (1, 4), (1, 5), (2, 6), (2, 13), (3, 9), (4, 16), (4, 17), (5, 30),
@@ -94,7 +95,7 @@ def test_inspect_matches_oracle(perc, W, L, form, depth):
 
 def test_forms_agree_bitwise(perc):
     """Each configuration's bits, steps and FP32 first-hit probability are the same
-    alone (plain), spread (span) and one-per-workgroup (persist), at every depth."""
+    alone (plain), spread (span) and one-per-workgroup (persist), at every item length."""
     W, L = 6, 40
     lat = perc.Lattice(W, L)
     occ = workloads.random_occupancy(lat.n, 200, 0.32, 77)
@@ -124,7 +125,7 @@ def test_graph_path_on_a_side_stream(perc):
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         for gs in (1, 3, 8, 32):
-            pg, sg, _ = perc.perc_inspect_ex(lat, d_occ, form="span", depth=3, graph_steps=gs, stream=s)
+            pg, sg, _ = perc.perc_inspect_ex(lat, d_occ, form="span", depth=8, graph_steps=gs, stream=s)
             s.synchronize()
             np.testing.assert_array_equal(pg.cpu().numpy(), pm)
             np.testing.assert_array_equal(sg.cpu().numpy(), sm)
@@ -275,3 +276,85 @@ def test_pi_batched_workload_sampled(perc):
         if prev is not None:
             assert np.all(prev <= b)
         prev = b
+
+
+# --------------------------------------------------------------------------------
+# uneven batches: several lattice shapes in one launch
+# --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("form,depth", [("span", 8), ("span", 16), ("persist", 8), ("plain", 8)])
+def test_batch_of_mixed_shapes(perc, form, depth):
+    shapes = [(2, 9), (5, 22), (3, 40), (8, 17), (0, 12), (11, 33)]
+    lats = {s: perc.Lattice(*s) for s in shapes}
+    refs = {s: oracle.Lattice(*s) for s in shapes}
+    rng = np.random.default_rng(4)
+    jobs, expect = [], []
+    n_groups = len(shapes) * 2
+    counts = np.zeros(n_groups, np.int64)
+    keep = []
+    for gi, s in enumerate(shapes):
+        for pi, p in enumerate((0.2, 0.45)):
+            grp = 2 * gi + pi
+            for cfg in range(6):
+                if rng.random() < 0.5:
+                    occ = refs[s].sample(p, 31, 1, cfg0=cfg)
+                    jobs.append((lats[s], p, 31, cfg, grp))
+                else:
+                    occ = workloads.random_occupancy(refs[s].n, 1, p, 1000 * gi + 10 * pi + cfg)
+                    t = dev(occ[0])
+                    keep.append(t)
+                    jobs.append((lats[s], t, grp))
+                pm, sm, hm = refs[s].inspect_markov(occ)
+                expect.append((pm[0], sm[0], hm[0]))
+                counts[grp] += pm[0]
+    order = rng.permutation(len(jobs))  # shapes interleaved in the batch
+    jobs = [jobs[i] for i in order]
+    expect = [expect[i] for i in order]
+    pg, sg, hg, cnt = perc.perc_batch(jobs, n_groups=n_groups, hit=True, form=form, depth=depth)
+    torch.cuda.synchronize()
+    pm = np.array([e[0] for e in expect]); sm = np.array([e[1] for e in expect]); hm = np.array([e[2] for e in expect])
+    np.testing.assert_array_equal(pg.cpu().numpy(), pm)
+    np.testing.assert_array_equal(sg.cpu().numpy(), sm)
+    check_hit(hg.cpu().numpy().astype(np.float64), hm, pm, sm)
+    assert cnt == counts.tolist()
+
+
+def test_batch_matches_single_shape_calls_bitwise(perc):
+    a, b = perc.Lattice(6, 30), perc.Lattice(9, 21)
+    jobs = [(a, 0.3, 5, i, 0) for i in range(40)] + [(b, 0.35, 6, i, 1) for i in range(40)]
+    rng = np.random.default_rng(0)
+    order = rng.permutation(len(jobs))
+    mixed = [jobs[i] for i in order]
+    pg, sg, hg, cnt = perc.perc_batch(mixed, n_groups=2, hit=True, form="span")
+    for lat, p, seed, grp in ((a, 0.3, 5, 0), (b, 0.35, 6, 1)):
+        bits = torch.empty(40, dtype=torch.uint8, device="cuda")
+        steps = torch.empty(40, dtype=torch.int32, device="cuda")
+        hit = torch.empty(40, dtype=torch.float32, device="cuda")
+        n_perc, _ = perc.perc_pi_ex(lat, p, 40, seed, bits=bits, steps=steps, hit=hit, form="persist")
+        assert n_perc == cnt[grp]
+        sel = [k for k, i in enumerate(order) if jobs[i][0] is lat]
+        cfgs = [mixed[k][3] for k in sel]
+        np.testing.assert_array_equal(pg.cpu().numpy()[sel], bits.cpu().numpy()[cfgs])
+        np.testing.assert_array_equal(sg.cpu().numpy()[sel], steps.cpu().numpy()[cfgs])
+        np.testing.assert_array_equal(hg.cpu().numpy().view(np.uint32)[sel], hit.cpu().numpy().view(np.uint32)[cfgs])
+
+
+def test_wide_fiber_many_tiles(perc):
+    """W=40 (4921 columns, ten column tiles with halos): every form against the oracle."""
+    W, L = 40, 20
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    occ = np.concatenate([workloads.random_occupancy(ref.n, 8, p, 50 + i) for i, p in enumerate((0.12, 0.2, 0.35))])
+    pm, sm, hm = ref.inspect_markov(occ)
+    for form, depth in (("span", 8), ("span", 40), ("persist", 16), ("plain", 8)):
+        pg, sg, hg = perc.perc_inspect_ex(lat, dev(occ), hit=True, form=form, depth=depth)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(pg.cpu().numpy(), pm)
+        np.testing.assert_array_equal(sg.cpu().numpy(), sm)
+        check_hit(hg.cpu().numpy().astype(np.float64), hm, pm, sm)
+    x64, r64 = ref.state_after(occ[5:6], 12)
+    x32, r32 = perc.perc_state_after(lat, dev(occ[5]), 12)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r32.cpu().numpy().astype(bool), r64)
+    big = x64 >= 2.0 ** -100
+    np.testing.assert_allclose(x32.cpu().numpy().astype(np.float64)[big], x64[big], rtol=1e-5, atol=0)
