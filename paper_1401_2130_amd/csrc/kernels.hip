@@ -8,25 +8,27 @@
 // stops at the first such step or when the set of tubes with non-zero probability in
 // exact arithmetic (the reached set) stops growing.
 //
-// Representation (one 32-bit word per tube, per state buffer):
-//   value  = y = x / deg, the mass the tube sends along each of its deg contacts, so a
-//            receiver sums its neighbours' words and scales by its own 1/deg only;
-//   sign   = reached bit. Probabilities are non-negative, so the sign bit is free; it
-//            carries the exact reached set even where the FP32 value has underflowed
-//            to zero (the decision never looks at the FP32 value).
+// Representation (one FP32 word per tube, per state buffer): y = x / deg, the mass the
+// tube sends along each of its deg contacts, so a receiver sums its neighbours' words
+// and scales by its own 1/deg only. The word of a tube is non-zero exactly when the
+// tube is in the reached set: a reached tube whose FP32 mass underflows keeps the
+// smallest positive (denormal) value instead of zero (denormals are preserved in these
+// kernels), so the sum over a tube's contacts is non-zero iff one of them is reached.
+// The decision never looks at a mass beyond that test; the floor moves a mass by at
+// most 2^-149 per step.
 // Per tube a byte `code` holds deg (0..14) of a metallic tube, 15 for an insulating or
 // absent one. A metallic tube of degree 0 keeps its mass (self-loop, Sec. II.B).
 //
-// The state of one configuration is [U cells][CP] words, cell u holding layer 3u + sigma
-// of every column (see perc_internal.hpp). Work is cut into items: one tile of
-// consecutive columns x a range of cells. A workgroup walks its item along the fiber
-// axis, one thread per column of the tile: the tile's halo range of columns is staged
-// for the cells u-1, u, u+1 in a ring of LDS slots (column-major, kRing words per
-// column, two mirrored slots so that any three consecutive cells sit at consecutive
-// indices), cell u+3 is fetched into registers while cell u computes, and one barrier
-// separates cells. The 14 contacts of a tube are LDS reads at per-column byte offsets
-// held in registers for the whole walk plus a compile-time immediate for the ring
-// phase. All LDS of these kernels is dynamic, so the ring sits at address 0.
+// Cell u of column c holds layer 3u + sigma(c) (see perc_internal.hpp); the state of a
+// configuration is stored in groups of four cells (layout below). Work is cut into
+// items: one tile of consecutive columns x a range of cells. A workgroup walks its
+// item along the fiber axis, one thread per column of the tile: the tile's halo range
+// of columns is staged in an LDS ring of eight cell slots (plus two mirrored rows, so
+// that any three consecutive cells sit in consecutive rows), four-cell groups are
+// fetched two groups ahead, with two barriers per group. The 14 contacts of a tube
+// are LDS reads at per-column word offsets held in registers for the whole walk plus a
+// compile-time row offset. All LDS of these kernels is dynamic, so the ring sits at
+// address 0.
 #include <hip/hip_runtime.h>
 
 #include "perc_internal.hpp"
@@ -109,12 +111,35 @@ __device__ __forceinline__ void fill_rcp(float* rcp) {
 
 __device__ __forceinline__ float mag(uint32_t w) { return __uint_as_float(w & 0x7fffffffu); }
 
+// Smallest positive FP32 value (denormal): the mass a reached tube keeps at least.
+constexpr float kReachFloor = 1.40129846e-45f;
+
 struct TileV {
     int ts, te, hs, he;
 };
+// A value every lane of the workgroup reads from the same address, moved into scalar
+// registers (the compiler cannot prove such loads uniform when the kernel also
+// writes global memory).
+__device__ __forceinline__ int32_t uniform_i32(const int32_t* p) { return __builtin_amdgcn_readfirstlane(*p); }
+__device__ __forceinline__ int64_t uniform_i64(const int64_t* p) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(w[0]), hi = __builtin_amdgcn_readfirstlane(w[1]);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    T v;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return v;
+}
+
 __device__ __forceinline__ TileV load_tile(const DevShape& sh, int k) {
     const int32_t* p = sh.tile + 4 * k;
-    return TileV{p[0], p[1], p[2], p[3]};
+    return TileV{uniform_i32(p), uniform_i32(p + 1), uniform_i32(p + 2), uniform_i32(p + 3)};
 }
 
 // ------------------------------------------------------------------------------
@@ -130,23 +155,27 @@ __device__ __forceinline__ uint32_t word_of(const DevShape& sh, int u, int c) {
 }
 
 // ------------------------------------------------------------------------------
-// The ring (per staged column, kRing words): cell u in index (u mod 8) + 1, the slot-7
-// cell also in index 0 and the slot-0 cell also in index 9, so the cells u-1, u, u+1
-// sit at consecutive indices for every u. LDS column 0 is the zero pad column (missing
-// contacts), staged column lc is LDS column lc + 1, and staging lanes beyond the halo
-// range write to dummy columns after it, so that no LDS write is predicated.
+// The ring (ring_word in perc_internal.hpp): per staged column, cell u in row
+// (u mod 8) + 1, the slot-7 cell also in row 0 and the slot-0 cell also in row 9, so
+// the cells u-1, u, u+1 sit in consecutive rows for every u; rows are 64 words apart
+// within a block of 64 columns. LDS column 0 is the zero pad column (every missing
+// contact reads its row 0 plus the slot offset: one broadcast address), and staged
+// column lc is LDS column lc + 1.
 //
 // A walk covers whole groups from an 8-aligned cell, one cell per phase, eight phases
-// unrolled so that every ring slot is a compile-time constant; one barrier per cell.
-// At the second cell of group g the next group g+1 goes from registers into the ring
-// (its slots held group g-1, whose last cell the first cell of g needed) and group
-// g+2 is fetched: four cells of work between the issue of a load and its use. Global
+// unrolled so that every ring slot is a compile-time constant. At the second cell of
+// group g the next group g+1 goes from registers into the ring (its slots held group
+// g-1, whose last cell only the first cell of g reads) and group g+2 is fetched: four
+// cells of work between the issue of a load and its use. Two barriers per group
+// suffice: one before that write (after the first cell's reads) and one before the
+// last cell, the first to read group g+1. Global
 // loads are never predicated: the group index is clamped into the configuration and
 // the words are masked when written to the ring.
 // ------------------------------------------------------------------------------
 struct Stage {
     int col[kLoadCols];         // global column of each staged column of this thread (clamped)
-    uint32_t* slot[kLoadCols];  // its LDS column (a dummy column beyond the range)
+    uint32_t* slot[kLoadCols];  // its LDS column (row 0)
+    bool ok[kLoadCols];         // inside the halo range
     int nj;                     // staged column slots the workgroup needs (uniform)
 };
 
@@ -158,16 +187,16 @@ __device__ __forceinline__ Stage stage_columns(const TileV& tv) {
 #pragma unroll
     for (int j = 0; j < kLoadCols; ++j) {
         const int lc = (int)threadIdx.x + j * (int)blockDim.x;
-        const bool ok = lc < span;
-        st.col[j] = ok ? tv.hs + lc : tv.hs;
-        st.slot[j] = base + (ok ? lc + 1 : span + 1 + (int)(threadIdx.x & (kDummyCols - 1))) * kRing;
+        st.ok[j] = lc < span;
+        st.col[j] = st.ok[j] ? tv.hs + lc : tv.hs;
+        st.slot[j] = base + ring_word(0, st.ok[j] ? lc + 1 : 0);
     }
     return st;
 }
 
 // The pad column holds zeros.
 __device__ __forceinline__ void zero_pad() {
-    if (threadIdx.x < (unsigned)kRing) reinterpret_cast<uint32_t*>(lds)[threadIdx.x] = 0u;
+    if (threadIdx.x < (unsigned)kRows) reinterpret_cast<uint32_t*>(lds)[ring_word((int)threadIdx.x, 0)] = 0u;
 }
 
 // Four ring words v[0..3] of group g into ring slots S0 .. S0+3 (S0 = 0 or 4) of staged
@@ -180,11 +209,11 @@ __device__ __forceinline__ void put_quad(uint32_t* slot, int g, int vmax, uint4 
     const uint32_t b = (u + 1 >= 0 && u + 1 <= vmax) ? q.y : 0u;
     const uint32_t c = (u + 2 >= 0 && u + 2 <= vmax) ? q.z : 0u;
     const uint32_t d = (u + 3 >= 0 && u + 3 <= vmax) ? q.w : 0u;
-    slot[S0 + 1] = a;
-    slot[S0 + 2] = b;
-    slot[S0 + 3] = c;
-    slot[S0 + 4] = d;
-    if (S0 == 0) slot[kRingCells + 1] = a;
+    slot[(S0 + 1) * kBlkCols] = a;
+    slot[(S0 + 2) * kBlkCols] = b;
+    slot[(S0 + 3) * kBlkCols] = c;
+    slot[(S0 + 4) * kBlkCols] = d;
+    if (S0 == 0) slot[(kRingCells + 1) * kBlkCols] = a;
     if (S0 == 4) slot[0] = d;
 }
 
@@ -201,7 +230,7 @@ __device__ __forceinline__ void put_quads(const Stage& st, int g, int vmax, cons
 #pragma unroll
     for (int j = 0; j < kLoadCols; ++j) {
         if (j >= st.nj) break;
-        put_quad<S0>(st.slot[j], g, vmax, q[j]);
+        if (st.ok[j]) put_quad<S0>(st.slot[j], g, vmax, q[j]);
     }
 }
 
@@ -221,7 +250,7 @@ __device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
     const uint32_t* base = reinterpret_cast<const uint32_t*>(lds);
 #pragma unroll
     for (int i = 0; i < kSide; ++i) w.nb[i] = base + sh.nboff[i * sh.C + w.c];
-    w.me = base + (w.c - tv.hs + 1) * kRing;
+    w.me = base + ring_word(0, w.c - tv.hs + 1);
     w.top = sh.top[w.c];
     return w;
 }
@@ -241,22 +270,19 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
                                           StepState& ss) {
     constexpr int k = K & 3, par = K >> 2;
     const int u = u8 + K, g = u >> 2;
-    __syncthreads();
+    if (k & 1) __syncthreads();
     if (k == 1) {
         put_quads<(par ^ 1) * 4>(st, g + 1, vmax, ss.next);
         load_quads(sh, st, yin, g + 2, vmax, ss.next);
         ss.cq[par ^ 1] = code4[quad_of(sh, min(g + 1, (sh.U + 3) / 4 - 1), w.c)];
     }
     const uint32_t cd = (ss.cq[par] >> (8 * k)) & 0xffu;
-    const uint32_t own = w.me[K + 1];
-    const uint32_t dn = w.me[K];
-    const uint32_t up = w.me[K + 2];
+    const uint32_t own = w.me[(K + 1) * kBlkCols];
+    const uint32_t dn = w.me[K * kBlkCols];
+    const uint32_t up = w.me[(K + 2) * kBlkCols];
     uint32_t n[kSide];
 #pragma unroll
-    for (int i = 0; i < kSide; ++i) n[i] = w.nb[i][K];
-    uint32_t any = own | dn | up;
-#pragma unroll
-    for (int i = 0; i < kSide; ++i) any |= n[i];
+    for (int i = 0; i < kSide; ++i) n[i] = w.nb[i][K * kBlkCols];
     // fixed order: in-layer pairs, up/down-layer pairs, then the end contacts
     const float s01 = mag(n[0]) + mag(n[1]);
     const float s23 = mag(n[2]) + mag(n[3]);
@@ -268,13 +294,14 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
     const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
     // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its
     // own mass
-    const float x = sum + (cd == 0u ? mag(own) : 0.0f);
-    const uint32_t newr = (any >> 31) & (cd < 15u ? 1u : 0u) & (u < ue ? 1u : 0u);
-    const float yn = x * rcp[cd];
-    ss.res[k] = __float_as_uint(yn) | (newr << 31);
-    ss.grew |= newr & ~(own >> 31);
-    ss.far |= newr & (u == w.top ? 1u : 0u);
-    ss.entered |= newr & (u == front + 1 ? 1u : 0u);
+    const float x = sum + (cd == 0u ? __uint_as_float(own) : 0.0f);
+    // reached: metallic, and reached before or next to a reached tube
+    const bool reach = cd < 15u && (x != 0.0f || own != 0u) && u < ue;
+    ss.res[k] = __float_as_uint(fmaxf(x * rcp[cd], reach ? kReachFloor : 0.0f));
+    const uint32_t r = reach ? 1u : 0u;
+    ss.grew |= r & (own == 0u ? 1u : 0u);
+    ss.far |= r & (u == w.top ? 1u : 0u);
+    ss.entered |= r & (u == front + 1 ? 1u : 0u);
     if (k == 3)
         reinterpret_cast<uint4*>(yout)[quad_of(sh, g, w.c)] = make_uint4(ss.res[0], ss.res[1], ss.res[2], ss.res[3]);
 }
@@ -307,6 +334,7 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
     load_quads(sh, st, yin, g0 + 1, vmax, ss.next);
     ss.cq[0] = code4[quad_of(sh, g0, w.c)];
     ss.cq[1] = 0xffffffffu;
+    __syncthreads();
     for (int u8 = ub; u8 < ue; u8 += kRingCells) {
         step_cell<0>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
         step_cell<1>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
@@ -348,6 +376,7 @@ __device__ __forceinline__ void put_occ_quad(const DevShape& sh, const Stage& st
 #pragma unroll
     for (int j = 0; j < kLoadCols; ++j) {
         if (j >= st.nj) break;
+        if (!st.ok[j]) continue;
         uint32_t b[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -355,11 +384,11 @@ __device__ __forceinline__ void put_occ_quad(const DevShape& sh, const Stage& st
             const int64_t s = (int64_t)v * sh.C + rk[j];
             b[k] = (v >= 0 && v < sh.U && s < sh.N) ? (raw[k][j] >> (uint32_t)(s & 31)) & 1u : 0u;
         }
-        st.slot[j][S0 + 1] = b[0];
-        st.slot[j][S0 + 2] = b[1];
-        st.slot[j][S0 + 3] = b[2];
-        st.slot[j][S0 + 4] = b[3];
-        if (S0 == 0) st.slot[j][kRingCells + 1] = b[0];
+        st.slot[j][(S0 + 1) * kBlkCols] = b[0];
+        st.slot[j][(S0 + 2) * kBlkCols] = b[1];
+        st.slot[j][(S0 + 3) * kBlkCols] = b[2];
+        st.slot[j][(S0 + 4) * kBlkCols] = b[3];
+        if (S0 == 0) st.slot[j][(kRingCells + 1) * kBlkCols] = b[0];
         if (S0 == 4) st.slot[j][0] = b[3];
     }
 }
@@ -378,19 +407,19 @@ __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, c
                                           float* __restrict__ y0, int u8, int ue, float x0, InitState& is) {
     constexpr int k = K & 3, par = K >> 2;
     const int u = u8 + K, g = u >> 2;
-    __syncthreads();
+    if (k & 1) __syncthreads();
     if (k == 1) {
         put_occ_quad<(par ^ 1) * 4>(sh, st, rk, g + 1, is.next);
         load_occ_quad(sh, st, rk, bits, g + 2, is.next);
     }
-    const uint32_t me = w.me[K + 1];
-    uint32_t deg = w.me[K] + w.me[K + 2] + (u == w.top ? 1u : 0u);
+    const uint32_t me = w.me[(K + 1) * kBlkCols];
+    uint32_t deg = w.me[K * kBlkCols] + w.me[(K + 2) * kBlkCols] + (u == w.top ? 1u : 0u);
 #pragma unroll
-    for (int i = 0; i < kSide; ++i) deg += w.nb[i][K];
+    for (int i = 0; i < kSide; ++i) deg += w.nb[i][K * kBlkCols];
     const uint32_t cd = me ? deg : 15u;
     is.cq |= cd << (8 * k);
     if (u == 0 && me) {
-        is.y0 = __uint_as_float(__float_as_uint(x0 * rcp[cd]) | 0x80000000u);
+        is.y0 = x0 * rcp[cd];
         is.fl |= F_NONEMPTY;
         if (u == w.top) is.fl |= F_FAR;
     }
@@ -427,6 +456,7 @@ __device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& t
     load_occ_quad(sh, st, rk, bits, g0, raw);
     put_occ_quad<0>(sh, st, rk, g0, raw);
     load_occ_quad(sh, st, rk, bits, g0 + 1, is.next);
+    __syncthreads();
     for (int u8 = ub; u8 < ue; u8 += kRingCells) {
         init_cell<0>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
         init_cell<1>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
@@ -478,7 +508,7 @@ __device__ __forceinline__ void far_sum(const DevShape& sh, const float* __restr
             if (u < 0 || u > front) continue;
             const uint32_t w = __float_as_uint(y[word_of(sh, u, c)]);
             s += mag(w);
-            r |= w >> 31;
+            r |= w != 0u ? 1u : 0u;
         }
         part[v] = s;
         if (r) atomicOr(reached, 1u);
@@ -518,9 +548,20 @@ __device__ __forceinline__ int find_entry(const int64_t* off, int n, int64_t g) 
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= g) lo = mid; else hi = mid - 1;
+        if (uniform_i64(off + mid) <= g) lo = mid; else hi = mid - 1;
     }
-    return lo;
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// OR of a flag word over the workgroup, added to *dst: one atomic per wave that has a
+// flag (no barrier).
+__device__ __forceinline__ void flags_to(uint32_t* dst, uint32_t fl) {
+    uint32_t w = 0;
+    if (__ballot(fl & F_GREW)) w |= F_GREW;
+    if (__ballot(fl & F_FRONT)) w |= F_FRONT;
+    if (__ballot(fl & F_FAR)) w |= F_FAR;
+    if (__ballot(fl & F_NONEMPTY)) w |= F_NONEMPTY;
+    if (w && (threadIdx.x & 63) == 0) atomicOr(dst, w);
 }
 
 // ------------------------------------------------------------------------------
@@ -587,29 +628,22 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
     const Tail tl = lds_tail(a.lds);
     fill_rcp(tl.rcp);
     const int E = a.depth;
-    const ItemRange it = my_items(a.chunk_off[a.n_slot]);
+    const ItemRange it = my_items(uniform_i64(a.chunk_off + a.n_slot));
     for (int64_t g = it.begin; g < it.end; ++g) {
         const int b = find_entry(a.chunk_off, a.n_slot, g);
-        const DevShape sh = a.shapes[a.slot_shape[b]];
-        const int local = (int)(g - a.chunk_off[b]);
+        const DevShape sh = uniform_load(a.shapes + uniform_i32(a.slot_shape + b));
+        const int local = (int)(g - uniform_i64(a.chunk_off + b));
         const int r = local / sh.ntile, k = local - r * sh.ntile;
         const int ub = r * E;
-        const uint32_t* bits = a.slot_bits[b];
+        const uint32_t* bits = reinterpret_cast<const uint32_t*>(uniform_i64(reinterpret_cast<const int64_t*>(a.slot_bits + b)));
         float x0 = 0.0f;
         if (ub == 0) {
             const int n0 = count_start(sh, bits, tl.misc + 1);
             x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
         }
-        const uint32_t fl = walk_init(sh, load_tile(sh, k), tl.rcp, bits, a.code + a.slot_off[b],
-                                      a.ya + a.slot_off[b], ub, ub + E, x0);
-        if (ub == 0) {
-            __syncthreads();
-            if (threadIdx.x == 0) tl.misc[0] = 0;
-            __syncthreads();
-            if (fl) atomicOr(&tl.misc[0], fl);
-            __syncthreads();
-            if (threadIdx.x == 0 && tl.misc[0]) atomicOr(&a.st[b].flags, tl.misc[0]);
-        }
+        const int64_t off = uniform_i64(a.slot_off + b);
+        const uint32_t fl = walk_init(sh, load_tile(sh, k), tl.rcp, bits, a.code + off, a.ya + off, ub, ub + E, x0);
+        if (ub == 0) flags_to(&a.st[b].flags, fl);
     }
 }
 
@@ -696,33 +730,30 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
 __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
     const Tail tl = lds_tail(a.lds);
     fill_rcp(tl.rcp);
-    const int n_act = a.hdr[0];
+    const int n_act = uniform_i32(a.hdr);
     const int E = a.depth;
-    const ItemRange it = my_items(a.hdr[1]);
+    const ItemRange it = my_items(uniform_i32(a.hdr + 1));
     if (it.begin >= it.end) return;
     int lo = find_entry(a.chunk_off, n_act, it.begin);
-    int64_t lo_end = a.chunk_off[lo + 1];
+    int64_t lo_begin = uniform_i64(a.chunk_off + lo);
+    int64_t lo_end = uniform_i64(a.chunk_off + lo + 1);
     for (int64_t g = it.begin; g < it.end; ++g) {
         while (g >= lo_end) {  // next active slot
             ++lo;
-            lo_end = a.chunk_off[lo + 1];
+            lo_begin = lo_end;
+            lo_end = uniform_i64(a.chunk_off + lo + 1);
         }
-        const int b = a.active[lo];
-        const DevShape sh = a.shapes[a.slot_shape[b]];
-        const int local = (int)(g - a.chunk_off[lo]);
+        const int b = uniform_i32(a.active + lo);
+        const DevShape sh = uniform_load(a.shapes + uniform_i32(a.slot_shape + b));
+        const int local = (int)(g - lo_begin);
         const int r = local / sh.ntile, k = local - r * sh.ntile;
-        const CfgState s = a.st[b];
-        const int64_t off = a.slot_off[b];
+        const CfgState s = uniform_load(a.st + b);
+        const int64_t off = uniform_i64(a.slot_off + b);
         const float* yin = ((s.m & 1) ? a.yb : a.ya) + off;
         float* yout = ((s.m & 1) ? a.ya : a.yb) + off;
         const uint32_t fl = walk_step(sh, load_tile(sh, k), tl.rcp, yin, yout, a.code + off, r * E, r * E + E,
                                       s.front);
-        __syncthreads();
-        if (threadIdx.x == 0) tl.misc[0] = 0;
-        __syncthreads();
-        if (fl) atomicOr(&tl.misc[0], fl);
-        __syncthreads();
-        if (threadIdx.x == 0 && tl.misc[0]) atomicOr(&a.st[b].flags, tl.misc[0]);
+        flags_to(&a.st[b].flags, fl);
     }
 }
 
@@ -780,8 +811,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
         __syncthreads();
         const int64_t j = (int64_t)(((uint64_t)tl.misc[3] << 32) | tl.misc[2]);
         if (j >= a.n_jobs) break;
-        const Job job = a.jobs[j];
-        const DevShape sh = a.shapes[job.shape];
+        const Job job = uniform_load(a.jobs + j);
+        const DevShape sh = uniform_load(a.shapes + job.shape);
         const uint32_t* bits;
         if (job.bits) {
             bits = job.bits;
@@ -880,7 +911,7 @@ __global__ void __launch_bounds__(256) k_export(DevShape sh, const float* __rest
         float x = 0.0f;
         if (cd < 15u) x = mag(w) * (cd == 0u ? 1.0f : (float)cd);
         x_out[s] = x;
-        reach_out[s] = (uint8_t)(w >> 31);
+        reach_out[s] = (uint8_t)(w != 0u ? 1 : 0);
     }
 }
 

@@ -116,10 +116,10 @@ std::vector<uint32_t> contact_table(const LatticeDesc& d) {
             for (int i = 0; i < kSide; ++i) {
                 const int32_t v = d.nb[(size_t)i * d.C + c];
                 const int32_t col = v >> 2, dcp1 = v & 3;  // dcell + 1
-                // LDS column of the contact: 1 + its place in the staged range, or the
-                // zero pad column 0 for a missing contact
-                const int32_t lcol = col < d.C ? col - hs + 1 : 0;
-                t[(size_t)i * d.C + c] = (uint32_t)(lcol * kRing + dcp1);
+                // LDS word of the contact: column 1 + its place in the staged range; a
+                // missing contact reads row 0 of the zero pad column 0 (one address for
+                // all of them, so such reads broadcast)
+                t[(size_t)i * d.C + c] = col < d.C ? (uint32_t)ring_word(dcp1, col - hs + 1) : 0u;
             }
     }
     return t;

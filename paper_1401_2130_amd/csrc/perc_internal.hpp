@@ -9,6 +9,14 @@
 #include <string>
 #include <vector>
 
+#if defined(__HIPCC__)
+#define PERC_HD __host__ __device__
+#define PERC_HD_INLINE __host__ __device__ __forceinline__
+#else
+#define PERC_HD
+#define PERC_HD_INLINE inline
+#endif
+
 namespace perc {
 
 // ---------------------------------------------------------------------------------
@@ -63,25 +71,28 @@ bool build_lattice(int32_t W, int32_t L, LatticeDesc& out, std::string& err);
 // 4g+k of column c).
 inline int64_t state_words(const LatticeDesc& d) { return (int64_t)((d.U + 3) / 4) * 4 * d.CP; }
 
-// LDS words per staged column: a ring of eight cell slots at indices 1..8 (cell u in
-// slot (u mod 8) + 1), with index 0 mirroring the slot-7 cell and index 9 the slot-0
-// cell, so that the four cells u-1 .. u+2 around any even cell u sit at consecutive
-// indices; stride 11 (odd) keeps consecutive columns on different LDS banks.
-constexpr int kRing = 11;
+// The LDS ring of the walking kernels holds, per staged column, ten words: cell u in
+// row (u mod 8) + 1, with row 0 mirroring the slot-7 cell and row 9 the slot-0 cell,
+// so that the cells u-1, u, u+1 sit in consecutive rows for every u. Columns are
+// grouped in blocks of 64; a block stores its ten rows of 64 words one after another,
+// so word (row, lcol) is at (lcol / 64) * 640 + row * 64 + lcol % 64. Lanes reading
+// consecutive columns then hit consecutive banks whatever the row, and a row offset
+// is a compile-time multiple of 64 words.
+constexpr int kRows = 10;
 constexpr int kRingCells = 8;
-constexpr int kDummyCols = 64;  // staging lanes beyond the halo range write here
+constexpr int kBlkCols = 64;
+constexpr int kBlkWords = kRows * kBlkCols;
+PERC_HD_INLINE int32_t ring_word(int32_t row, int32_t lcol) {
+    return (lcol / kBlkCols) * kBlkWords + row * kBlkCols + lcol % kBlkCols;
+}
 
-// Contact table: for side contact i of column c (in tile k), the LDS word index
-// lcol * kRing + 1 + dcell of that contact for a tube in ring slot 0, lcol being 1 +
-// its column within the tile's staged range [halo first, halo end), or 0 (the zero pad
-// column) for a missing contact; a tube in slot s reads it at that index plus s.
+// Contact table: for side contact i of column c (in tile k), the LDS word
+// ring_word(1 + dcell, lcol) of that contact for a tube in ring slot 0, lcol being 1 +
+// its column within the tile's staged range [halo first, halo end); word 0 (row 0 of
+// the zero pad column 0) for a missing contact. A tube in slot s reads it s rows (64 s
+// words) further.
 std::vector<uint32_t> contact_table(const LatticeDesc& d);
 
-#if defined(__HIPCC__)
-#define PERC_HD __host__ __device__
-#else
-#define PERC_HD
-#endif
 
 // One lattice shape as the kernels see it (device pointers).
 struct DevShape {
@@ -103,13 +114,14 @@ struct LatticeDevice {
     int32_t* top = nullptr;
 };
 
-// Dynamic LDS of the walking kernels: the ring from address 0, (1 + span + kDummyCols)
-// columns x kRing words (pad column, staged range, dummy columns), then a fixed tail
-// (the last kLdsTail bytes of the launch's allocation): rcp (16 floats, 1/deg per
-// code), misc (16 words), part (256 floats).
+// Dynamic LDS of the walking kernels: the ring from address 0, 1 + span columns (pad
+// column, staged range) in whole blocks, then a fixed tail (the last kLdsTail bytes of
+// the launch's allocation): rcp (16 floats, 1/deg per code), misc (16 words), part
+// (256 floats).
 constexpr uint32_t kLdsTail = 64u + 64u + 1024u;
 PERC_HD inline uint32_t lds_total(int32_t span) {
-    return (((uint32_t)(span + 1 + kDummyCols) * (uint32_t)kRing * 4u + 15u) & ~15u) + kLdsTail;
+    const uint32_t blocks = (uint32_t)(span + 1 + kBlkCols - 1) / kBlkCols;
+    return blocks * kBlkWords * 4u + kLdsTail;
 }
 
 // ---------------------------------------------------------------------------------
