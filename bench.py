@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device to device (counter calibration runs)")
+    ap.add_argument("--copy-bandwidth-mib", type=int, default=1024,
+                    help="measure device-to-device copy bandwidth on this many MiB (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -176,6 +178,24 @@ def main():
             upd_plain += int(st.cpu().numpy().astype(np.int64).sum()) * lat.n
     log(f"plain form: {3 * k} configurations in {t_plain:.2f} s")
 
+    # achievable HBM bandwidth on this device: a plain device-to-device copy, timed with
+    # events on the same stream (bytes read + written per second)
+    copy_gbs = None
+    if args.copy_bandwidth_mib > 0:
+        src = torch.ones(args.copy_bandwidth_mib * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                dst.copy_(src)
+            e1.record(stream)
+        e1.synchronize()
+        copy_gbs = 2 * src.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+        del src, dst
+
     launches = max(prof["step_launches"], 1)
     step_s = prof["step_ms"] / 1e3
     alg_bytes = prof["tube_steps"] * BYTES_PER_TUBE_STEP
@@ -207,6 +227,7 @@ def main():
         "batched_over_plain": (value / (3 * k / t_plain)) if k > 0 else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "copy_gbs": copy_gbs, "frac_of_copy": (achieved / copy_gbs) if copy_gbs else None,
                      "kernel": STEP_KERNEL, "launches": prof["step_launches"],
                      "avg_launch_us": prof["step_ms"] / launches * 1e3,
                      "tube_steps_per_launch": prof["tube_steps"] / launches,

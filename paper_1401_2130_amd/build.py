@@ -36,8 +36,11 @@ def _flags():
     return ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 
 
-# device code: packed FP32 instructions stay off (the compiler must not form them)
-_DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# device code: packed FP32 instructions stay off (the compiler must not form them), and
+# FP32 denormals are kept: a reached tube's state word never drops below the smallest
+# denormal, which is how the kernels carry the exact reached set
+_DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                 "-fno-gpu-flush-denormals-to-zero"]
 _HOST_FLAGS = ["-x", "c++", f"-I{ROCM}/include", "-D__HIP_PLATFORM_AMD__=1"]
 
 

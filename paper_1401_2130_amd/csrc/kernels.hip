@@ -40,6 +40,8 @@ namespace {
 constexpr int kMaxBlock = 1024;
 constexpr int kXcds = 8;         // MI355X: workgroups are dealt round-robin over 8 XCDs
 constexpr int kLoadCols = 2;     // staged columns per thread: span <= 2 * blockDim
+// Smallest positive FP32 value (denormal): the mass a reached tube keeps at least.
+constexpr float kReachFloor = 1.40129846e-45f;
 
 extern __shared__ __align__(16) unsigned char lds[];
 
@@ -47,14 +49,14 @@ __device__ __forceinline__ void lds_put_u32(uint32_t off, uint32_t v) { *reinter
 
 // Fixed tail of the dynamic LDS of a launch of `total` bytes.
 struct Tail {
-    float* rcp;  // the 16 reciprocals
+    float4* ct;  // the code table
     uint32_t* misc;
     float* part;
 };
 __device__ __forceinline__ Tail lds_tail(int total) {
-    const uint32_t t = (uint32_t)total - kLdsTail;
-    return Tail{reinterpret_cast<float*>(lds + t), reinterpret_cast<uint32_t*>(lds + t + 64),
-                reinterpret_cast<float*>(lds + t + 128)};
+    const uint32_t t = (uint32_t)total - kLdsTail;  // a multiple of 16
+    return Tail{reinterpret_cast<float4*>(lds + t), reinterpret_cast<uint32_t*>(lds + t + 256),
+                reinterpret_cast<float*>(lds + t + 320)};
 }
 
 // ------------------------------------------------------------------------------
@@ -100,19 +102,21 @@ __device__ __forceinline__ uint32_t sample_word(int64_t w, int64_t N, uint64_t g
 
 __device__ __forceinline__ uint32_t shape_tag(const DevShape& sh) { return ((uint32_t)sh.W << 16) | (uint32_t)sh.L; }
 
-// 1/deg per code: code 0 keeps its mass (factor 1), 1..14 the correctly rounded
-// FP32 reciprocal, 15 (insulating) sends nothing.
-__device__ __forceinline__ void fill_rcp(float* rcp) {
+// Per degree code d, one 16-byte entry {1/deg, reach floor, self weight, 0}:
+//   1/deg  the correctly rounded FP32 reciprocal for d = 1..14; 1 for d = 0 (a metallic
+//          tube without metallic contact keeps its mass); 0 for 15 (insulating);
+//   floor  the smallest positive FP32 value for a metallic tube, 0 for an insulating one;
+//   self   1 for d = 0 (the self-loop adds the tube's own mass), else 0.
+__device__ __forceinline__ void fill_codes(float4* ct) {
     if (threadIdx.x < 16) {
         const int d = threadIdx.x;
-        rcp[d] = d == 0 ? 1.0f : (d == 15 ? 0.0f : 1.0f / (float)d);
+        ct[d] = make_float4(d == 0 ? 1.0f : (d == 15 ? 0.0f : 1.0f / (float)d), d < 15 ? kReachFloor : 0.0f,
+                            d == 0 ? 1.0f : 0.0f, 0.0f);
     }
 }
 
 __device__ __forceinline__ float mag(uint32_t w) { return __uint_as_float(w & 0x7fffffffu); }
 
-// Smallest positive FP32 value (denormal): the mass a reached tube keeps at least.
-constexpr float kReachFloor = 1.40129846e-45f;
 
 struct TileV {
     int ts, te, hs, he;
@@ -259,15 +263,16 @@ struct StepState {
     uint4 next[kLoadCols];  // staged quads of the group after the current one
     uint32_t cq[2];         // code quads, by group parity
     uint32_t res[4];        // new words of the current group
-    uint32_t grew = 0, far = 0, entered = 0;
+    uint32_t grew = 0;      // OR of the new words of tubes that were not reached before
+    uint32_t far = 0, entered = 0;
 };
 
 // Cell u = u8 + K (ring slot K) of a step walk.
 template <int K>
-__device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, const Own& w, const float* rcp,
+__device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, const Own& w, const float4* ct,
                                           const float* __restrict__ yin, float* __restrict__ yout,
-                                          const uint32_t* __restrict__ code4, int u8, int ue, int front, int vmax,
-                                          StepState& ss) {
+                                          const uint32_t* __restrict__ code4, int u8, int front, int vmax,
+                                          int top_min, StepState& ss) {
     constexpr int k = K & 3, par = K >> 2;
     const int u = u8 + K, g = u >> 2;
     if (k & 1) __syncthreads();
@@ -294,16 +299,28 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
     const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
     // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its
     // own mass
-    const float x = sum + (cd == 0u ? __uint_as_float(own) : 0.0f);
-    // reached: metallic, and reached before or next to a reached tube
-    const bool reach = cd < 15u && (x != 0.0f || own != 0u) && u < ue;
-    ss.res[k] = __float_as_uint(fmaxf(x * rcp[cd], reach ? kReachFloor : 0.0f));
-    const uint32_t r = reach ? 1u : 0u;
-    ss.grew |= r & (own == 0u ? 1u : 0u);
-    ss.far |= r & (u == w.top ? 1u : 0u);
-    ss.entered |= r & (u == front + 1 ? 1u : 0u);
-    if (k == 3)
+    const float4 t = ct[cd];
+    // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its own
+    // mass (self weight 1); for every other code the own word enters with weight 0
+    const float x = fmaf(__uint_as_float(own), t.z, sum);
+    // reached: metallic (the floor is 0 otherwise), and reached before or next to a
+    // reached tube. The new word is non-zero exactly for reached tubes: cells beyond
+    // the cut have no reached input, cells beyond U are coded insulating.
+    const float yn = fmaxf(x * t.x, (x != 0.0f || own != 0u) ? t.y : 0.0f);
+    ss.res[k] = __float_as_uint(yn);
+    ss.grew |= own == 0u ? ss.res[k] : 0u;
+    if (k == 3) {
+        const int u4 = u - 3;
         reinterpret_cast<uint4*>(yout)[quad_of(sh, g, w.c)] = make_uint4(ss.res[0], ss.res[1], ss.res[2], ss.res[3]);
+        // far-end tubes lie in the last cells of the fiber; the front cell in one group
+        if (u4 + 3 >= top_min) {
+            const int kt = w.top - u4;
+            ss.far |= kt == 0 ? ss.res[0] : kt == 1 ? ss.res[1] : kt == 2 ? ss.res[2] : kt == 3 ? ss.res[3] : 0u;
+        }
+        const int kf = front + 1 - u4;
+        if (kf >= 0 && kf < 4)
+            ss.entered |= kf == 0 ? ss.res[0] : kf == 1 ? ss.res[1] : kf == 2 ? ss.res[2] : ss.res[3];
+    }
 }
 
 // One Jacobi step of the tile's tubes in cells [ub, ue) (cut at min(U, front+2); ub a
@@ -313,12 +330,13 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
 // written for cells of the last group at or beyond the cut are zero (their inputs are
 // beyond the front) or lie in the padding beyond U: no other item writes them and no
 // reader uses them.
-__device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& tv, const float* rcp,
+__device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& tv, const float4* ct,
                                               const float* __restrict__ yin, float* __restrict__ yout,
                                               const uint8_t* __restrict__ code, int ub, int ue, int front) {
     ue = min(ue, min(sh.U, front + 2));
     if (ub >= ue) return 0u;
     const int vmax = min(front, sh.U - 1);
+    const int top_min = (sh.L - 3) / 3;  // no far-end tube lies in an earlier cell
     const uint32_t* code4 = reinterpret_cast<const uint32_t*>(code);
     const Stage st = stage_columns(tv);
     const Own w = own_column(sh, tv);
@@ -336,15 +354,15 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
     ss.cq[1] = 0xffffffffu;
     __syncthreads();
     for (int u8 = ub; u8 < ue; u8 += kRingCells) {
-        step_cell<0>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
-        step_cell<1>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
-        step_cell<2>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
-        step_cell<3>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        step_cell<0>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
+        step_cell<1>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
+        step_cell<2>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
+        step_cell<3>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
         if (u8 + 4 >= ue) break;
-        step_cell<4>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
-        step_cell<5>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
-        step_cell<6>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
-        step_cell<7>(sh, st, w, rcp, yin, yout, code4, u8, ue, front, vmax, ss);
+        step_cell<4>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
+        step_cell<5>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
+        step_cell<6>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
+        step_cell<7>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
     }
     return (ss.grew ? F_GREW : 0u) | (ss.far ? F_FAR : 0u) | (ss.entered ? F_FRONT : 0u);
 }
@@ -402,7 +420,7 @@ struct InitState {
 
 template <int K>
 __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, const Own& w,
-                                          const int (&rk)[kLoadCols], const float* rcp,
+                                          const int (&rk)[kLoadCols], const float4* ct,
                                           const uint32_t* __restrict__ bits, uint32_t* __restrict__ code4,
                                           float* __restrict__ y0, int u8, int ue, float x0, InitState& is) {
     constexpr int k = K & 3, par = K >> 2;
@@ -419,7 +437,7 @@ __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, c
     const uint32_t cd = me ? deg : 15u;
     is.cq |= cd << (8 * k);
     if (u == 0 && me) {
-        is.y0 = x0 * rcp[cd];
+        is.y0 = x0 * ct[cd].x;
         is.fl |= F_NONEMPTY;
         if (u == w.top) is.fl |= F_FAR;
     }
@@ -435,7 +453,7 @@ __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, c
 // 8) from the occupancy, and the start state (group 0): x0 = 1/|S0| on every metallic
 // start tube, reached. Returns the initialisation flags (start set non-empty, a start
 // tube on the far surface).
-__device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& tv, const float* rcp,
+__device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& tv, const float4* ct,
                                               const uint32_t* __restrict__ bits, uint8_t* __restrict__ code,
                                               float* __restrict__ y0, int ub, int ue, float x0) {
     ue = min(ue, sh.U);
@@ -458,15 +476,15 @@ __device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& t
     load_occ_quad(sh, st, rk, bits, g0 + 1, is.next);
     __syncthreads();
     for (int u8 = ub; u8 < ue; u8 += kRingCells) {
-        init_cell<0>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
-        init_cell<1>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
-        init_cell<2>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
-        init_cell<3>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        init_cell<0>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
+        init_cell<1>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
+        init_cell<2>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
+        init_cell<3>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
         if (u8 + 4 >= ue) break;
-        init_cell<4>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
-        init_cell<5>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
-        init_cell<6>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
-        init_cell<7>(sh, st, w, rk, rcp, bits, code4, y0, u8, ue, x0, is);
+        init_cell<4>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
+        init_cell<5>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
+        init_cell<6>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
+        init_cell<7>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
     }
     return is.fl;
 }
@@ -626,7 +644,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_layout(SpanArgs a) {
 // Initialisation of every slot: items (slot, cell range, tile) over all cells.
 __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
     const Tail tl = lds_tail(a.lds);
-    fill_rcp(tl.rcp);
+    fill_codes(tl.ct);
     const int E = a.depth;
     const ItemRange it = my_items(uniform_i64(a.chunk_off + a.n_slot));
     for (int64_t g = it.begin; g < it.end; ++g) {
@@ -642,7 +660,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
             x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
         }
         const int64_t off = uniform_i64(a.slot_off + b);
-        const uint32_t fl = walk_init(sh, load_tile(sh, k), tl.rcp, bits, a.code + off, a.ya + off, ub, ub + E, x0);
+        const uint32_t fl = walk_init(sh, load_tile(sh, k), tl.ct, bits, a.code + off, a.ya + off, ub, ub + E, x0);
         if (ub == 0) flags_to(&a.st[b].flags, fl);
     }
 }
@@ -729,7 +747,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
 // One step over the work list: items (active slot, cell range, tile).
 __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
     const Tail tl = lds_tail(a.lds);
-    fill_rcp(tl.rcp);
+    fill_codes(tl.ct);
     const int n_act = uniform_i32(a.hdr);
     const int E = a.depth;
     const ItemRange it = my_items(uniform_i32(a.hdr + 1));
@@ -751,7 +769,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
         const int64_t off = uniform_i64(a.slot_off + b);
         const float* yin = ((s.m & 1) ? a.yb : a.ya) + off;
         float* yout = ((s.m & 1) ? a.ya : a.yb) + off;
-        const uint32_t fl = walk_step(sh, load_tile(sh, k), tl.rcp, yin, yout, a.code + off, r * E, r * E + E,
+        const uint32_t fl = walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, a.code + off, r * E, r * E + E,
                                       s.front);
         flags_to(&a.st[b].flags, fl);
     }
@@ -763,9 +781,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
 __global__ void __launch_bounds__(kMaxBlock) k_chunk_step(DevShape sh, const float* yin, float* yout,
                                                           const uint8_t* code, int E, int lds_bytes) {
     const Tail tl = lds_tail(lds_bytes);
-    fill_rcp(tl.rcp);
+    fill_codes(tl.ct);
     const int r = blockIdx.x / sh.ntile, k = blockIdx.x - r * sh.ntile;
-    (void)walk_step(sh, load_tile(sh, k), tl.rcp, yin, yout, code, r * E, r * E + E, sh.U);
+    (void)walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, code, r * E, r * E + E, sh.U);
 }
 
 // Per slot: first-hit probability of a percolating configuration (the detector mass at
@@ -796,7 +814,7 @@ __global__ void __launch_bounds__(256) k_span_finish(SpanArgs a) {
 
 __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
     const Tail tl = lds_tail(a.lds);
-    fill_rcp(tl.rcp);
+    fill_codes(tl.ct);
     const int E = a.depth;
     float* ya = a.ya + blockIdx.x * a.state_stride;
     float* yb = a.yb + blockIdx.x * a.state_stride;
@@ -829,7 +847,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
         const float x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
         uint32_t f = 0;
         for (int ub = 0; ub < sh.U; ub += E)
-            for (int k = 0; k < sh.ntile; ++k) f |= walk_init(sh, load_tile(sh, k), tl.rcp, bits, code, ya, ub, ub + E, x0);
+            for (int k = 0; k < sh.ntile; ++k) f |= walk_init(sh, load_tile(sh, k), tl.ct, bits, code, ya, ub, ub + E, x0);
         __syncthreads();
         if (threadIdx.x == 0) tl.misc[0] = 0;
         __syncthreads();
@@ -846,7 +864,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
             uint32_t fl = 0;
             for (int ub = 0; ub < ulim; ub += E)
                 for (int k = 0; k < sh.ntile; ++k)
-                    fl |= walk_step(sh, load_tile(sh, k), tl.rcp, yin, yout, code, ub, ub + E, front);
+                    fl |= walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, code, ub, ub + E, front);
             __syncthreads();
             if (threadIdx.x == 0) tl.misc[0] = 0;
             __syncthreads();

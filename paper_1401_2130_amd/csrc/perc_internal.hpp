@@ -116,9 +116,9 @@ struct LatticeDevice {
 
 // Dynamic LDS of the walking kernels: the ring from address 0, 1 + span columns (pad
 // column, staged range) in whole blocks, then a fixed tail (the last kLdsTail bytes of
-// the launch's allocation): rcp (16 floats, 1/deg per code), misc (16 words), part
-// (256 floats).
-constexpr uint32_t kLdsTail = 64u + 64u + 1024u;
+// the launch's allocation): the code table (16 x 16 bytes: 1/deg, reach floor, self
+// weight per degree code), misc (16 words), part (256 floats).
+constexpr uint32_t kLdsTail = 256u + 64u + 1024u;
 PERC_HD inline uint32_t lds_total(int32_t span) {
     const uint32_t blocks = (uint32_t)(span + 1 + kBlkCols - 1) / kBlkCols;
     return blocks * kBlkWords * 4u + kLdsTail;
