@@ -190,6 +190,77 @@ typedef struct perc_profile {
 int perc_profile_enable(int32_t on);
 int perc_profile_read(perc_profile* out);
 
+/* ---- serving: continuous batching of single inspections -------------------------- */
+/* A server keeps the state of every admitted inspection resident on the GPU and advances
+ * all of them together, a tick at a time; requests that arrive meanwhile wait in a FIFO
+ * queue and are admitted at the next tick as a slot and HBM (the pool below) free up.
+ * A request is one configuration: fiber (W, L), metallic probability p, the Philox
+ * configuration cfg of stream seed (the same draw as perc_pi_ex's configuration cfg and
+ * perc_batch's Philox jobs), so its result is bitwise the result of inspecting that
+ * configuration alone (Sec. II.B method, outputs as perc_inspect_ex). */
+typedef struct perc_server perc_server;
+
+typedef struct perc_server_config {
+    int64_t hbm_bytes;   /* device pool for resident state (0: half the free memory, <= 64 GiB) */
+    int32_t max_slots;   /* inspections in flight at once (0: 1024) */
+    int32_t tick_steps;  /* iteration steps per tick (0: 16) */
+    int32_t max_w;       /* widest fiber accepted (0: 64; at most 128) */
+    int32_t host_only;   /* 1: no GPU work, every admitted request completes at the next
+                            tick with status PERC_OK and zero outputs (scheduler tests) */
+    perc_options opt;    /* item length (depth), block, grid of the step launches */
+} perc_server_config;
+
+typedef struct perc_result {
+    uint64_t tag;        /* the caller's request id */
+    int32_t W, L;
+    double p;
+    uint64_t seed, cfg;
+    int32_t status;      /* PERC_OK, or PERC_ECAP if the step cap was reached */
+    uint8_t perc;        /* percolates */
+    int32_t steps;       /* as perc_inspect */
+    float hit;           /* first-hit probability at the stop (0 if not percolating) */
+    int64_t t_arrive_ns, t_admit_ns, t_done_ns;  /* host steady clock */
+} perc_result;
+
+typedef struct perc_server_stats {
+    int64_t queued, in_flight, completed, ticks;
+    int64_t pool_bytes, pool_used_bytes;
+} perc_server_stats;
+
+/* Create a server on the current device, working on `stream` (hipStream_t or NULL); the
+ * server owns its device memory (allocated here, freed by destroy). NULL on failure
+ * (see perc_last_error). */
+perc_server* perc_server_create(const perc_server_config* cfg, void* stream);
+void perc_server_destroy(perc_server* srv);
+
+/* Queue one request; t_arrive_ns < 0 stamps the current steady-clock time. PERC_EINVAL
+ * for W outside [0, max_w], L outside [1, 2^22], p outside [0, 1], or a request whose
+ * resident state would exceed the pool. */
+int perc_server_submit(perc_server* srv, int32_t W, int32_t L, double p, uint64_t seed, uint64_t cfg, uint64_t tag,
+                       int64_t t_arrive_ns);
+
+/* One tick: admit queued requests (FIFO; a request that does not fit waits, and so do
+ * the ones behind it), sample and initialise them, advance every resident inspection by
+ * tick_steps steps, retire the finished ones. Returns the number retired (>= 0) or an
+ * error. Synchronous. */
+int perc_server_tick(perc_server* srv);
+
+/* Move up to max finished results (retirement order) into out; returns the count. */
+int perc_server_poll(perc_server* srv, perc_result* out, int32_t max);
+int perc_server_stats_read(const perc_server* srv, perc_server_stats* out);
+
+/* Serve a whole request stream natively: request i arrives t_arrive_ns[i] after the
+ * start (non-decreasing); the loop submits arrivals as their time comes, ticks while
+ * anything is queued or in flight, sleeps otherwise, and writes the n results (in
+ * retirement order, t_arrive_ns on the same clock as t_done_ns) to out. */
+typedef struct perc_request {
+    int64_t t_arrive_ns;
+    int32_t W, L;
+    double p;
+    uint64_t seed, cfg, tag;
+} perc_request;
+int perc_server_run(perc_server* srv, const perc_request* reqs, int64_t n, perc_result* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,27 @@ class perc_job(C.Structure):
                 ("cfg", C.c_int64), ("group", C.c_int32)]
 
 
+class perc_server_config(C.Structure):
+    _fields_ = [("hbm_bytes", C.c_int64), ("max_slots", C.c_int32), ("tick_steps", C.c_int32), ("max_w", C.c_int32),
+                ("host_only", C.c_int32), ("opt", perc_options)]
+
+
+class perc_result(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("W", C.c_int32), ("L", C.c_int32), ("p", C.c_double), ("seed", C.c_uint64),
+                ("cfg", C.c_uint64), ("status", C.c_int32), ("perc", C.c_uint8), ("steps", C.c_int32),
+                ("hit", C.c_float), ("t_arrive_ns", C.c_int64), ("t_admit_ns", C.c_int64), ("t_done_ns", C.c_int64)]
+
+
+class perc_server_stats(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("in_flight", C.c_int64), ("completed", C.c_int64), ("ticks", C.c_int64),
+                ("pool_bytes", C.c_int64), ("pool_used_bytes", C.c_int64)]
+
+
+class perc_request(C.Structure):
+    _fields_ = [("t_arrive_ns", C.c_int64), ("W", C.c_int32), ("L", C.c_int32), ("p", C.c_double),
+                ("seed", C.c_uint64), ("cfg", C.c_uint64), ("tag", C.c_uint64)]
+
+
 class perc_pi_out(C.Structure):
     _fields_ = [("n_perc", C.c_int64), ("pi", C.c_double), ("bits", C.c_void_p), ("steps", C.c_void_p),
                 ("hit", C.c_void_p)]
@@ -77,6 +98,14 @@ def _load():
     lib.perc_batch.argtypes = [C.POINTER(perc_job), i64, vp, vp, vp, vp, i32, C.POINTER(perc_options), vp]
     lib.perc_profile_enable.argtypes = [i32]
     lib.perc_profile_read.argtypes = [C.POINTER(perc_profile)]
+    lib.perc_server_create.restype = vp
+    lib.perc_server_create.argtypes = [C.POINTER(perc_server_config), vp]
+    lib.perc_server_destroy.argtypes = [vp]
+    lib.perc_server_submit.argtypes = [vp, i32, i32, dbl, C.c_uint64, C.c_uint64, C.c_uint64, i64]
+    lib.perc_server_tick.argtypes = [vp]
+    lib.perc_server_poll.argtypes = [vp, C.POINTER(perc_result), i32]
+    lib.perc_server_stats_read.argtypes = [vp, C.POINTER(perc_server_stats)]
+    lib.perc_server_run.argtypes = [vp, C.POINTER(perc_request), i64, C.POINTER(perc_result)]
     return lib
 
 
@@ -85,7 +114,9 @@ _lib = _load()
 EXPORTED = ("perc_lattice_create", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
             "perc_last_error", "perc_sample", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
-            "perc_batch", "perc_state_after", "perc_profile_enable", "perc_profile_read")
+            "perc_batch", "perc_state_after", "perc_profile_enable", "perc_profile_read", "perc_server_create",
+            "perc_server_destroy", "perc_server_submit", "perc_server_tick", "perc_server_poll",
+            "perc_server_stats_read", "perc_server_run")
 
 
 def perc_last_error() -> str:
@@ -300,3 +331,70 @@ def perc_state_after(lat: Lattice, occ: torch.Tensor, K: int, x=None, reach=None
                                  _dptr(x, torch.float32, lat.n + 1), _dptr(reach, torch.uint8, lat.n + 1),
                                  _stream(stream)))
     return x, reach
+
+
+# ---------------------------------------------------------------------------------
+# serving (continuous batching of single inspections)
+# ---------------------------------------------------------------------------------
+
+_RESULT_KEYS = ("tag", "W", "L", "p", "seed", "cfg", "status", "perc", "steps", "hit", "t_arrive_ns", "t_admit_ns",
+                "t_done_ns")
+
+
+def _result_dict(r: perc_result) -> dict:
+    return {k: getattr(r, k) for k in _RESULT_KEYS}
+
+
+class perc_server:
+    """A serving instance (``perc_server_create``): requests of single configurations
+    (W, L, p, seed, cfg) are admitted by HBM footprint as slots free up and advanced
+    together, a tick at a time; the state of every admitted request stays on the GPU."""
+
+    def __init__(self, hbm_bytes: int = 0, max_slots: int = 0, tick_steps: int = 0, max_w: int = 0,
+                 host_only: bool = False, depth: int = 0, block: int = 0, grid: int = 0, stream=None):
+        cfg = perc_server_config(int(hbm_bytes), int(max_slots), int(tick_steps), int(max_w), 1 if host_only else 0,
+                                 _options("span", depth, block, grid, 0))
+        self._lib = _lib
+        self._stream = stream  # the server works on this stream; keep it alive as long
+        self.handle = _lib.perc_server_create(C.byref(cfg), None if host_only else _stream(stream))
+        if not self.handle:
+            raise PercError(PERC_EINVAL, perc_last_error())
+
+    def __del__(self):
+        h, lib = getattr(self, "handle", None), getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.perc_server_destroy(h)
+            self.handle = None
+
+    def submit(self, W: int, L: int, p: float, seed: int, cfg: int = 0, tag: int = 0, t_arrive_ns: int = -1):
+        _check(_lib.perc_server_submit(self.handle, int(W), int(L), float(p), int(seed), int(cfg), int(tag),
+                                       int(t_arrive_ns)))
+
+    def tick(self) -> int:
+        rc = _lib.perc_server_tick(self.handle)
+        if rc < 0:
+            _check(rc)
+        return rc
+
+    def poll(self, max_results: int = 4096) -> list:
+        buf = (perc_result * max_results)()
+        n = _lib.perc_server_poll(self.handle, buf, int(max_results))
+        if n < 0:
+            _check(n)
+        return [_result_dict(buf[i]) for i in range(n)]
+
+    def stats(self) -> dict:
+        st = perc_server_stats()
+        _check(_lib.perc_server_stats_read(self.handle, C.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in perc_server_stats._fields_}
+
+    def run(self, requests) -> list:
+        """Serve a request stream natively (``perc_server_run``): requests are
+        (t_arrive_s, W, L, p, seed, cfg, tag) with non-decreasing arrival offsets."""
+        n = len(requests)
+        reqs = (perc_request * max(n, 1))()
+        for i, (t, W, L, p, seed, cfg, tag) in enumerate(requests):
+            reqs[i] = perc_request(int(round(t * 1e9)), int(W), int(L), float(p), int(seed), int(cfg), int(tag))
+        out = (perc_result * max(n, 1))()
+        _check(_lib.perc_server_run(self.handle, reqs, n, out))
+        return [_result_dict(out[i]) for i in range(n)]

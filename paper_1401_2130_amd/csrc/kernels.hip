@@ -117,6 +117,13 @@ __device__ __forceinline__ void fill_codes(float4* ct) {
 
 __device__ __forceinline__ float mag(uint32_t w) { return __uint_as_float(w & 0x7fffffffu); }
 
+// Cell of the far-end tube of column c: the highest layer k < L with k = sigma (mod 3),
+// or -1 if the column holds no tube.
+__device__ __forceinline__ int top_of(const DevShape& sh, int c) {
+    const int sg = sh.sig[c];
+    return sg < sh.L ? (sh.L - 1 - sg) / 3 : -1;
+}
+
 
 struct TileV {
     int ts, te, hs, he;
@@ -255,7 +262,7 @@ __device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
 #pragma unroll
     for (int i = 0; i < kSide; ++i) w.nb[i] = base + sh.nboff[i * sh.C + w.c];
     w.me = base + ring_word(0, w.c - tv.hs + 1);
-    w.top = sh.top[w.c];
+    w.top = top_of(sh, w.c);
     return w;
 }
 
@@ -522,7 +529,7 @@ __device__ __forceinline__ void far_sum(const DevShape& sh, const float* __restr
         float s = 0.0f;
         uint32_t r = 0;
         for (int c = v; c < sh.C; c += 256) {
-            const int u = sh.top[c];
+            const int u = top_of(sh, c);
             if (u < 0 || u > front) continue;
             const uint32_t w = __float_as_uint(y[word_of(sh, u, c)]);
             s += mag(w);
@@ -579,6 +586,7 @@ __device__ __forceinline__ void flags_to(uint32_t* dst, uint32_t fl) {
     if (__ballot(fl & F_FRONT)) w |= F_FRONT;
     if (__ballot(fl & F_FAR)) w |= F_FAR;
     if (__ballot(fl & F_NONEMPTY)) w |= F_NONEMPTY;
+    if (__ballot(fl & F_STEPPED)) w |= F_STEPPED;
     if (w && (threadIdx.x & 63) == 0) atomicOr(dst, w);
 }
 
@@ -613,16 +621,22 @@ __global__ void __launch_bounds__(256) k_sample_slots(const DevShape* shapes, co
 }
 
 // Item layout of the initialisation (all cells of every slot) and the slot states.
+// Slots to initialise: the listed ones (a.ids), else all.
+__device__ __forceinline__ int init_count(const SpanArgs& a) { return a.ids ? a.n_ids : a.n_slot; }
+__device__ __forceinline__ int init_slot(const SpanArgs& a, int i) { return a.ids ? a.ids[i] : i; }
+
 __global__ void __launch_bounds__(kMaxBlock) k_span_layout(SpanArgs a) {
     __shared__ int64_t sums[kMaxBlock];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int per = (a.n_slot + nt - 1) / nt;
-    const int i0 = min(a.n_slot, tid * per), i1 = min(a.n_slot, i0 + per);
+    const int n = init_count(a);
+    const int per = (n + nt - 1) / nt;
+    const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
     int64_t mine = 0;
-    for (int b = i0; b < i1; ++b) {
+    for (int i = i0; i < i1; ++i) {
+        const int b = init_slot(a, i);
         const DevShape& sh = a.shapes[a.slot_shape[b]];
         mine += items_of(sh, sh.U, a.depth);
-        a.st[b] = CfgState{0, 0, 0, 0u};
+        a.st[b] = CfgState{0, -1, 0, 0u};  // m = -1: initialised, not yet decided
     }
     sums[tid] = mine;
     __syncthreads();
@@ -633,12 +647,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_layout(SpanArgs a) {
         __syncthreads();
     }
     int64_t pos = sums[tid] - mine;
-    for (int b = i0; b < i1; ++b) {
-        a.chunk_off[b] = pos;
-        const DevShape& sh = a.shapes[a.slot_shape[b]];
+    for (int i = i0; i < i1; ++i) {
+        a.chunk_off[i] = pos;
+        const DevShape& sh = a.shapes[a.slot_shape[init_slot(a, i)]];
         pos += items_of(sh, sh.U, a.depth);
     }
-    if (tid == nt - 1) a.chunk_off[a.n_slot] = sums[nt - 1];
+    if (tid == nt - 1) a.chunk_off[n] = sums[nt - 1];
 }
 
 // Initialisation of every slot: items (slot, cell range, tile) over all cells.
@@ -646,11 +660,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
     const Tail tl = lds_tail(a.lds);
     fill_codes(tl.ct);
     const int E = a.depth;
-    const ItemRange it = my_items(uniform_i64(a.chunk_off + a.n_slot));
+    const int n = init_count(a);
+    const ItemRange it = my_items(uniform_i64(a.chunk_off + n));
     for (int64_t g = it.begin; g < it.end; ++g) {
-        const int b = find_entry(a.chunk_off, a.n_slot, g);
+        const int i = find_entry(a.chunk_off, n, g);
+        const int b = a.ids ? uniform_i32(a.ids + i) : i;
         const DevShape sh = uniform_load(a.shapes + uniform_i32(a.slot_shape + b));
-        const int local = (int)(g - uniform_i64(a.chunk_off + b));
+        const int local = (int)(g - uniform_i64(a.chunk_off + i));
         const int r = local / sh.ntile, k = local - r * sh.ntile;
         const int ub = r * E;
         const uint32_t* bits = reinterpret_cast<const uint32_t*>(uniform_i64(reinterpret_cast<const int64_t*>(a.slot_bits + b)));
@@ -665,10 +681,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
     }
 }
 
-// Decide every active configuration from the flags of the last launch, write the
-// outputs of those that stopped, and lay out the items of the next step for the rest.
-// did_step = 0 right after initialisation. One workgroup of kMaxBlock threads.
-__global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_step, int first) {
+// Decide every listed configuration (all slots if first, else the active list) from
+// its flags, write the outputs of those that stopped (and list them in a.fin), and lay
+// out the items of the next step for the rest. A slot just initialised (m = -1) gets
+// the initial decision; a slot the last step launch touched (F_STEPPED) the step
+// decision; any other keeps its state (it is only laid out again). One workgroup of
+// kMaxBlock threads.
+__global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) {
     __shared__ int32_t keep_s[kMaxBlock];
     __shared__ int64_t chunk_s[kMaxBlock];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -686,10 +705,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
         s.flags = 0;
         int dec = -1;  // -1 continue, 0 no, 1 yes
         int32_t steps = 0;
-        if (!did_step) {
+        if (s.m < 0) {
+            s.m = 0;
             if (!(f & F_NONEMPTY)) { dec = 0; steps = 0; }
             else if (f & F_FAR) { dec = 1; steps = 1; }
-        } else {
+        } else if (f & F_STEPPED) {
             s.m += 1;
             if (f & F_FRONT) s.front += 1;
             if (f & F_FAR) { dec = 1; steps = s.m + 1; }
@@ -700,6 +720,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int did_ste
             if (s.done == 0) s.done = 1;
             a.out.perc[b] = (uint8_t)dec;
             a.out.steps[b] = steps;
+            if (a.fin) a.fin[atomicAdd(a.hdr + 3, 1)] = b;
         } else {
             keep += 1;
             chunks += items_of(sh, min(sh.U, s.front + 2), E);
@@ -771,7 +792,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
         float* yout = ((s.m & 1) ? a.ya : a.yb) + off;
         const uint32_t fl = walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, a.code + off, r * E, r * E + E,
                                       s.front);
-        flags_to(&a.st[b].flags, fl);
+        flags_to(&a.st[b].flags, fl | (threadIdx.x < 64 ? F_STEPPED : 0u));
     }
 }
 
@@ -792,7 +813,9 @@ __global__ void __launch_bounds__(256) k_span_finish(SpanArgs a) {
     __shared__ float part[256];
     __shared__ uint32_t reached;
     __shared__ float result;
-    for (int b = blockIdx.x; b < a.n_slot; b += gridDim.x) {
+    const int n = a.fin ? a.hdr[3] : a.n_slot;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int b = a.fin ? a.fin[i] : i;
         const int pc = a.out.perc[b];
         if (threadIdx.x == 0 && a.out.group_count && a.out.group && pc) {
             const int grp = a.out.group[b];
@@ -1016,7 +1039,7 @@ hipError_t launch_span_init_only(const SpanArgs& a, hipStream_t s) {
 hipError_t launch_span_init(const SpanArgs& a, hipStream_t s) {
     hipError_t e = launch_span_init_only(a, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_span_plan, dim3(1), dim3(kMaxBlock), 0, s, a, 0, 1);
+    hipLaunchKernelGGL(k_span_plan, dim3(1), dim3(kMaxBlock), 0, s, a, 1);
     return hipGetLastError();
 }
 
@@ -1026,13 +1049,13 @@ hipError_t launch_span_step(const SpanArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_span_plan(const SpanArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_span_plan, dim3(1), dim3(kMaxBlock), 0, s, a, 1, 0);
+    hipLaunchKernelGGL(k_span_plan, dim3(1), dim3(kMaxBlock), 0, s, a, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_span_finish(const SpanArgs& a, hipStream_t s) {
     if (!a.out.hit && !a.out.group_count) return hipSuccess;
-    const int grid = std::min(a.n_slot, 4096);
+    const int grid = std::min(a.fin ? std::max(a.n_slot, 1) : a.n_slot, 4096);
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_span_finish, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -4,6 +4,7 @@
 // neighbours) and 2 end contacts (the next tube of the same column) per tube.
 #include <algorithm>
 #include <cstdlib>
+#include <map>
 
 #include "perc_internal.hpp"
 
@@ -23,13 +24,10 @@ constexpr int kSideOff[kSide][3] = {
     {0, 1, -1}, {-1, 0, -1}, {1, -1, -1},
 };
 
-}  // namespace
-
-bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
-    if (W < 0 || W > 1024) { err = "W must be in [0, 1024]"; return false; }
-    if (L < 1 || L > (1 << 22)) { err = "L must be in [1, 4194304]"; return false; }
-    d = LatticeDesc{};
-    d.W = W; d.L = L;
+std::shared_ptr<ColumnSet> build_columns(int32_t W) {
+    auto cs = std::make_shared<ColumnSet>();
+    ColumnSet& d = *cs;
+    d.W = W;
     // internal column order: (q, r) lexicographic, so that every contact of a column
     // lies within two q-rows of it
     for (int q = -W; q <= W; ++q)
@@ -37,7 +35,6 @@ bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
             if (hexdist(q, r) <= W) { d.q.push_back(q); d.r.push_back(r); d.sig.push_back(mod3(q - r)); }
     const int C = (int)d.q.size();
     d.C = C;
-    d.U = (L + 2) / 3;
     d.CP = std::max(32, ((C + 31) / 32) * 32);
     // canonical rank: (sigma, q, r) order inside a cell = lexicographic (k, q, r) overall
     std::vector<int32_t> by_canon(C);
@@ -50,23 +47,7 @@ bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
     d.rank.assign(C, 0);
     d.by_rank = by_canon;
     for (int k = 0; k < C; ++k) d.rank[by_canon[k]] = k;
-    d.top.resize(C);
-    for (int c = 0; c < C; ++c) {
-        d.nsig[d.sig[c]]++;
-        // far-end tube: the highest layer k < L with k = sig (mod 3)
-        d.top[c] = d.sig[c] < L ? (L - 1 - d.sig[c]) / 3 : -1;
-    }
-    // sites: every column of every full cell, then the columns of the last cell whose
-    // layer exists (a prefix in canonical rank)
-    int64_t n = (int64_t)(d.U - 1) * C;
-    const int k_last = 3 * (d.U - 1);
-    for (int c = 0; c < C; ++c)
-        if (k_last + d.sig[c] < L) ++n;
-    d.N = n;
-    d.words = (n + 31) / 32;
-    if (n > (int64_t)INT32_MAX) { err = "lattice exceeds 2^31 - 1 sites"; return false; }
-    // state arrays are indexed with 32-bit offsets inside one configuration
-    if (state_words(d) > (int64_t)INT32_MAX) { err = "lattice state exceeds 2^31 - 1 words"; return false; }
+    for (int c = 0; c < C; ++c) d.nsig[d.sig[c]]++;
     const int S = 2 * W + 1;
     std::vector<int32_t> index((size_t)S * S, -1);
     for (int c = 0; c < C; ++c) index[(size_t)(d.q[c] + W) * S + (d.r[c] + W)] = c;
@@ -104,25 +85,62 @@ bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
         d.span_max = std::max(d.span_max, he - hs);
         d.tile_max = std::max(d.tile_max, te - ts);
     }
-    return true;
-}
-
-std::vector<uint32_t> contact_table(const LatticeDesc& d) {
-    std::vector<uint32_t> t((size_t)kSide * d.C);
-    for (int k = 0; k < d.ntile; ++k) {
+    // contact table: LDS word of each side contact within its tile's staged range
+    d.contact.assign((size_t)kSide * C, 0u);
+    for (int k = 0; k < nt; ++k) {
         const int ts = d.tile[k * 4 + 0], te = d.tile[k * 4 + 1];
         const int hs = d.tile[k * 4 + 2];
         for (int c = ts; c < te; ++c)
             for (int i = 0; i < kSide; ++i) {
-                const int32_t v = d.nb[(size_t)i * d.C + c];
+                const int32_t v = d.nb[(size_t)i * C + c];
                 const int32_t col = v >> 2, dcp1 = v & 3;  // dcell + 1
                 // LDS word of the contact: column 1 + its place in the staged range; a
                 // missing contact reads row 0 of the zero pad column 0 (one address for
                 // all of them, so such reads broadcast)
-                t[(size_t)i * d.C + c] = col < d.C ? (uint32_t)ring_word(dcp1, col - hs + 1) : 0u;
+                d.contact[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col - hs + 1) : 0u;
             }
     }
-    return t;
+    return cs;
+}
+
+std::mutex g_cols_mu;
+std::map<int32_t, std::shared_ptr<const ColumnSet>> g_cols;
+
+}  // namespace
+
+std::shared_ptr<const ColumnSet> column_set(int32_t W, std::string& err) {
+    if (W < 0 || W > 1024) { err = "W must be in [0, 1024]"; return nullptr; }
+    std::lock_guard<std::mutex> g(g_cols_mu);
+    auto it = g_cols.find(W);
+    if (it != g_cols.end()) return it->second;
+    std::shared_ptr<const ColumnSet> cs = build_columns(W);
+    g_cols.emplace(W, cs);
+    return cs;
+}
+
+bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
+    if (W < 0 || W > 1024) { err = "W must be in [0, 1024]"; return false; }
+    if (L < 1 || L > (1 << 22)) { err = "L must be in [1, 4194304]"; return false; }
+    d = LatticeDesc{};
+    d.cs = column_set(W, err);
+    if (!d.cs) return false;
+    const ColumnSet& cs = *d.cs;
+    d.W = W; d.L = L;
+    d.C = cs.C; d.CP = cs.CP;
+    d.ntile = cs.ntile; d.span_max = cs.span_max; d.tile_max = cs.tile_max;
+    d.U = (L + 2) / 3;
+    // sites: every column of every full cell, then the columns of the last cell whose
+    // layer exists (a prefix in canonical rank: sigma < L - 3 (U - 1))
+    const int k_last = 3 * (d.U - 1);
+    int64_t n = (int64_t)(d.U - 1) * d.C;
+    for (int sg = 0; sg < 3; ++sg)
+        if (k_last + sg < L) n += cs.nsig[sg];
+    d.N = n;
+    d.words = (n + 31) / 32;
+    if (n > (int64_t)INT32_MAX) { err = "lattice exceeds 2^31 - 1 sites"; return false; }
+    // state arrays are indexed with 32-bit offsets inside one configuration
+    if (state_words(d) > (int64_t)INT32_MAX) { err = "lattice state exceeds 2^31 - 1 words"; return false; }
+    return true;
 }
 
 }  // namespace perc

@@ -7,6 +7,9 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -21,8 +24,6 @@ using namespace perc;
 
 struct perc_lattice {
     LatticeDesc d;
-    std::mutex mu;
-    std::vector<LatticeDevice> dev;
 };
 
 namespace {
@@ -74,35 +75,45 @@ int upload(T** dst, const std::vector<T>& src) {
     return PERC_OK;
 }
 
-int shape_for(const perc_lattice* lat_c, DevShape& sh) {
-    perc_lattice* lat = const_cast<perc_lattice*>(lat_c);
+// Device tables of each column set, per device: uploaded on first use and kept for the
+// process (one set per fiber width in use; every fiber length shares them).
+std::mutex g_coldev_mu;
+std::map<std::pair<int, int32_t>, ColumnDevice> g_coldev;
+
+int column_device(const ColumnSet& cs, int dev, ColumnDevice& out) {
+    std::lock_guard<std::mutex> g(g_coldev_mu);
+    auto it = g_coldev.find({dev, cs.W});
+    if (it != g_coldev.end()) {
+        out = it->second;
+        return PERC_OK;
+    }
+    ColumnDevice n;
+    PERC_TRY(upload(&n.nboff, cs.contact));
+    PERC_TRY(upload(&n.tile, cs.tile));
+    PERC_TRY(upload(&n.rank, cs.rank));
+    PERC_TRY(upload(&n.sig, cs.sig));
+    g_coldev.emplace(std::make_pair(dev, cs.W), n);
+    out = n;
+    return PERC_OK;
+}
+
+int shape_of(const LatticeDesc& d, DevShape& sh) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     PERC_TRY(prepare(dev));
-    const LatticeDesc& d = lat->d;
-    std::lock_guard<std::mutex> g(lat->mu);
-    LatticeDevice* ld = nullptr;
-    for (auto& x : lat->dev)
-        if (x.device == dev) ld = &x;
-    if (!ld) {
-        LatticeDevice n;
-        n.device = dev;
-        PERC_TRY(upload(&n.nboff, contact_table(d)));
-        PERC_TRY(upload(&n.tile, d.tile));
-        PERC_TRY(upload(&n.rank, d.rank));
-        PERC_TRY(upload(&n.top, d.top));
-        lat->dev.push_back(n);
-        ld = &lat->dev.back();
-    }
-    sh.nboff = ld->nboff;
-    sh.tile = ld->tile;
-    sh.rank = ld->rank;
-    sh.top = ld->top;
+    ColumnDevice cd;
+    PERC_TRY(column_device(*d.cs, dev, cd));
+    sh.nboff = cd.nboff;
+    sh.tile = cd.tile;
+    sh.rank = cd.rank;
+    sh.sig = cd.sig;
     sh.C = d.C; sh.CP = d.CP; sh.U = d.U; sh.L = d.L;
     sh.ntile = d.ntile; sh.span_max = d.span_max; sh.tile_max = d.tile_max; sh.W = d.W;
     sh.N = d.N; sh.words = d.words;
     return PERC_OK;
 }
+
+int shape_for(const perc_lattice* lat, DevShape& sh) { return shape_of(lat->d, sh); }
 
 // ---------------------------------------------------------------------------------
 // Stream-ordered work memory: one allocation carved into aligned pieces.
@@ -650,6 +661,472 @@ int pi_impl(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, per
     return PERC_OK;
 }
 
+// ---------------------------------------------------------------------------------
+// Serving: continuous batching of single inspections (see perc.h).
+// ---------------------------------------------------------------------------------
+
+// First-fit allocator of [0, capacity) in whole units, free blocks coalesced.
+class RangeAlloc {
+public:
+    void reset(int64_t capacity) {
+        free_.clear();
+        if (capacity > 0) free_[0] = capacity;
+        used_ = 0;
+    }
+    int64_t alloc(int64_t n) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const int64_t off = it->first, rest = it->second - n;
+            free_.erase(it);
+            if (rest > 0) free_[off + n] = rest;
+            used_ += n;
+            return off;
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t n) {
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t used() const { return used_; }
+
+private:
+    std::map<int64_t, int64_t> free_;
+    int64_t used_ = 0;
+};
+
+// occupancy words of one request in the server pool (16-word granules)
+int64_t server_bits_words(const LatticeDesc& d) { return (d.words + 15) & ~(int64_t)15; }
+
+int64_t steady_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct ServerSlot {
+    bool busy = false;
+    perc_result res{};
+    int64_t state_off = 0, state_words = 0, bits_off = 0, bits_n = 0;
+    int32_t shape = -1;
+    int64_t seq = 0;  // admission order
+};
+
+}  // namespace
+
+struct perc_server {
+    perc_server_config cfg{};
+    hipStream_t s = nullptr;
+    bool host_only = false;
+    // device pools: state words (two FP32 buffers and the codes share offsets), occupancy
+    char* mem = nullptr;
+    float* ya = nullptr;
+    float* yb = nullptr;
+    uint8_t* code = nullptr;
+    uint32_t* bits = nullptr;
+    int64_t state_cap = 0, bits_cap = 0, pool_bytes = 0;
+    RangeAlloc state_alloc, bits_alloc;
+    // per-slot device arrays and the planner's work list
+    SpanArgs a{};
+    DevShape* d_shapes = nullptr;
+    int32_t* d_slot_shape = nullptr;
+    int64_t* d_slot_off = nullptr;
+    const uint32_t** d_slot_bits = nullptr;
+    Job* d_new_jobs = nullptr;
+    uint32_t** d_new_bits = nullptr;
+    int32_t* d_ids = nullptr;
+    // pinned host staging: hdr (16), fin (max_slots), perc, steps, hit, upload of ids
+    char* pin = nullptr;
+    int32_t* h_hdr = nullptr;
+    int32_t* h_fin = nullptr;
+    uint8_t* h_perc = nullptr;
+    int32_t* h_steps = nullptr;
+    float* h_hit = nullptr;
+    int32_t* h_ids = nullptr;
+    Job* h_new_jobs = nullptr;
+    uint32_t** h_new_bits = nullptr;
+    CfgState* h_st = nullptr;
+    // host mirrors
+    std::vector<DevShape> shapes;
+    std::vector<int32_t> shape_ref;
+    std::map<std::pair<int32_t, int32_t>, int32_t> shape_of_wl;
+    std::vector<int32_t> free_shapes;
+    std::vector<int32_t> h_slot_shape;
+    std::vector<int64_t> h_slot_off;
+    std::vector<const uint32_t*> h_slot_bits;
+    std::vector<ServerSlot> slots;
+    std::vector<int32_t> free_slots;
+    std::deque<perc_result> queue;
+    std::deque<perc_result> done;
+    int32_t n_act = 0;
+    int64_t ticks = 0, completed = 0, admitted = 0;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int32_t kServerMaxW = 128;
+
+void server_release(perc_server* v) {
+    if (!v) return;
+    if (v->exec) (void)hipGraphExecDestroy(v->exec);
+    if (v->mem) (void)hipFree(v->mem);
+    if (v->pin) (void)hipHostFree(v->pin);
+    delete v;
+}
+
+template <typename T>
+T* carve(char*& p, int64_t n) {
+    T* r = reinterpret_cast<T*>(p);
+    p += ((int64_t)sizeof(T) * std::max<int64_t>(n, 1) + 255) & ~(int64_t)255;
+    return r;
+}
+
+int server_init(perc_server* v, const perc_server_config* cfg, hipStream_t s) {
+    v->cfg = cfg ? *cfg : perc_server_config{};
+    perc_server_config& c = v->cfg;
+    if (c.max_slots <= 0) c.max_slots = 1024;
+    if (c.tick_steps <= 0) c.tick_steps = 16;
+    if (c.max_w <= 0) c.max_w = 64;
+    if (c.max_slots > (1 << 20)) return fail(PERC_EINVAL, "max_slots must be <= 2^20");
+    if (c.tick_steps > 4096) return fail(PERC_EINVAL, "tick_steps must be <= 4096");
+    if (c.max_w > kServerMaxW) return fail(PERC_EINVAL, "max_w must be <= 128");
+    v->s = s;
+    v->host_only = c.host_only != 0;
+    const int32_t M = c.max_slots;
+    if (c.hbm_bytes <= 0) {
+        if (v->host_only) return fail(PERC_EINVAL, "host_only needs an explicit hbm_bytes");
+        size_t free_b = 0, total_b = 0;
+        HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+        c.hbm_bytes = std::min<int64_t>((int64_t)(free_b / 2), 64ll << 30);
+    }
+    // pool: per state word 9 bytes (two FP32 buffers, one code byte), occupancy words an
+    // eighth of the state words (a tube needs 1/32 of a word, rounded per request)
+    const int64_t unit = 9 * 16 + 2 * 4;
+    const int64_t blocks = c.hbm_bytes / unit;
+    v->state_cap = blocks * 16;
+    v->bits_cap = blocks * 2;
+    v->pool_bytes = v->state_cap * 9 + v->bits_cap * 4;
+    if (v->state_cap < 64) return fail(PERC_EINVAL, "hbm_bytes too small");
+    v->state_alloc.reset(v->state_cap);
+    v->bits_alloc.reset(v->bits_cap);
+    v->slots.assign(M, ServerSlot{});
+    for (int32_t b = M - 1; b >= 0; --b) v->free_slots.push_back(b);
+    v->h_slot_shape.assign(M, 0);
+    v->h_slot_off.assign(M, 0);
+    v->h_slot_bits.assign(M, nullptr);
+    if (v->host_only) return PERC_OK;
+
+    // launch shape: one thread per column of the widest tile of any accepted width
+    ShapeNeed nd;
+    for (int32_t w = 0; w <= c.max_w; ++w) {
+        std::string err;
+        auto cs = column_set(w, err);
+        if (!cs) return fail(PERC_EINVAL, err);
+        nd.span_max = std::max(nd.span_max, cs->span_max);
+        nd.tile_max = std::max(nd.tile_max, cs->tile_max);
+        nd.C = std::max(nd.C, cs->C);
+    }
+    Tuning tu;
+    perc_options o = c.opt;
+    o.form = FORM_SPAN;
+    PERC_TRY(resolve(nd, 0, 1, &o, tu, nullptr));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    PERC_TRY(prepare(dev));
+    // one device allocation for the pools and every per-slot array (carved below; each
+    // piece rounded to 256 bytes)
+    auto al = [](int64_t b) { return (std::max<int64_t>(b, 1) + 255) & ~(int64_t)255; };
+    const int64_t bytes = al(4 * v->state_cap) * 2 + al(v->state_cap) + al(4 * v->bits_cap) +
+                          al((int64_t)sizeof(DevShape) * M) + al(4ll * M) + al(8ll * M) + al(8ll * M) +
+                          al((int64_t)sizeof(Job) * M) + al(8ll * M) + al(4ll * M) + al((int64_t)sizeof(CfgState) * M) +
+                          al(4ll * M) * 2 + al(8ll * (M + 1)) + al(64) + al(4ll * M) + al(M) + al(4ll * M) * 2;
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&v->mem), (size_t)bytes));
+    char* p = v->mem;
+    v->ya = carve<float>(p, v->state_cap);
+    v->yb = carve<float>(p, v->state_cap);
+    v->code = carve<uint8_t>(p, v->state_cap);
+    v->bits = carve<uint32_t>(p, v->bits_cap);
+    v->d_shapes = carve<DevShape>(p, M);
+    v->d_slot_shape = carve<int32_t>(p, M);
+    v->d_slot_off = carve<int64_t>(p, M);
+    v->d_slot_bits = carve<const uint32_t*>(p, M);
+    v->d_new_jobs = carve<Job>(p, M);
+    v->d_new_bits = carve<uint32_t*>(p, M);
+    v->d_ids = carve<int32_t>(p, M);
+    SpanArgs& a = v->a;
+    a = SpanArgs{};
+    a.st = carve<CfgState>(p, M);
+    a.active = carve<int32_t>(p, M);
+    a.active2 = carve<int32_t>(p, M);
+    a.chunk_off = carve<int64_t>(p, M + 1);
+    a.hdr = carve<int32_t>(p, 16);
+    a.fin = carve<int32_t>(p, M);
+    a.out.perc = carve<uint8_t>(p, M);
+    a.out.steps = carve<int32_t>(p, M);
+    a.out.hit = carve<float>(p, M);
+    a.shapes = v->d_shapes;
+    a.slot_shape = v->d_slot_shape;
+    a.slot_off = v->d_slot_off;
+    a.slot_bits = v->d_slot_bits;
+    a.ya = v->ya;
+    a.yb = v->yb;
+    a.code = v->code;
+    a.work = nullptr;
+    a.n_slot = M;
+    a.depth = tu.depth;
+    a.block = tu.block;
+    a.grid = tu.grid ? tu.grid : 2048;
+    a.lds = (int)lds_total(nd.span_max);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.hdr), 16, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.st), (int64_t)M * 4, 0u, s));
+    const size_t pin_bytes =
+        64 + (size_t)M * (4 + 1 + 4 + 4 + 4) + (size_t)M * (sizeof(Job) + sizeof(void*) + sizeof(CfgState)) + 1024;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&v->pin), pin_bytes, hipHostMallocDefault));
+    char* q = v->pin;
+    v->h_hdr = reinterpret_cast<int32_t*>(q); q += 64;
+    v->h_fin = reinterpret_cast<int32_t*>(q); q += (size_t)M * 4;
+    v->h_steps = reinterpret_cast<int32_t*>(q); q += (size_t)M * 4;
+    v->h_hit = reinterpret_cast<float*>(q); q += (size_t)M * 4;
+    v->h_ids = reinterpret_cast<int32_t*>(q); q += (size_t)M * 4;
+    q = reinterpret_cast<char*>(((uintptr_t)q + 15) & ~(uintptr_t)15);
+    v->h_new_jobs = reinterpret_cast<Job*>(q); q += (size_t)M * sizeof(Job);
+    v->h_new_bits = reinterpret_cast<uint32_t**>(q); q += (size_t)M * sizeof(void*);
+    v->h_st = reinterpret_cast<CfgState*>(q); q += (size_t)M * sizeof(CfgState);
+    v->h_perc = reinterpret_cast<uint8_t*>(q);
+    HIP_TRY(hipStreamSynchronize(s));
+    return PERC_OK;
+}
+
+int server_shape(perc_server* v, const LatticeDesc& d, int32_t& idx) {
+    auto key = std::make_pair(d.W, d.L);
+    auto it = v->shape_of_wl.find(key);
+    if (it != v->shape_of_wl.end()) {
+        idx = it->second;
+        v->shape_ref[idx] += 1;
+        return PERC_OK;
+    }
+    DevShape sh{};
+    if (!v->host_only) PERC_TRY(shape_of(d, sh));
+    if (!v->free_shapes.empty()) {
+        idx = v->free_shapes.back();
+        v->free_shapes.pop_back();
+        v->shapes[idx] = sh;
+        v->shape_ref[idx] = 1;
+    } else {
+        idx = (int32_t)v->shapes.size();
+        v->shapes.push_back(sh);
+        v->shape_ref.push_back(1);
+    }
+    v->shape_of_wl[key] = idx;
+    return PERC_OK;
+}
+
+void server_unshape(perc_server* v, int32_t idx, int32_t W, int32_t L) {
+    if (--v->shape_ref[idx] == 0) {
+        v->shape_of_wl.erase(std::make_pair(W, L));
+        v->free_shapes.push_back(idx);
+    }
+}
+
+void server_retire(perc_server* v, int32_t b, int64_t now) {
+    ServerSlot& sl = v->slots[b];
+    sl.res.t_done_ns = now;
+    v->done.push_back(sl.res);
+    v->state_alloc.release(sl.state_off, sl.state_words);
+    v->bits_alloc.release(sl.bits_off, sl.bits_n);
+    server_unshape(v, sl.shape, sl.res.W, sl.res.L);
+    sl.busy = false;
+    v->free_slots.push_back(b);
+    v->completed += 1;
+}
+
+// Admit queued requests in FIFO order while a slot and pool room are free.
+int server_admit(perc_server* v, std::vector<int32_t>& new_ids) {
+    const int64_t now = steady_ns();
+    while (!v->queue.empty() && !v->free_slots.empty()) {
+        const perc_result& r = v->queue.front();
+        LatticeDesc d;
+        std::string err;
+        if (!build_lattice(r.W, r.L, d, err)) return fail(PERC_EINVAL, err);
+        const int64_t sw = slot_words(d), bw = server_bits_words(d);
+        const int64_t so = v->state_alloc.alloc(sw);
+        if (so < 0) break;
+        const int64_t bo = v->bits_alloc.alloc(bw);
+        if (bo < 0) {
+            v->state_alloc.release(so, sw);
+            break;
+        }
+        int32_t idx = -1;
+        PERC_TRY(server_shape(v, d, idx));
+        const int32_t b = v->free_slots.back();
+        v->free_slots.pop_back();
+        ServerSlot& sl = v->slots[b];
+        sl.busy = true;
+        sl.res = r;
+        sl.res.t_admit_ns = now;
+        sl.state_off = so;
+        sl.state_words = sw;
+        sl.bits_off = bo;
+        sl.bits_n = bw;
+        sl.shape = idx;
+        sl.seq = v->admitted++;
+        v->queue.pop_front();
+        v->h_slot_shape[b] = idx;
+        v->h_slot_off[b] = so;
+        v->h_slot_bits[b] = v->bits ? v->bits + bo : nullptr;
+        new_ids.push_back(b);
+    }
+    return PERC_OK;
+}
+
+int server_tick(perc_server* v) {
+    std::vector<int32_t> new_ids;
+    PERC_TRY(server_admit(v, new_ids));
+    v->ticks += 1;
+    if (v->host_only) {
+        // fake executor: every request admitted before this tick completes now, in
+        // admission order
+        std::vector<std::pair<int64_t, int32_t>> fin;
+        for (int32_t b = 0; b < (int32_t)v->slots.size(); ++b) {
+            const ServerSlot& sl = v->slots[b];
+            if (sl.busy && std::find(new_ids.begin(), new_ids.end(), b) == new_ids.end()) fin.emplace_back(sl.seq, b);
+        }
+        std::sort(fin.begin(), fin.end());
+        const int64_t now = steady_ns();
+        for (const auto& f : fin) {
+            v->slots[f.second].res.status = PERC_OK;
+            server_retire(v, f.second, now);
+        }
+        return (int)fin.size();
+    }
+    hipStream_t s = v->s;
+    SpanArgs& a = v->a;
+    const int32_t k = (int32_t)new_ids.size();
+    if (k > 0) {
+        for (int32_t i = 0; i < k; ++i) {
+            const int32_t b = new_ids[i];
+            const perc_result& r = v->slots[b].res;
+            v->h_ids[i] = b;
+            v->h_new_jobs[i] = Job{nullptr, r.seed, r.cfg, threshold_of(r.p), v->h_slot_shape[b], -1};
+            v->h_new_bits[i] = const_cast<uint32_t*>(v->h_slot_bits[b]);
+        }
+        HIP_TRY(hipMemcpyAsync(v->d_shapes, v->shapes.data(), sizeof(DevShape) * v->shapes.size(),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(v->d_slot_shape, v->h_slot_shape.data(), sizeof(int32_t) * v->slots.size(),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(v->d_slot_off, v->h_slot_off.data(), sizeof(int64_t) * v->slots.size(),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(v->d_slot_bits, v->h_slot_bits.data(), sizeof(void*) * v->slots.size(),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(v->d_ids, v->h_ids, sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(v->d_new_jobs, v->h_new_jobs, sizeof(Job) * k, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(v->d_new_bits, v->h_new_bits, sizeof(void*) * k, hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_sample_slots(v->d_shapes, v->d_new_jobs, k, v->d_new_bits, s));
+        SpanArgs ai = a;
+        ai.ids = v->d_ids;
+        ai.n_ids = k;
+        HIP_TRY(launch_span_init_only(ai, s));
+        // the new slots join the active list; the planner gives them their initial
+        // decision and lays out the next step for every active slot
+        HIP_TRY(hipMemcpyAsync(a.active + v->n_act, v->h_ids, sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+        v->h_hdr[0] = v->n_act + k;
+        HIP_TRY(hipMemcpyAsync(a.hdr, v->h_hdr, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_span_plan(a, s));
+        v->n_act += k;
+    }
+    if (v->n_act > 0 || k > 0) {
+        if (!v->exec && s) {
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = hipSuccess;
+            for (int i = 0; i < v->cfg.tick_steps && ce == hipSuccess; ++i) {
+                ce = launch_span_step(a, s);
+                if (ce == hipSuccess) ce = launch_span_plan(a, s);
+            }
+            hipError_t ee = hipStreamEndCapture(s, &graph);
+            if (ce != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return hip_fail(ce, "capture");
+            }
+            if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+            hipError_t ie = hipGraphInstantiate(&v->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+        }
+        if (v->exec) {
+            HIP_TRY(hipGraphLaunch(v->exec, s));
+        } else {
+            for (int i = 0; i < v->cfg.tick_steps; ++i) {
+                HIP_TRY(launch_span_step(a, s));
+                HIP_TRY(launch_span_plan(a, s));
+            }
+        }
+        HIP_TRY(launch_span_finish(a, s));
+    }
+    const int32_t M = (int32_t)v->slots.size();
+    HIP_TRY(hipMemcpyAsync(v->h_hdr, a.hdr, 64, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(v->h_fin, a.fin, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(v->h_perc, a.out.perc, M, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(v->h_steps, a.out.steps, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(v->h_hit, a.out.hit, sizeof(float) * M, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(v->h_st, a.st, sizeof(CfgState) * M, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t now = steady_ns();
+    const int32_t nfin = v->h_hdr[3];
+    const bool cap = v->h_hdr[2] != 0;
+    for (int32_t i = 0; i < nfin; ++i) {
+        const int32_t b = v->h_fin[i];
+        ServerSlot& sl = v->slots[b];
+        sl.res.perc = v->h_perc[b];
+        sl.res.steps = v->h_steps[b];
+        sl.res.hit = v->h_hit[b];
+        sl.res.status = v->h_st[b].done == 2 ? PERC_ECAP : PERC_OK;
+        server_retire(v, b, now);
+    }
+    v->n_act = v->h_hdr[0];
+    if (nfin > 0 || cap) {
+        v->h_hdr[2] = 0;
+        v->h_hdr[3] = 0;
+        HIP_TRY(hipMemcpyAsync(a.hdr + 2, v->h_hdr + 2, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return nfin;
+}
+
+int server_submit(perc_server* v, int32_t W, int32_t L, double p, uint64_t seed, uint64_t cfg, uint64_t tag,
+                  int64_t t_arrive) {
+    if (W < 0 || W > v->cfg.max_w) return fail(PERC_EINVAL, "W outside [0, max_w]");
+    if (!(p >= 0.0 && p <= 1.0)) return fail(PERC_EINVAL, "p must be in [0, 1]");
+    LatticeDesc d;
+    std::string err;
+    if (!build_lattice(W, L, d, err)) return fail(PERC_EINVAL, err);
+    if (slot_words(d) > v->state_cap || server_bits_words(d) > v->bits_cap)
+        return fail(PERC_EINVAL, "the request's resident state exceeds the server pool");
+    perc_result r{};
+    r.tag = tag;
+    r.W = W;
+    r.L = L;
+    r.p = p;
+    r.seed = seed;
+    r.cfg = cfg;
+    r.t_arrive_ns = t_arrive >= 0 ? t_arrive : steady_ns();
+    v->queue.push_back(r);
+    return PERC_OK;
+}
+
 }  // namespace
 
 // =================================================================================
@@ -672,21 +1149,7 @@ perc_lattice* perc_lattice_create(int32_t W, int32_t L) {
     return lat;
 }
 
-void perc_lattice_destroy(perc_lattice* lat) {
-    if (!lat) return;
-    int cur = 0;
-    const bool have = hipGetDevice(&cur) == hipSuccess;
-    for (auto& x : lat->dev) {
-        if (hipSetDevice(x.device) == hipSuccess) {
-            (void)hipFree(x.nboff);
-            (void)hipFree(x.tile);
-            (void)hipFree(x.rank);
-            (void)hipFree(x.top);
-        }
-    }
-    if (have) (void)hipSetDevice(cur);
-    delete lat;
-}
+void perc_lattice_destroy(perc_lattice* lat) { delete lat; }
 
 int64_t perc_lattice_sites(const perc_lattice* lat) { return lat ? lat->d.N : -1; }
 int64_t perc_lattice_words(const perc_lattice* lat) { return lat ? lat->d.words : -1; }
@@ -697,11 +1160,12 @@ int perc_site_coord(const perc_lattice* lat, int64_t s, int32_t* q, int32_t* r, 
     PERC_TRY(validate_lat(lat));
     const LatticeDesc& d = lat->d;
     if (s < 0 || s >= d.N) return fail(PERC_EINVAL, "site index out of range");
+    const ColumnSet& cs = *d.cs;
     const int64_t u = s / d.C;
-    const int32_t c = d.by_rank[s - u * d.C];
-    if (q) *q = d.q[c];
-    if (r) *r = d.r[c];
-    if (k) *k = (int32_t)(3 * u + d.sig[c]);
+    const int32_t c = cs.by_rank[s - u * d.C];
+    if (q) *q = cs.q[c];
+    if (r) *r = cs.r[c];
+    if (k) *k = (int32_t)(3 * u + cs.sig[c]);
     return PERC_OK;
 }
 
@@ -709,16 +1173,17 @@ int perc_site_neighbors(const perc_lattice* lat, int64_t s, int64_t* nbr, int32_
     PERC_TRY(validate_lat(lat));
     const LatticeDesc& d = lat->d;
     if (s < 0 || s >= d.N || !nbr || !count) return fail(PERC_EINVAL, "bad site or NULL output");
+    const ColumnSet& cs = *d.cs;
     const int64_t u = s / d.C;
-    const int32_t c = d.by_rank[s - u * d.C];
+    const int32_t c = cs.by_rank[s - u * d.C];
     std::vector<int64_t> out;
     auto add = [&](int64_t uu, int32_t cc) {
         if (uu < 0 || uu >= d.U || cc >= d.C) return;
-        const int64_t t = uu * d.C + d.rank[cc];
+        const int64_t t = uu * d.C + cs.rank[cc];
         if (t < d.N) out.push_back(t);
     };
     for (int i = 0; i < kSide; ++i) {
-        const int32_t v = d.nb[(size_t)i * d.C + c];
+        const int32_t v = cs.nb[(size_t)i * d.C + c];
         add(u + ((v & 3) - 1), v >> 2);
     }
     add(u - 1, c);
@@ -891,6 +1356,88 @@ int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t 
         std::swap(cur, nxt);
     }
     HIP_TRY(launch_export(sh, cur, code, det, det_r, x_out, reach_out, s));
+    return PERC_OK;
+}
+
+
+perc_server* perc_server_create(const perc_server_config* cfg, void* stream) {
+    perc_server* v = new (std::nothrow) perc_server();
+    if (!v) {
+        g_err = "out of host memory";
+        return nullptr;
+    }
+    if (server_init(v, cfg, reinterpret_cast<hipStream_t>(stream)) != PERC_OK) {
+        server_release(v);
+        return nullptr;
+    }
+    return v;
+}
+
+void perc_server_destroy(perc_server* srv) {
+    if (srv && srv->s && !srv->host_only) (void)hipStreamSynchronize(srv->s);
+    server_release(srv);
+}
+
+int perc_server_submit(perc_server* srv, int32_t W, int32_t L, double p, uint64_t seed, uint64_t cfg, uint64_t tag,
+                       int64_t t_arrive_ns) {
+    if (!srv) return fail(PERC_EINVAL, "server is NULL");
+    return server_submit(srv, W, L, p, seed, cfg, tag, t_arrive_ns);
+}
+
+int perc_server_tick(perc_server* srv) {
+    if (!srv) return fail(PERC_EINVAL, "server is NULL");
+    return server_tick(srv);
+}
+
+int perc_server_poll(perc_server* srv, perc_result* out, int32_t max) {
+    if (!srv || (!out && max > 0) || max < 0) return fail(PERC_EINVAL, "bad poll arguments");
+    int32_t n = 0;
+    while (n < max && !srv->done.empty()) {
+        out[n++] = srv->done.front();
+        srv->done.pop_front();
+    }
+    return n;
+}
+
+int perc_server_stats_read(const perc_server* srv, perc_server_stats* out) {
+    if (!srv || !out) return fail(PERC_EINVAL, "NULL argument");
+    out->queued = (int64_t)srv->queue.size();
+    out->in_flight = (int64_t)(srv->slots.size() - srv->free_slots.size());
+    out->completed = srv->completed;
+    out->ticks = srv->ticks;
+    out->pool_bytes = srv->pool_bytes;
+    out->pool_used_bytes = srv->state_alloc.used() * 9 + srv->bits_alloc.used() * 4;
+    return PERC_OK;
+}
+
+int perc_server_run(perc_server* srv, const perc_request* reqs, int64_t n, perc_result* out) {
+    if (!srv || n < 0 || (n > 0 && (!reqs || !out))) return fail(PERC_EINVAL, "bad run arguments");
+    for (int64_t i = 1; i < n; ++i)
+        if (reqs[i].t_arrive_ns < reqs[i - 1].t_arrive_ns) return fail(PERC_EINVAL, "arrivals must be non-decreasing");
+    const int64_t t0 = steady_ns();
+    int64_t next = 0, got = 0;
+    while (got < n) {
+        const int64_t now = steady_ns();
+        while (next < n && t0 + reqs[next].t_arrive_ns <= now) {
+            const perc_request& q = reqs[next];
+            PERC_TRY(server_submit(srv, q.W, q.L, q.p, q.seed, q.cfg, q.tag, t0 + q.t_arrive_ns));
+            ++next;
+        }
+        const bool idle = srv->queue.empty() && srv->free_slots.size() == srv->slots.size();
+        if (idle) {
+            if (next < n) {
+                std::this_thread::sleep_until(std::chrono::steady_clock::time_point(
+                    std::chrono::nanoseconds(t0 + reqs[next].t_arrive_ns)));
+            }
+            continue;
+        }
+        const int rc = server_tick(srv);
+        if (rc < 0) return rc;
+        while (!srv->done.empty() && got < n) {
+            out[got++] = srv->done.front();
+            srv->done.pop_front();
+        }
+    }
     return PERC_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -43,18 +44,16 @@ namespace perc {
 constexpr int kSide = 12;
 constexpr int kTileCols = 512;  // target columns per tile
 
-struct LatticeDesc {
-    int32_t W = 0, L = 0;
+// Everything that depends on the cross-section only (hex radius W): built once per W
+// and shared by every fiber length (see column_set).
+struct ColumnSet {
+    int32_t W = 0;
     int32_t C = 0;       // columns
-    int32_t U = 0;       // unit cells, ceil(L / 3)
     int32_t CP = 0;      // row length of the state arrays: multiple of 32, >= C
-    int64_t N = 0;       // sites
-    int64_t words = 0;   // ceil(N / 32)
     int32_t nsig[3] = {0, 0, 0};
     std::vector<int32_t> q, r, sig;  // per internal column
     std::vector<int32_t> rank;       // canonical rank of internal column c
     std::vector<int32_t> by_rank;    // internal column of canonical rank k
-    std::vector<int32_t> top;        // per column: cell of its far-end tube, -1 if empty
     // per side contact i (0..11) and column c: packed (nb_col << 2) | (dcell + 1);
     // a contact outside the hexagon has nb_col = C
     std::vector<int32_t> nb;         // [kSide][C]
@@ -62,6 +61,28 @@ struct LatticeDesc {
     std::vector<int32_t> tile;       // [ntile][4]: first col, end col, halo first, halo end
     int32_t span_max = 0;            // widest halo range
     int32_t tile_max = 0;            // widest tile
+    std::vector<uint32_t> contact;   // contact table (layout below)
+};
+
+// The column set of hex radius W, built on first use and kept for the process (one per
+// distinct W; thread safe). Null with a message for a bad W.
+std::shared_ptr<const ColumnSet> column_set(int32_t W, std::string& err);
+
+// A fiber: the column set of its W and the quantities that depend on L.
+struct LatticeDesc {
+    std::shared_ptr<const ColumnSet> cs;
+    int32_t W = 0, L = 0;
+    int32_t C = 0, CP = 0;
+    int32_t U = 0;       // unit cells, ceil(L / 3)
+    int64_t N = 0;       // sites
+    int64_t words = 0;   // ceil(N / 32)
+    int32_t ntile = 1, span_max = 0, tile_max = 0;
+    // cell of the far-end tube of column c (the highest layer k < L with k = sigma), or
+    // -1 if the column holds no tube
+    int32_t top(int32_t c) const {
+        const int32_t sg = cs->sig[c];
+        return sg < L ? (L - 1 - sg) / 3 : -1;
+    }
 };
 
 bool build_lattice(int32_t W, int32_t L, LatticeDesc& out, std::string& err);
@@ -86,32 +107,31 @@ PERC_HD_INLINE int32_t ring_word(int32_t row, int32_t lcol) {
     return (lcol / kBlkCols) * kBlkWords + row * kBlkCols + lcol % kBlkCols;
 }
 
-// Contact table: for side contact i of column c (in tile k), the LDS word
-// ring_word(1 + dcell, lcol) of that contact for a tube in ring slot 0, lcol being 1 +
-// its column within the tile's staged range [halo first, halo end); word 0 (row 0 of
-// the zero pad column 0) for a missing contact. A tube in slot s reads it s rows (64 s
-// words) further.
-std::vector<uint32_t> contact_table(const LatticeDesc& d);
+// Contact table (ColumnSet::contact): for side contact i of column c (in tile k), the
+// LDS word ring_word(1 + dcell, lcol) of that contact for a tube in ring slot 0, lcol
+// being 1 + its column within the tile's staged range [halo first, halo end); word 0
+// (row 0 of the zero pad column 0) for a missing contact. A tube in slot s reads it s
+// rows (64 s words) further.
 
 
-// One lattice shape as the kernels see it (device pointers).
+// One lattice shape as the kernels see it (device pointers to the tables of its
+// column set; the far cell of a column follows from sigma and L).
 struct DevShape {
     const uint32_t* nboff;  // [kSide][C] contact table
     const int32_t* tile;    // [ntile][4]
     const int32_t* rank;    // [C]
-    const int32_t* top;     // [C]
+    const int32_t* sig;     // [C]
     int32_t C, CP, U, L;
     int32_t ntile, span_max, tile_max, W;
     int64_t N, words;
 };
 
-// Device copies of the per-lattice tables, one set per HIP device that used it.
-struct LatticeDevice {
-    int device = -1;
+// Device copies of the tables of one column set on one HIP device (kept for the process).
+struct ColumnDevice {
     uint32_t* nboff = nullptr;
     int32_t* tile = nullptr;
     int32_t* rank = nullptr;
-    int32_t* top = nullptr;
+    int32_t* sig = nullptr;
 };
 
 // Dynamic LDS of the walking kernels: the ring from address 0, 1 + span columns (pad
@@ -155,6 +175,7 @@ constexpr uint32_t F_GREW = 1u;      // some tube joined the reached set
 constexpr uint32_t F_FRONT = 2u;     // the reached set entered cell front+1
 constexpr uint32_t F_FAR = 4u;       // a far-end tube is reached: detector next step
 constexpr uint32_t F_NONEMPTY = 8u;  // (initialisation) some start tube is metallic
+constexpr uint32_t F_STEPPED = 16u;  // the last step launch advanced the configuration
 
 // Outputs, device pointers indexed by slot (span) or job (persistent).
 struct BatchOut {
@@ -201,9 +222,12 @@ struct SpanArgs {
     int32_t* active;           // [n_slot] active slots
     int32_t* active2;          // scratch for compaction
     int64_t* chunk_off;        // [n_slot + 1] prefix sums of items per active slot
-    int32_t* hdr;              // [16]: n_active, total items, error flag
+    int32_t* hdr;              // [16]: n_active, total items, error flag, finished count
     unsigned long long* work;  // tube slots scheduled over all steps (planner adds)
     BatchOut out;
+    const int32_t* ids;        // slots to initialise (null: all n_slot)
+    int32_t n_ids;
+    int32_t* fin;              // slots decided by the planner are appended here (nullable)
     int32_t n_slot;
     int32_t depth;             // cells per work item
     int32_t block;
