@@ -80,6 +80,91 @@ def cpu_baseline(wl, budget_s: float):
     }
 
 
+def batched_leg(perc, workloads, stream):
+    """Batched Monte Carlo: every configuration of the Pi(p) sweep in one batch (one
+    output group per p), settings picked by the autotuner on a sample, then the Eq. 5 fit."""
+    import numpy as np
+    from paper_1401_2130_amd import fss
+    wl = workloads.BATCH
+    (W, L), seed, n = wl.shapes[0], wl.seed, wl.n_cfg
+    lat = perc.Lattice(W, L)
+    p_mid = wl.ps[len(wl.ps) // 2]
+    sample = [(lat, p_mid, seed, c) for c in range(512)]
+    tuned = perc.perc_autotune(sample, n_target=n * len(wl.ps), stream=stream)
+    jobs = [(lat, p, seed, c, g) for g, p in enumerate(wl.ps) for c in range(n)]
+    opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
+    perc.perc_batch(jobs[:1024], n_groups=len(wl.ps), stream=stream, **opts)  # warm-up
+    torch_sync()
+    t0 = time.perf_counter()
+    _, st, _, counts = perc.perc_batch(jobs, n_groups=len(wl.ps), stream=stream, **opts)
+    torch_sync()
+    wall = time.perf_counter() - t0
+    steps = st.cpu().numpy().astype(np.int64)
+    pis = np.array(counts) / n
+    out = {"workload": f"W={W} L={L} ({lat.n} tubes), p = 0.100..0.200 step 0.005 x {n}, Philox seed {seed}",
+           "configs": len(jobs), "configs_per_s": len(jobs) / wall, "wall_s": wall,
+           "site_updates_per_s": float(steps.sum()) * lat.n / wall, "autotune": tuned,
+           "pi": {f"{p:.3f}": float(v) for p, v in zip(wl.ps, pis)}}
+    try:
+        pc, T, cov = fss.fit_fermi_dirac(wl.ps, pis, n)
+        out["eq5_fit"] = {"pc": pc, "T": T, "pc_err": float(np.sqrt(cov[0, 0]))}
+    except Exception as e:
+        out["eq5_fit"] = {"error": str(e)}
+    return out
+
+
+def uneven_leg(perc, workloads, stream):
+    """Uneven batch: 35 shapes x 2 p x 1024 configurations mixed in one batch; effective
+    thresholds per shape and the Eq. 7 / Eq. 8 fits."""
+    from paper_1401_2130_amd import fss
+    wl = workloads.UNEVEN
+    lats = [perc.Lattice(*sh) for sh in wl.shapes]
+    tuned = perc.perc_autotune([(lat, wl.ps[0], wl.seed, c) for lat in lats for c in range(8)], stream=stream)
+    opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
+    torch_sync()
+    t0 = time.perf_counter()
+    counts = fss.pi_table(wl.shapes, wl.ps, wl.n_cfg, wl.seed, stream=stream, **opts)
+    torch_sync()
+    wall = time.perf_counter() - t0
+    n_jobs = len(wl.shapes) * len(wl.ps) * wl.n_cfg
+    ana = fss.uneven_analysis(counts, wl.n_cfg)
+    return {"workload": "W in {8,12,16,24,32} x L/W in {1,2,4,8,16,32,64}, p in {0.1533, 0.16} x 1024, Philox seed 4",
+            "configs": n_jobs, "configs_per_s": n_jobs / wall, "wall_s": wall, "autotune": tuned,
+            "pc_inf": ana.get("pc_inf"), "eq8": ana.get("eq8"),
+            "shapes_with_pc": sum(1 for r in ana["shapes"] if r["pc"] is not None)}
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def serving_leg(perc, workloads, n: int, rate_hz: float, stream):
+    """Serve the first n requests of the serving recipe (W, L, p per request; Philox seed
+    = request id, configuration 0) with arrivals rescaled to rate_hz; latency = completion
+    minus scheduled arrival on the host steady clock."""
+    import numpy as np
+    base = workloads.serving_requests(n)
+    scale = workloads.SERVING.rate_hz / rate_hz
+    reqs = [(t * scale, W, L, p, i, 0, i) for (t, W, L, p, i) in base]
+    srv = perc.perc_server(hbm_bytes=96 << 30, max_slots=2048, tick_steps=16, max_w=workloads.SERVING.w_range[1],
+                           stream=stream)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    lat = np.array([r["t_done_ns"] - r["t_arrive_ns"] for r in res], dtype=np.float64) / 1e6
+    upd = sum(int(r["steps"]) * perc.Lattice(r["W"], r["L"]).n for r in res)
+    span = reqs[-1][0] if reqs else 0.0
+    st = srv.stats()
+    del srv
+    return {"requests": n, "offered_per_s": rate_hz, "arrival_span_s": span, "wall_s": wall,
+            "completed_per_s": n / wall, "site_updates_per_s": upd / wall,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "percolating": float(np.mean([r["perc"] for r in res])),
+            "ticks": st["ticks"], "tick_steps": 16, "max_slots": 2048,
+            "overloaded": bool(wall > 1.5 * span + 1.0)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +181,13 @@ def main():
                     help="first copy this many MiB device to device (counter calibration runs)")
     ap.add_argument("--copy-bandwidth-mib", type=int, default=1024,
                     help="measure device-to-device copy bandwidth on this many MiB (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="serving leg: first requests of the Poisson stream at its own rate (0: skip)")
+    ap.add_argument("--serve-low-rate", type=float, default=150.0,
+                    help="serving leg at a sustainable rate: the same request mix at this many per second")
+    ap.add_argument("--serve-low-requests", type=int, default=450)
+    ap.add_argument("--batched", type=int, default=1, help="batched Pi(p) leg (W=16 L=256, 21 p x 4096)")
+    ap.add_argument("--uneven", type=int, default=1, help="uneven aspect-ratio sweep leg (35 shapes x 2 p x 1024)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -233,6 +325,26 @@ def main():
                      "tube_steps_per_launch": prof["tube_steps"] / launches,
                      "bytes_per_tube_step": BYTES_PER_TUBE_STEP},
     }
+    if args.batched:
+        log("batched Pi(p) leg ...")
+        result["batched"] = batched_leg(perc, workloads, stream)
+        log(f"batched: {result['batched']['configs_per_s']:.0f} configs/s, fit {result['batched'].get('eq5_fit')}")
+    if args.uneven:
+        log("uneven aspect-ratio leg ...")
+        result["uneven"] = uneven_leg(perc, workloads, stream)
+        log(f"uneven: {result['uneven']['configs_per_s']:.0f} configs/s, pc_inf {result['uneven']['pc_inf']}")
+    if args.serve_requests > 0:
+        log(f"serving: {args.serve_requests} requests at {workloads.SERVING.rate_hz:.0f}/s ...")
+        result["serving"] = {"offered": serving_leg(perc, workloads, args.serve_requests, workloads.SERVING.rate_hz,
+                                                    stream)}
+        if args.serve_low_requests > 0:
+            log(f"serving: {args.serve_low_requests} requests at {args.serve_low_rate:.0f}/s ...")
+            result["serving"]["sustainable"] = serving_leg(perc, workloads, args.serve_low_requests,
+                                                           args.serve_low_rate, stream)
+        result["serving"]["workload"] = ("Poisson arrivals (seed 5), W uniform 8..64, L uniform 64..4096, "
+                                         "p uniform 0.12..0.19, Philox seed = request id, configuration 0")
+        log(f"serving p50/p99: {result['serving']['offered']['p50_ms']:.1f} / "
+            f"{result['serving']['offered']['p99_ms']:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

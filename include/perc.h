@@ -190,6 +190,17 @@ typedef struct perc_profile {
 int perc_profile_enable(int32_t on);
 int perc_profile_read(perc_profile* out);
 
+/* ---- autotuning of the execution settings -------------------------------------- */
+/* Time candidate settings (span form with 32/64/128 cells per work item and one or two
+ * block sizes, persistent form with 32/64/128) on the sample `jobs` (as perc_batch; group
+ * must be -1) and return the fastest in *best (wall time of the whole sample, ms, in
+ * *best_ms; either may be NULL). If every job has the same (W, L), the choice is also
+ * remembered for PERC_FORM_AUTO calls on that shape with a batch of about n_target
+ * configurations (n_target <= 0: the sample size). Synchronous; the outputs of the
+ * timing runs are discarded. */
+int perc_autotune(const perc_job* jobs, int64_t n_jobs, int64_t n_target, perc_options* best, double* best_ms,
+                  void* stream);
+
 /* ---- serving: continuous batching of single inspections -------------------------- */
 /* A server keeps the state of every admitted inspection resident on the GPU and advances
  * all of them together, a tick at a time; requests that arrive meanwhile wait in a FIFO

@@ -98,6 +98,7 @@ def _load():
     lib.perc_batch.argtypes = [C.POINTER(perc_job), i64, vp, vp, vp, vp, i32, C.POINTER(perc_options), vp]
     lib.perc_profile_enable.argtypes = [i32]
     lib.perc_profile_read.argtypes = [C.POINTER(perc_profile)]
+    lib.perc_autotune.argtypes = [C.POINTER(perc_job), i64, i64, C.POINTER(perc_options), C.POINTER(dbl), vp]
     lib.perc_server_create.restype = vp
     lib.perc_server_create.argtypes = [C.POINTER(perc_server_config), vp]
     lib.perc_server_destroy.argtypes = [vp]
@@ -114,7 +115,8 @@ _lib = _load()
 EXPORTED = ("perc_lattice_create", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
             "perc_last_error", "perc_sample", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
-            "perc_batch", "perc_state_after", "perc_profile_enable", "perc_profile_read", "perc_server_create",
+            "perc_batch", "perc_state_after", "perc_profile_enable", "perc_profile_read", "perc_autotune",
+            "perc_server_create",
             "perc_server_destroy", "perc_server_submit", "perc_server_tick", "perc_server_poll",
             "perc_server_stats_read", "perc_server_run")
 
@@ -276,13 +278,9 @@ def perc_pi_ex(lat: Lattice, p: float, n_cfg: int, seed: int, bits=None, steps=N
     return int(out.n_perc), float(out.pi)
 
 
-def perc_batch(jobs, n_groups: int = 0, perc=None, steps=None, hit=False, form="auto", depth=0, block=0, grid=0,
-               graph_steps=0, stream=None):
-    """Inspect a list of jobs of possibly different lattices in one batch.
-
-    ``jobs``: sequence of (lattice, occ) with occ a device int32 word tensor of one
-    configuration, or (lattice, p, seed, cfg[, group]) for a Philox draw. Returns
-    (perc uint8, steps int32, hit float32 or None, group counts list)."""
+def _job_array(jobs):
+    """perc_job array of (lattice, occ[, group]) or (lattice, p, seed, cfg[, group]) tuples,
+    and the tensors it points into (kept alive by the caller)."""
     n = len(jobs)
     arr = (perc_job * max(n, 1))()
     keep = []
@@ -296,6 +294,33 @@ def perc_batch(jobs, n_groups: int = 0, perc=None, steps=None, hit=False, form="
             p, seed, cfg = job[1], job[2], job[3]
             grp = int(job[4]) if len(job) > 4 else -1
             arr[j] = perc_job(lat.handle, None, float(p), int(seed) & (2**64 - 1), int(cfg), grp)
+    return arr, keep
+
+
+def perc_autotune(jobs, n_target: int = 0, stream=None) -> dict:
+    """Time candidate execution settings on the sample ``jobs`` (tuples as perc_batch,
+    without groups) and return the fastest as keyword options for perc_batch /
+    perc_pi_ex / perc_inspect_ex (``form``, ``depth``, ``block``, ``graph_steps``) plus
+    ``ms``; a single-shape sample also sets the choice for form="auto" at batch size
+    about ``n_target``."""
+    arr, keep = _job_array(jobs)
+    best = perc_options()
+    ms = C.c_double()
+    _check(_lib.perc_autotune(arr, len(jobs), int(n_target), C.byref(best), C.byref(ms), _stream(stream)))
+    names = {v: k for k, v in _FORMS.items()}
+    return {"form": names[best.form], "depth": int(best.depth), "block": int(best.block),
+            "graph_steps": int(best.graph_steps), "ms": float(ms.value)}
+
+
+def perc_batch(jobs, n_groups: int = 0, perc=None, steps=None, hit=False, form="auto", depth=0, block=0, grid=0,
+               graph_steps=0, stream=None):
+    """Inspect a list of jobs of possibly different lattices in one batch.
+
+    ``jobs``: sequence of (lattice, occ) with occ a device int32 word tensor of one
+    configuration, or (lattice, p, seed, cfg[, group]) for a Philox draw. Returns
+    (perc uint8, steps int32, hit float32 or None, group counts list)."""
+    n = len(jobs)
+    arr, keep = _job_array(jobs)
     if perc is None:
         perc = torch.empty(n, dtype=torch.uint8, device="cuda")
     if steps is None:

@@ -661,6 +661,81 @@ int pi_impl(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, per
     return PERC_OK;
 }
 
+// Jobs of the C ABI to host jobs (validated).
+int convert_jobs(const perc_job* jobs, int64_t n_jobs, int32_t n_groups, std::vector<HostJob>& hj) {
+    hj.resize(n_jobs);
+    for (int64_t j = 0; j < n_jobs; ++j) {
+        const perc_job& x = jobs[j];
+        PERC_TRY(validate_lat(x.lat));
+        if (!x.occ_bits && !(x.p >= 0.0 && x.p <= 1.0)) return fail(PERC_EINVAL, "job p must be in [0, 1]");
+        if (x.cfg < 0) return fail(PERC_EINVAL, "job cfg must be >= 0");
+        if (x.group >= n_groups) return fail(PERC_EINVAL, "job group out of range");
+        hj[j] = HostJob{x.lat, x.occ_bits, x.seed, (uint64_t)x.cfg, x.occ_bits ? 0 : threshold_of(x.p),
+                        x.group < 0 ? -1 : x.group};
+    }
+    return PERC_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Autotuning: time candidate execution settings on a sample batch.
+// ---------------------------------------------------------------------------------
+int autotune(const std::vector<HostJob>& hj, int64_t n_target, perc_options* best, double* best_ms, hipStream_t s) {
+    Shapes S;
+    collect_shapes(hj, S);
+    const int32_t b0 = block_for(S.need);
+    std::vector<perc_options> cands;
+    for (int32_t depth : {32, 64, 128}) {
+        cands.push_back(perc_options{FORM_SPAN, depth, b0, 0, 16});
+        if (b0 + 64 <= 1024) cands.push_back(perc_options{FORM_SPAN, depth, b0 + 64, 0, 16});
+        cands.push_back(perc_options{FORM_PERSIST, depth, b0, 0, 0});
+    }
+    const int64_t n = (int64_t)hj.size();
+    Arena ar;
+    PERC_TRY(ar.reserve(Arena::align((size_t)n) + Arena::align(4 * (size_t)n), s));
+    BatchOut out;
+    out.perc = ar.take<uint8_t>(n);
+    out.steps = ar.take<int32_t>(n);
+    double best_t = -1.0;
+    perc_options best_o{};
+    bool warm = false;
+    for (const perc_options& o : cands) {
+        double t_min = -1.0;
+        for (int rep = 0; rep < (warm ? 2 : 3); ++rep) {
+            HIP_TRY(hipStreamSynchronize(s));
+            const auto t0 = std::chrono::steady_clock::now();
+            const int rc = run_jobs(hj, out, &o, s);
+            if (rc == PERC_EINVAL) break;  // a candidate these shapes cannot take (e.g. LDS)
+            PERC_TRY(rc);
+            HIP_TRY(hipStreamSynchronize(s));
+            const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (!warm) {  // the first run of all pays one-time preparation
+                warm = true;
+                continue;
+            }
+            if (t_min < 0.0 || t < t_min) t_min = t;
+        }
+        if (t_min >= 0.0 && (best_t < 0.0 || t_min < best_t)) {
+            best_t = t_min;
+            best_o = o;
+        }
+    }
+    if (best_t < 0.0) return fail(PERC_EINVAL, "no candidate setting runs these jobs");
+    if (S.lats.size() == 1) {
+        const LatticeDesc& d = S.lats[0]->d;
+        Tuning t;
+        t.form = best_o.form;
+        t.depth = best_o.depth;
+        t.block = best_o.block;
+        t.graph_steps = best_o.graph_steps;
+        t.grid = 0;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[TuneKey{d.W, d.L, size_bucket(n_target > 0 ? n_target : n)}] = t;
+    }
+    if (best) *best = best_o;
+    if (best_ms) *best_ms = best_t;
+    return PERC_OK;
+}
+
 // ---------------------------------------------------------------------------------
 // Serving: continuous batching of single inspections (see perc.h).
 // ---------------------------------------------------------------------------------
@@ -1256,16 +1331,8 @@ int perc_batch(const perc_job* jobs, int64_t n_jobs, uint8_t* perc, int32_t* ste
         return PERC_OK;
     }
     if (!jobs || !perc) return fail(PERC_EINVAL, "jobs and perc must not be NULL");
-    std::vector<HostJob> hj(n_jobs);
-    for (int64_t j = 0; j < n_jobs; ++j) {
-        const perc_job& x = jobs[j];
-        PERC_TRY(validate_lat(x.lat));
-        if (!x.occ_bits && !(x.p >= 0.0 && x.p <= 1.0)) return fail(PERC_EINVAL, "job p must be in [0, 1]");
-        if (x.cfg < 0) return fail(PERC_EINVAL, "job cfg must be >= 0");
-        if (x.group >= n_groups) return fail(PERC_EINVAL, "job group out of range");
-        hj[j] = HostJob{x.lat, x.occ_bits, x.seed, (uint64_t)x.cfg, x.occ_bits ? 0 : threshold_of(x.p),
-                        x.group < 0 ? -1 : x.group};
-    }
+    std::vector<HostJob> hj;
+    PERC_TRY(convert_jobs(jobs, n_jobs, n_groups, hj));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Arena ar;
     PERC_TRY(ar.reserve(Arena::align(sizeof(int32_t) * n_jobs) + Arena::align(8 * (size_t)std::max(n_groups, 1)), s));
@@ -1439,6 +1506,15 @@ int perc_server_run(perc_server* srv, const perc_request* reqs, int64_t n, perc_
         }
     }
     return PERC_OK;
+}
+
+
+int perc_autotune(const perc_job* jobs, int64_t n_jobs, int64_t n_target, perc_options* best, double* best_ms,
+                  void* stream) {
+    if (n_jobs <= 0 || !jobs) return fail(PERC_EINVAL, "autotuning needs a non-empty job sample");
+    std::vector<HostJob> hj;
+    PERC_TRY(convert_jobs(jobs, n_jobs, 0, hj));
+    return autotune(hj, n_target, best, best_ms, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -1,0 +1,152 @@
+"""Pi(p) curves and the finite-size-scaling analysis of Sec. III.
+
+The GPU side (``pi_curve``, ``pi_table``) runs all configurations of a sweep in one
+``perc_batch`` launch sequence, with one output group per (shape, p), and returns the
+integer percolating counts. The fits are host-side statistics on those counts:
+
+* Eq. 5: Pi(p) = 1 / (1 + exp((p_c - p) / T)), the effective threshold p_c of a finite
+  fiber being the p where Pi = 1/2 (``fit_fermi_dirac``; ``pc_two_point`` solves it from
+  two points on the logit scale);
+* Eq. 6-7: p_c = p_c_inf + C(W/L) L^(-1/nu), nu = 0.88 in 3D, one slope per aspect ratio
+  and a common intercept (``fit_eq7``);
+* Eq. 8: C(W/L) = C0 + C1 (W/L)^alpha (``fit_eq8``), hence Eq. 9:
+  p_c = p_c_inf + C0 L^(-1/nu) + C1 W^alpha L^(-alpha - 1/nu) (``eq9``).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+NU_3D = 0.88  # universal correlation-length exponent in three dimensions (Sec. III)
+
+
+def fermi_dirac(p, pc: float, T: float):
+    """Eq. 5."""
+    return 1.0 / (1.0 + np.exp((pc - np.asarray(p, dtype=np.float64)) / T))
+
+
+def fit_fermi_dirac(ps: Sequence[float], pis: Sequence[float], n: int) -> Tuple[float, float, np.ndarray]:
+    """Weighted least-squares fit of Eq. 5 to Pi estimates from n configurations each
+    (binomial standard errors); returns (p_c, T, covariance)."""
+    from scipy.optimize import curve_fit
+    ps = np.asarray(ps, dtype=np.float64)
+    pis = np.asarray(pis, dtype=np.float64)
+    pe = np.clip(pis, 0.5 / n, 1.0 - 0.5 / n)
+    sigma = np.sqrt(pe * (1.0 - pe) / n)
+    inside = (pis > 0.0) & (pis < 1.0)
+    if inside.any():
+        pc0 = float(ps[inside][np.argmin(np.abs(pis[inside] - 0.5))])
+    else:
+        pc0 = float(ps[np.argmin(np.abs(pis - 0.5))])
+    T0 = max((ps.max() - ps.min()) / 20.0, 1e-4)
+    popt, pcov = curve_fit(fermi_dirac, ps, pis, p0=(pc0, T0), sigma=sigma, absolute_sigma=True, maxfev=20000)
+    return float(popt[0]), float(popt[1]), pcov
+
+
+def pc_two_point(p1: float, pi1: float, p2: float, pi2: float) -> Optional[Tuple[float, float]]:
+    """(p_c, T) of the Eq. 5 curve through two points with 0 < Pi < 1 (logit(Pi) is linear
+    in p); None if a point lies outside (0, 1) or the curve does not rise."""
+    if not (0.0 < pi1 < 1.0 and 0.0 < pi2 < 1.0) or p1 == p2:
+        return None
+    l1, l2 = math.log(pi1 / (1.0 - pi1)), math.log(pi2 / (1.0 - pi2))
+    if l2 == l1:
+        return None
+    T = (p2 - p1) / (l2 - l1)
+    if T <= 0.0:
+        return None
+    return p1 - T * l1, T
+
+
+def fit_eq7(W: Sequence[float], L: Sequence[float], pc: Sequence[float], nu: float = NU_3D,
+            weights: Optional[Sequence[float]] = None) -> Tuple[float, Dict[float, float]]:
+    """Eq. 7 with a common intercept: least squares of p_c = p_c_inf + C(r) L^(-1/nu) over
+    the aspect ratios r = W/L present. Returns (p_c_inf, {r: C(r)})."""
+    W = np.asarray(W, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    pc = np.asarray(pc, dtype=np.float64)
+    r = W / L
+    keys = sorted(set(np.round(r, 12).tolist()))
+    A = np.zeros((len(pc), 1 + len(keys)))
+    A[:, 0] = 1.0
+    x = L ** (-1.0 / nu)
+    for j, k in enumerate(keys):
+        A[np.isclose(r, k, rtol=0, atol=1e-12), 1 + j] = x[np.isclose(r, k, rtol=0, atol=1e-12)]
+    w = np.ones_like(pc) if weights is None else np.sqrt(np.asarray(weights, dtype=np.float64))
+    sol, *_ = np.linalg.lstsq(A * w[:, None], pc * w, rcond=None)
+    return float(sol[0]), {k: float(sol[1 + j]) for j, k in enumerate(keys)}
+
+
+def fit_eq8(ratios: Sequence[float], slopes: Sequence[float]) -> Tuple[float, float, float]:
+    """Eq. 8: C(r) = C0 + C1 r^alpha, fitted to per-aspect-ratio slopes; (C0, C1, alpha)."""
+    from scipy.optimize import curve_fit
+    r = np.asarray(ratios, dtype=np.float64)
+    c = np.asarray(slopes, dtype=np.float64)
+
+    def f(x, c0, c1, a):
+        return c0 + c1 * np.power(x, a)
+
+    popt, _ = curve_fit(f, r, c, p0=(float(np.min(c)), 0.3, -1.2), maxfev=50000)
+    return float(popt[0]), float(popt[1]), float(popt[2])
+
+
+def eq9(W, L, pc_inf: float, C0: float, C1: float, alpha: float, nu: float = NU_3D):
+    """Eq. 9: the effective threshold of a W x L fiber."""
+    W = np.asarray(W, dtype=np.float64)
+    L = np.asarray(L, dtype=np.float64)
+    return pc_inf + C0 * L ** (-1.0 / nu) + C1 * W ** alpha * L ** (-alpha - 1.0 / nu)
+
+
+# ---------------------------------------------------------------------------------
+# GPU sweeps (one batch each)
+# ---------------------------------------------------------------------------------
+
+def pi_table(shapes: Iterable[Tuple[int, int]], ps: Sequence[float], n_cfg: int, seed: int, stream=None,
+             **opts) -> Dict[Tuple[int, int, float], int]:
+    """Percolating counts for every (W, L) x p, configurations 0..n_cfg-1 of the Philox
+    stream `seed` (common random numbers across p), all in one perc_batch call (mixed
+    shapes in one work list). Returns {(W, L, p): count}."""
+    import paper_1401_2130_amd as perc
+    shapes = list(shapes)
+    lats = {s: perc.Lattice(*s) for s in shapes}
+    jobs, keys = [], []
+    for (W, L) in shapes:
+        for p in ps:
+            g = len(keys)
+            keys.append((W, L, float(p)))
+            jobs += [(lats[(W, L)], float(p), seed, c, g) for c in range(n_cfg)]
+    _, _, _, counts = perc.perc_batch(jobs, n_groups=len(keys), stream=stream, **opts)
+    return {k: int(c) for k, c in zip(keys, counts)}
+
+
+def pi_curve(W: int, L: int, ps: Sequence[float], n_cfg: int, seed: int, stream=None, **opts) -> np.ndarray:
+    """Pi(p) estimates of one fiber at every p (one batch)."""
+    t = pi_table([(W, L)], ps, n_cfg, seed, stream=stream, **opts)
+    return np.array([t[(W, L, float(p))] / n_cfg for p in ps])
+
+
+def uneven_analysis(counts: Dict[Tuple[int, int, float], int], n_cfg: int, nu: float = NU_3D) -> dict:
+    """Effective thresholds per shape from two p values (Eq. 5 through two points), then
+    Eq. 7 (common intercept) and, with three or more aspect ratios, Eq. 8."""
+    by_shape: Dict[Tuple[int, int], List[Tuple[float, float]]] = {}
+    for (W, L, p), c in counts.items():
+        by_shape.setdefault((W, L), []).append((p, c / n_cfg))
+    rows = []
+    for (W, L), pts in sorted(by_shape.items()):
+        pts.sort()
+        sol = pc_two_point(pts[0][0], pts[0][1], pts[-1][0], pts[-1][1]) if len(pts) >= 2 else None
+        rows.append({"W": W, "L": L, "pi": [x[1] for x in pts], "pc": None if sol is None else sol[0],
+                     "T": None if sol is None else sol[1]})
+    ok = [r for r in rows if r["pc"] is not None]
+    out = {"shapes": rows, "n_cfg": n_cfg, "nu": nu}
+    if len(ok) >= 3:
+        pinf, slopes = fit_eq7([r["W"] for r in ok], [r["L"] for r in ok], [r["pc"] for r in ok], nu)
+        out["pc_inf"] = pinf
+        out["slopes"] = {str(k): v for k, v in slopes.items()}
+        if len(slopes) >= 3:
+            try:
+                out["eq8"] = dict(zip(("C0", "C1", "alpha"), fit_eq8(list(slopes), list(slopes.values()))))
+            except Exception as e:  # a fit that does not converge is reported, not raised
+                out["eq8"] = {"error": str(e)}
+    return out

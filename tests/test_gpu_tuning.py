@@ -1,0 +1,53 @@
+"""Autotuner and sweep driver on the GPU: the tuned settings are valid, the automatic
+form picks them up without changing any result (bits, steps, FP32 hit), and a mixed
+Pi table from one batch equals the per-shape Pi counts of perc_pi_ex."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def perc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1401_2130_amd as p
+    return p
+
+
+def test_autotune_then_auto_form_is_bitwise_unchanged(perc):
+    lat = perc.Lattice(6, 40)
+    best = perc.perc_autotune([(lat, 0.3, 9, c) for c in range(64)], n_target=300)
+    assert best["form"] in ("span", "persist")
+    assert best["depth"] % 16 == 0 and 64 <= best["block"] <= 1024 and best["ms"] > 0
+    jobs = [(lat, 0.3, 9, c) for c in range(300)]
+    pa, sa, ha, _ = perc.perc_batch(jobs, hit=True, form="auto")
+    pb, sb, hb, _ = perc.perc_batch(jobs, hit=True, form="span", depth=64)
+    pc, sc, hc, _ = perc.perc_batch(jobs, hit=True, **{k: best[k] for k in ("form", "depth", "block", "graph_steps")})
+    torch.cuda.synchronize()
+    for x, y in ((pa, pb), (sa, sb), (pa, pc), (sa, sc)):
+        assert torch.equal(x, y)
+    for x, y in ((ha, hb), (ha, hc)):
+        assert torch.equal(x.view(torch.int32), y.view(torch.int32))
+
+
+def test_autotune_mixed_shapes(perc):
+    shapes = [perc.Lattice(3, 20), perc.Lattice(9, 30)]
+    best = perc.perc_autotune([(shapes[c % 2], 0.35, 2, c) for c in range(40)])
+    assert best["form"] in ("span", "persist")
+    with pytest.raises(perc.PercError):
+        perc.perc_autotune([])
+
+
+def test_pi_table_matches_pi_ex(perc):
+    from paper_1401_2130_amd import fss
+    shapes, ps, n, seed = [(4, 16), (3, 10), (0, 9)], [0.2, 0.45, 0.9], 200, 77
+    table = fss.pi_table(shapes, ps, n, seed)
+    for (W, L) in shapes:
+        lat = perc.Lattice(W, L)
+        for p in ps:
+            n_perc, _ = perc.perc_pi_ex(lat, p, n, seed)
+            assert table[(W, L, float(p))] == n_perc
+    curve = fss.pi_curve(4, 16, ps, n, seed)
+    assert np.all(np.diff(curve) >= 0)  # common random numbers: monotone in p
