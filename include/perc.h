@@ -110,6 +110,15 @@ const char* perc_last_error(void);
 int perc_sample(const perc_lattice* lat, double p, uint64_t seed, int64_t cfg0, int64_t n_cfg,
                 uint32_t* occ_bits, void* stream);
 
+/* Fixed-count ensemble (Sec. II.A: Np of the N tubes are chosen metallic, uniformly):
+ * each configuration has exactly K = floor(N p + 1/2) metallic tubes, the K with the
+ * smallest 64-bit keys, ties by tube index; tube s's key is words 2(s%2) (high) and
+ * 2(s%2)+1 (low) of Philox4x32-10 with counter (s/2, c mod 2^32, c / 2^32,
+ * (W<<16 | L) | 2^31) and key (seed mod 2^32, seed / 2^32). Same layout and ownership
+ * as perc_sample (device bits, async). */
+int perc_sample_fixed(const perc_lattice* lat, double p, uint64_t seed, int64_t cfg0, int64_t n_cfg,
+                      uint32_t* occ_bits, void* stream);
+
 /* ---- inspection (Sec. II.B) --------------------------------------------------------- */
 
 /* Decide percolation of n_cfg >= 0 configurations given as canonical occupancy bits

@@ -69,6 +69,9 @@ def _load():
     lib.orc_threshold.restype = C.c_uint64
     lib.orc_threshold.argtypes = [dbl]
     lib.orc_sample.argtypes = [vp, dbl, C.c_uint64, i64, i64, vp]
+    lib.orc_sample_fixed.argtypes = [vp, dbl, C.c_uint64, i64, i64, vp]
+    lib.orc_fixed_count.restype = i64
+    lib.orc_fixed_count.argtypes = [i64, dbl]
     lib.orc_inspect_markov.argtypes = [vp, vp, i64, vp, vp, vp, C.c_int]
     lib.orc_state_after.argtypes = [vp, vp, i32, vp, vp]
     lib.orc_row_sums.argtypes = [vp, vp, vp, vp]
@@ -152,6 +155,14 @@ class Lattice:
         bits = np.zeros((n_cfg, self.words), np.uint32)
         _check(_lib.orc_sample(self._h, float(p), int(seed) & (2**64 - 1), int(cfg0), int(n_cfg),
                                _ptr(bits)), "sample")
+        return bits
+
+    def sample_fixed(self, p: float, seed: int, n_cfg: int, cfg0: int = 0) -> np.ndarray:
+        """Fixed-count ensemble: floor(N p + 1/2) metallic sites per configuration, the
+        ones with the smallest 64-bit Philox keys (orc_sample_fixed)."""
+        bits = np.zeros((n_cfg, self.words), np.uint32)
+        _check(_lib.orc_sample_fixed(self._h, float(p), int(seed) & (2**64 - 1), int(cfg0), int(n_cfg),
+                                     _ptr(bits)), "sample_fixed")
         return bits
 
     def _bits(self, bits) -> np.ndarray:

@@ -250,6 +250,49 @@ int orc_sample(const orc_lattice *lat, double p, uint64_t seed, int64_t cfg0, in
     return ORC_OK;
 }
 
+/* Fixed-count ensemble (Sec. II.A: Np of the N sites are chosen metallic, uniformly):
+ * K = floor(N p + 1/2) sites per configuration, the K sites with the smallest 64-bit keys
+ * (ties by site index). Site s takes words 2(s&1) (high) and 2(s&1)+1 (low) of the
+ * Philox block with counter (s >> 1, cfg lo, cfg hi, tag | 2^31) under key = seed; the
+ * top counter bit keeps these draws apart from the Bernoulli sampler's. Sorting all keys
+ * is the plain definition of "the K smallest". */
+typedef struct { uint64_t key; int64_t s; } orc_keyed;
+
+static int orc_keyed_cmp(const void *a, const void *b) {
+    const orc_keyed *x = (const orc_keyed *)a, *y = (const orc_keyed *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->s < y->s ? -1 : (x->s > y->s ? 1 : 0);
+}
+
+int64_t orc_fixed_count(int64_t n, double p) { return (int64_t)floor((double)n * p + 0.5); }
+
+int orc_sample_fixed(const orc_lattice *lat, double p, uint64_t seed, int64_t cfg0, int64_t n_cfg,
+                     uint32_t *bits) {
+    if (!(p >= 0.0 && p <= 1.0) || n_cfg < 0) return ORC_EINVAL;
+    int64_t n = lat->n, words = (n + 31) / 32, K = orc_fixed_count(n, p);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t tag = (((uint32_t)lat->W << 16) | (uint32_t)lat->L) | 0x80000000u;
+    orc_keyed *ks = (orc_keyed *)malloc(sizeof(orc_keyed) * (size_t)(n > 0 ? n : 1));
+    if (!ks) return ORC_ENOMEM;
+    for (int64_t c = 0; c < n_cfg; ++c) {
+        uint64_t cfg = (uint64_t)(cfg0 + c);
+        uint32_t *b = bits + c * words;
+        memset(b, 0, sizeof(uint32_t) * (size_t)words);
+        for (int64_t s = 0; s < n; ++s) {
+            uint32_t ctr[4] = {(uint32_t)(s >> 1), (uint32_t)cfg, (uint32_t)(cfg >> 32), tag};
+            uint32_t out[4];
+            orc_philox4x32_10(ctr, key, out);
+            int w = 2 * (int)(s & 1);
+            ks[s].key = ((uint64_t)out[w] << 32) | out[w + 1];
+            ks[s].s = s;
+        }
+        qsort(ks, (size_t)n, sizeof(orc_keyed), orc_keyed_cmp);
+        for (int64_t i = 0; i < K; ++i) b[ks[i].s >> 5] |= 1u << (ks[i].s & 31);
+    }
+    free(ks);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------------ */
 /* Markov chain: Eq. (1)-(2) with the detector j1 of Sec. II.B                     */
 /* ------------------------------------------------------------------------------ */

@@ -90,6 +90,7 @@ def _load():
     lib.perc_site_neighbors.argtypes = [vp, i64, vp, vp]
     lib.perc_last_error.restype = C.c_char_p
     lib.perc_sample.argtypes = [vp, dbl, C.c_uint64, i64, i64, vp, vp]
+    lib.perc_sample_fixed.argtypes = [vp, dbl, C.c_uint64, i64, i64, vp, vp]
     lib.perc_inspect.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.perc_inspect_ex.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(perc_options), vp]
     lib.perc_pi.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), vp]
@@ -114,7 +115,7 @@ _lib = _load()
 
 EXPORTED = ("perc_lattice_create", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
-            "perc_last_error", "perc_sample", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
+            "perc_last_error", "perc_sample", "perc_sample_fixed", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
             "perc_batch", "perc_state_after", "perc_profile_enable", "perc_profile_read", "perc_autotune",
             "perc_server_create",
             "perc_server_destroy", "perc_server_submit", "perc_server_tick", "perc_server_poll",
@@ -232,6 +233,17 @@ def perc_sample(lat: Lattice, p: float, seed: int, n_cfg: int, cfg0: int = 0, ou
         out = torch.empty((n_cfg, lat.words), dtype=torch.int32, device="cuda")
     _check(_lib.perc_sample(lat.handle, float(p), int(seed) & (2**64 - 1), int(cfg0), int(n_cfg),
                             _dptr(out, torch.int32, n_cfg * lat.words), _stream(stream)))
+    return out
+
+
+def perc_sample_fixed(lat: Lattice, p: float, seed: int, n_cfg: int, cfg0: int = 0,
+                      out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Occupancy words [n_cfg, words] of the fixed-count ensemble: exactly
+    floor(N p + 1/2) metallic tubes per configuration, chosen uniformly (Philox keys)."""
+    if out is None:
+        out = torch.empty((n_cfg, lat.words), dtype=torch.int32, device="cuda")
+    _check(_lib.perc_sample_fixed(lat.handle, float(p), int(seed) & (2**64 - 1), int(cfg0), int(n_cfg),
+                                  _dptr(out, torch.int32, n_cfg * lat.words), _stream(stream)))
     return out
 
 

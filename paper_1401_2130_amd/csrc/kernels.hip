@@ -605,6 +605,104 @@ __global__ void __launch_bounds__(256) k_sample(uint32_t* __restrict__ bits, int
     }
 }
 
+// Fixed-count ensemble (Sec. II.A: Np of the N tubes metallic, chosen uniformly): the K
+// tubes with the smallest 64-bit keys, ties by tube index. Tube s takes words 2(s&1)
+// (high) and 2(s&1)+1 (low) of the Philox block with counter (s >> 1, cfg lo, cfg hi,
+// tag | 2^31), a counter space apart from the Bernoulli draws. One workgroup per
+// configuration: a most-significant-digit radix select (six digits of 11 bits, LDS
+// histograms, keys regenerated every pass) finds the key T of rank K-1 and how many keys
+// equal to T are taken; a last pass writes the bits, taking equal keys in tube order.
+__device__ __forceinline__ uint64_t fixed_key(int64_t s, uint64_t cfg, uint32_t k0, uint32_t k1, uint32_t tag) {
+    const Ctr4 r = philox4x32_10(Ctr4{(uint32_t)(s >> 1), (uint32_t)cfg, (uint32_t)(cfg >> 32), tag | 0x80000000u},
+                                 k0, k1);
+    return (s & 1) ? (((uint64_t)r.v2 << 32) | r.v3) : (((uint64_t)r.v0 << 32) | r.v1);
+}
+
+constexpr int kSelBits = 11;
+constexpr int kSelBins = 1 << kSelBits;
+
+__global__ void __launch_bounds__(1024) k_sample_fixed(uint32_t* __restrict__ bits, int64_t words, int64_t N,
+                                                       int64_t K, int64_t n_cfg, uint64_t cfg0, uint32_t k0,
+                                                       uint32_t k1, uint32_t tag) {
+    __shared__ uint32_t hist[kSelBins];
+    __shared__ uint32_t scan[1024];
+    __shared__ uint64_t sel_prefix;
+    __shared__ int64_t sel_rank;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int64_t c = blockIdx.x; c < n_cfg; c += gridDim.x) {
+        const uint64_t cfg = cfg0 + (uint64_t)c;
+        uint32_t* out = bits + c * words;
+        if (K <= 0 || K >= N) {  // none or every tube
+            for (int64_t w = tid; w < words; w += nt) {
+                const int64_t rem = N - w * 32;
+                out[w] = K <= 0 ? 0u : (rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u));
+            }
+            continue;
+        }
+        uint64_t prefix = 0, mask = 0;
+        int64_t rank = K - 1;  // rank of the target among the keys that match the prefix
+        for (int shift = 64 - kSelBits; shift > -kSelBits; shift -= kSelBits) {
+            const int sh = shift < 0 ? 0 : shift;
+            const int width = shift < 0 ? kSelBits + shift : kSelBits;
+            const uint64_t dmask = ((uint64_t)1 << width) - 1;
+            for (int b = tid; b < kSelBins; b += nt) hist[b] = 0;
+            __syncthreads();
+            for (int64_t s = tid; s < N; s += nt) {
+                const uint64_t key = fixed_key(s, cfg, k0, k1, tag);
+                if ((key & mask) == prefix) atomicAdd(&hist[(key >> sh) & dmask], 1u);
+            }
+            __syncthreads();
+            // find the digit whose cumulative count passes rank (thread 0; 2048 bins)
+            if (tid == 0) {
+                int64_t below = 0;
+                uint32_t b = 0;
+                for (; b < (uint32_t)(1u << width); ++b) {
+                    if (below + hist[b] > rank) break;
+                    below += hist[b];
+                }
+                sel_prefix = prefix | ((uint64_t)b << sh);
+                sel_rank = rank - below;
+            }
+            __syncthreads();
+            prefix = sel_prefix;
+            rank = sel_rank;
+            mask |= dmask << sh;
+            __syncthreads();
+        }
+        // prefix = T, the key of rank K-1; rank + 1 keys equal to T are taken (by index)
+        const uint64_t T = prefix;
+        const int64_t need_eq = rank + 1;
+        const int64_t wpt = (words + nt - 1) / nt;  // contiguous words per thread
+        const int64_t w0 = min((int64_t)tid * wpt, words), w1 = min(w0 + wpt, words);
+        uint32_t eq = 0;
+        for (int64_t w = w0; w < w1; ++w)
+            for (int i = 0; i < 32; ++i) {
+                const int64_t s = w * 32 + i;
+                if (s < N && fixed_key(s, cfg, k0, k1, tag) == T) ++eq;
+            }
+        scan[tid] = eq;
+        __syncthreads();
+        for (int off = 1; off < nt; off <<= 1) {
+            const uint32_t v = tid >= off ? scan[tid - off] : 0u;
+            __syncthreads();
+            scan[tid] += v;
+            __syncthreads();
+        }
+        int64_t eq_before = (int64_t)scan[tid] - eq;
+        for (int64_t w = w0; w < w1; ++w) {
+            uint32_t word = 0;
+            for (int i = 0; i < 32; ++i) {
+                const int64_t s = w * 32 + i;
+                if (s >= N) break;
+                const uint64_t key = fixed_key(s, cfg, k0, k1, tag);
+                if (key < T || (key == T && eq_before++ < need_eq)) word |= 1u << i;
+            }
+            out[w] = word;
+        }
+        __syncthreads();
+    }
+}
+
 // Occupancy of the slots whose job samples from Philox, one workgroup per slot, into
 // the slot's bits buffer.
 __global__ void __launch_bounds__(256) k_sample_slots(const DevShape* shapes, const Job* jobs, int32_t n_slot,
@@ -1016,6 +1114,16 @@ hipError_t launch_sample(const DevShape& sh, uint32_t* bits, int64_t n_cfg, uint
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
     const uint32_t tag = ((uint32_t)sh.W << 16) | (uint32_t)sh.L;
     hipLaunchKernelGGL(k_sample, dim3(grid), dim3(256), 0, s, bits, sh.words, sh.N, n_cfg, cfg0, threshold,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), tag);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_fixed(const DevShape& sh, uint32_t* bits, int64_t n_cfg, uint64_t cfg0, int64_t K,
+                               uint64_t seed, hipStream_t s) {
+    if (n_cfg <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(n_cfg, 65536);
+    const uint32_t tag = ((uint32_t)sh.W << 16) | (uint32_t)sh.L;
+    hipLaunchKernelGGL(k_sample_fixed, dim3(grid), dim3(1024), 0, s, bits, sh.words, sh.N, K, n_cfg, cfg0,
                        (uint32_t)seed, (uint32_t)(seed >> 32), tag);
     return hipGetLastError();
 }

@@ -1303,6 +1303,20 @@ int perc_sample(const perc_lattice* lat, double p, uint64_t seed, int64_t cfg0, 
     return PERC_OK;
 }
 
+int perc_sample_fixed(const perc_lattice* lat, double p, uint64_t seed, int64_t cfg0, int64_t n_cfg,
+                      uint32_t* occ_bits, void* stream) {
+    PERC_TRY(validate_lat(lat));
+    if (!(p >= 0.0 && p <= 1.0)) return fail(PERC_EINVAL, "p must be in [0, 1]");
+    if (n_cfg < 0 || cfg0 < 0) return fail(PERC_EINVAL, "n_cfg and cfg0 must be >= 0");
+    if (n_cfg == 0) return PERC_OK;
+    if (!occ_bits) return fail(PERC_EINVAL, "occ_bits is NULL");
+    DevShape sh;
+    PERC_TRY(shape_for(lat, sh));
+    const int64_t K = (int64_t)std::floor((double)lat->d.N * p + 0.5);
+    HIP_TRY(launch_sample_fixed(sh, occ_bits, n_cfg, (uint64_t)cfg0, K, seed, reinterpret_cast<hipStream_t>(stream)));
+    return PERC_OK;
+}
+
 int perc_inspect(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc, int32_t* steps,
                  void* stream) {
     return inspect_impl(lat, occ_bits, n_cfg, perc, steps, nullptr, nullptr, stream);

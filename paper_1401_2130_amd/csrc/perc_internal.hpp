@@ -204,6 +204,10 @@ struct Job {
 hipError_t launch_sample(const DevShape& sh, uint32_t* bits, int64_t n_cfg, uint64_t cfg0, uint64_t threshold,
                          uint64_t seed, hipStream_t s);
 
+// Fixed-count occupancy: the K tubes with the smallest 64-bit Philox keys per configuration.
+hipError_t launch_sample_fixed(const DevShape& sh, uint32_t* bits, int64_t n_cfg, uint64_t cfg0, int64_t K,
+                               uint64_t seed, hipStream_t s);
+
 // Philox occupancy of the slots whose job has no caller bits (jobs indexed by slot).
 hipError_t launch_sample_slots(const DevShape* shapes, const Job* jobs, int32_t n_slot, uint32_t* const* slot_bits,
                                hipStream_t s);

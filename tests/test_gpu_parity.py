@@ -65,6 +65,30 @@ def test_sampler_bit_exact(perc, W, L, p, seed, cfg0, n):
     np.testing.assert_array_equal(host_words(got), ref)
 
 
+@pytest.mark.parametrize("W,L,p,seed,cfg0,n", [(4, 16, 0.1533, 1, 0, 16), (0, 7, 0.5, 3, 2, 8), (2, 9, 0.0, 1, 0, 3),
+                                               (2, 9, 1.0, 1, 0, 3), (16, 256, 0.15, 3, 100, 3),
+                                               (3, 13, 0.3, 2 ** 40 + 1, 2 ** 33, 4), (32, 64, 0.17, 9, 0, 2)])
+def test_fixed_count_sampler_bit_exact(perc, W, L, p, seed, cfg0, n):
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L).sample_fixed(p, seed, n, cfg0=cfg0)
+    got = perc.perc_sample_fixed(lat, p, seed, n, cfg0=cfg0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host_words(got), ref)
+
+
+def test_fixed_count_ensemble_inspection(perc):
+    """Configurations of the fixed-count ensemble inspected on the GPU: bits and steps of
+    the oracle on the same configurations."""
+    W, L, p, n = 5, 30, 0.3, 64
+    lat, ref = perc.Lattice(W, L), oracle.Lattice(W, L)
+    occ = perc.perc_sample_fixed(lat, p, 17, n)
+    pg, sg = perc.perc_inspect(lat, occ)
+    torch.cuda.synchronize()
+    pm, sm, _ = ref.inspect_markov(ref.sample_fixed(p, 17, n))
+    np.testing.assert_array_equal(pg.cpu().numpy(), pm)
+    np.testing.assert_array_equal(sg.cpu().numpy(), sm)
+
+
 # --------------------------------------------------------------------------------
 # inspection: every form and item length against the oracle
 # --------------------------------------------------------------------------------
