@@ -70,6 +70,7 @@ def _load():
     lib.orc_threshold.argtypes = [dbl]
     lib.orc_sample.argtypes = [vp, dbl, C.c_uint64, i64, i64, vp]
     lib.orc_sample_fixed.argtypes = [vp, dbl, C.c_uint64, i64, i64, vp]
+    lib.orc_first_passage_all.argtypes = [vp, vp, i32, vp]
     lib.orc_fixed_count.restype = i64
     lib.orc_fixed_count.argtypes = [i64, dbl]
     lib.orc_inspect_markov.argtypes = [vp, vp, i64, vp, vp, vp, C.c_int]
@@ -188,6 +189,14 @@ class Lattice:
         x = np.zeros(self.n + 1, np.float64); reach = np.zeros(self.n + 1, np.uint8)
         _check(_lib.orc_state_after(self._h, _ptr(b[0]), int(K), _ptr(x), _ptr(reach)), "state_after")
         return x, reach.astype(bool)
+
+    def first_passage_all(self, bits, M: int) -> np.ndarray:
+        """out[s] = probability that the walk from tube s first reaches the detector at
+        step M (Eq. 3 for every source), FP64; 0 for insulating tubes."""
+        b = self._bits(bits)
+        out = np.zeros(self.n, np.float64)
+        _check(_lib.orc_first_passage_all(self._h, _ptr(b[0]), int(M), _ptr(out)), "first_passage_all")
+        return out
 
     def row_sums(self, bits):
         b = self._bits(bits)

@@ -518,6 +518,39 @@ int orc_eq3_backward(int64_t n, const int64_t *ptr, const int32_t *col, const do
     return ORC_OK;
 }
 
+/* Eq. 3 for every source at once on the fiber: out[s] = P_s[the walk from tube s first
+ * reaches the detector j1 at step M] = [(^(j1)P)^(M-1) f](s), f = the j1 column of P (the
+ * detector's entry of each row), ^(j1)P = P with that column zeroed; 0 for insulating
+ * tubes. The plain backward recursion over the explicit CSR, in FP64. */
+int orc_first_passage_all(const orc_lattice *lat, const uint32_t *bits, int32_t M, double *out) {
+    if (M < 1) return ORC_EINVAL;
+    int64_t n = lat->n;
+    int64_t *map = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    if (!map) return ORC_ENOMEM;
+    orc_csr P; memset(&P, 0, sizeof(P));
+    int rc = build_P(lat, bits, &P, map);
+    if (rc) { free(map); csr_free(&P); return rc; }
+    int64_t m = P.n - 1, j1 = m;
+    double *f = (double *)calloc((size_t)P.n, sizeof(double));
+    double *g = (double *)calloc((size_t)P.n, sizeof(double));
+    if (!f || !g) { rc = ORC_ENOMEM; goto done; }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) if (P.col[e] == j1) f[i] += P.val[e];
+    for (int32_t it = 1; it < M; ++it) {
+        for (int64_t i = 0; i < m; ++i) {
+            double v = 0.0;
+            for (int64_t e = P.ptr[i]; e < P.ptr[i + 1]; ++e) if (P.col[e] != j1) v += P.val[e] * f[P.col[e]];
+            g[i] = v;
+        }
+        double *t = f; f = g; g = t;
+    }
+    for (int64_t s = 0; s < n; ++s) out[s] = 0.0;
+    for (int64_t i = 0; i < m; ++i) out[P.site[i]] = f[i];
+done:
+    free(f); free(g); free(map); csr_free(&P);
+    return rc;
+}
+
 /* Forward form: x^(0) = x0, the row of j0 replaced by an absorbing self-loop, x <- x P.
  * hit[m-1] = x^(m)_j0 - x^(m-1)_j0 = P_x0[first hit of j0 at step m]. */
 int orc_first_passage_forward(int64_t n, const int64_t *ptr, const int32_t *col, const double *val,
