@@ -134,6 +134,49 @@ def uneven_leg(perc, workloads, stream):
             "shapes_with_pc": sum(1 for r in ana["shapes"] if r["pc"] is not None)}
 
 
+def hist_summary(h) -> dict:
+    """Count, mean, quantiles and range of m* from its histogram (bin = m*)."""
+    import numpy as np
+    h = np.asarray(h, dtype=np.int64)
+    tot = int(h.sum())
+    if tot == 0:
+        return {"percolating": 0}
+    m = np.arange(h.size)
+    cdf = np.cumsum(h)
+    q = lambda f: int(np.searchsorted(cdf, f * tot))
+    nz = np.nonzero(h)[0]
+    return {"percolating": tot, "mean": float((m * h).sum() / tot), "p5": q(0.05), "p50": q(0.5), "p95": q(0.95),
+            "min": int(nz[0]), "max": int(nz[-1])}
+
+
+def first_passage_leg(perc, workloads, stream, M: int):
+    """Backward all-sources form of Eq. 3 on one configuration of the headline fiber:
+    M moves timed with HIP events on the launching stream (setup, backward init, M - 1
+    full-fiber steps and the export inside the timed region)."""
+    import torch
+    wl = workloads.LARGE
+    (W, L) = wl.shapes[0]
+    lat = perc.Lattice(W, L)
+    p = wl.ps[-1]
+    occ = perc.perc_sample(lat, p, wl.seed, 1, stream=stream)
+    f = torch.empty(lat.n, dtype=torch.float32, device="cuda")
+    perc.perc_first_passage(lat, occ, 8, f=f, stream=stream)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    perc.perc_first_passage(lat, occ, M, f=f, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    cols = perc.perc_lattice_columns(lat)
+    cells = (L + 2) // 3
+    slot_moves = float(M) * cols * cells
+    return {"workload": f"W={W} L={L} ({lat.n} tubes), p = {p}, Philox seed {wl.seed}, configuration 0",
+            "M": M, "ms": ms, "moves_per_s": M / (ms / 1e3), "site_updates_per_s": float(M) * lat.n / (ms / 1e3),
+            "achieved_gbs": slot_moves * BYTES_PER_TUBE_STEP / (ms / 1e3) / 1e9,
+            "kernel": "k_chunk_step (every cell of the fiber per move)",
+            "max_f": float(f.max().item()), "nonzero": int((f > 0).sum().item())}
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -187,6 +230,8 @@ def main():
                     help="serving leg at a sustainable rate: the same request mix at this many per second")
     ap.add_argument("--serve-low-requests", type=int, default=450)
     ap.add_argument("--batched", type=int, default=1, help="batched Pi(p) leg (W=16 L=256, 21 p x 4096)")
+    ap.add_argument("--first-passage", type=int, default=1024,
+                    help="moves of the backward all-sources leg on the headline fiber (0: skip)")
     ap.add_argument("--uneven", type=int, default=1, help="uneven aspect-ratio sweep leg (35 shapes x 2 p x 1024)")
     args = ap.parse_args()
 
@@ -325,6 +370,17 @@ def main():
                      "tube_steps_per_launch": prof["tube_steps"] / launches,
                      "bytes_per_tube_step": BYTES_PER_TUBE_STEP},
     }
+    # the m* (shortest spanning path) distribution of the timed workload, on the device
+    result["backbone"] = {"bins": "m* = tubes on the shortest spanning path", "per_p": {}}
+    for (b, s, _), p in zip(bufs, wl.ps):
+        h = perc.perc_steps_hist(b, s, 4 * L, stream=stream)
+        torch.cuda.synchronize()
+        result["backbone"]["per_p"][f"{p}"] = hist_summary(h.cpu().numpy())
+    if args.first_passage > 0:
+        log(f"first-passage leg (M = {args.first_passage}) ...")
+        result["first_passage"] = first_passage_leg(perc, workloads, stream, args.first_passage)
+        log(f"first passage: {result['first_passage']['ms']:.1f} ms, "
+            f"{result['first_passage']['achieved_gbs']:.0f} GB/s")
     if args.batched:
         log("batched Pi(p) leg ...")
         result["batched"] = batched_leg(perc, workloads, stream)

@@ -185,6 +185,33 @@ int perc_batch(const perc_job* jobs, int64_t n_jobs, uint8_t* perc, int32_t* ste
 int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t K, float* x_out,
                      uint8_t* reach_out, void* stream);
 
+/* ---- first-passage outputs (Sec. II.B, Eq. 3; Sec. III) ------------------------- */
+
+/* First-passage probabilities from every tube at once: the backward form of Eq. 3, in
+ * which the vector runs from the detector towards the sources. f_out (device, N floats,
+ * canonical order) receives, for each tube i, the probability that a walk started on i
+ * enters the detector for the first time at move M >= 1: f^(1)_i = 1/deg_i on metallic
+ * far-end tubes (0 elsewhere), f^(m)_i = (1/deg_i) sum over metallic contacts k of
+ * f^(m-1)_k (a metallic tube of degree 0 keeps its value; insulating tubes hold 0). The
+ * forward first-hit probability of the inspection at step m equals the mean of f^(m)
+ * over the metallic start tubes. FP32 with the step kernel's fixed summation order;
+ * values the exact recursion makes zero may read as denormals up to about M * 2^-149
+ * (the kernel keeps every word that was once non-zero at least 2^-149). occ_bits:
+ * device, words uint32, canonical order. Work memory is taken from and returned to the
+ * stream-ordered pool of `stream`. Async. Errors: PERC_EINVAL for M < 1 or NULL
+ * pointers, PERC_ENOMEM, PERC_EHIP. */
+int perc_first_passage(const perc_lattice* lat, const uint32_t* occ_bits, int32_t M, float* f_out, void* stream);
+
+/* Histogram of the stop step m* (Sec. III: the first step with a non-zero detector
+ * probability is the length of the shortest spanning path, m* tubes) over the
+ * percolating configurations of an inspection: hist[min(m*, nbins - 1)] += 1 for every
+ * i < n with perc[i] == 1. perc (device, n bytes), steps (device, n int32) as written by
+ * perc_inspect / perc_batch; hist: device, nbins uint64, accumulated into (the caller
+ * zeroes it). Async. Errors: PERC_EINVAL for n < 0, nbins < 1 or NULL pointers,
+ * PERC_EHIP. */
+int perc_steps_hist(const uint8_t* perc, const int32_t* steps, int64_t n, int32_t nbins, uint64_t* hist,
+                    void* stream);
+
 /* ---- profiling of the step kernel (span and plain forms) ------------------------- */
 
 typedef struct perc_profile {

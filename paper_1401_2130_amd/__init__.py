@@ -96,6 +96,8 @@ def _load():
     lib.perc_pi.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), vp]
     lib.perc_pi_ex.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), C.POINTER(perc_options), vp]
     lib.perc_state_after.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.perc_first_passage.argtypes = [vp, vp, i32, vp, vp]
+    lib.perc_steps_hist.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.perc_batch.argtypes = [C.POINTER(perc_job), i64, vp, vp, vp, vp, i32, C.POINTER(perc_options), vp]
     lib.perc_profile_enable.argtypes = [i32]
     lib.perc_profile_read.argtypes = [C.POINTER(perc_profile)]
@@ -116,7 +118,7 @@ _lib = _load()
 EXPORTED = ("perc_lattice_create", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
             "perc_last_error", "perc_sample", "perc_sample_fixed", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
-            "perc_batch", "perc_state_after", "perc_profile_enable", "perc_profile_read", "perc_autotune",
+            "perc_batch", "perc_state_after", "perc_first_passage", "perc_steps_hist", "perc_profile_enable", "perc_profile_read", "perc_autotune",
             "perc_server_create",
             "perc_server_destroy", "perc_server_submit", "perc_server_tick", "perc_server_poll",
             "perc_server_stats_read", "perc_server_run")
@@ -368,6 +370,25 @@ def perc_state_after(lat: Lattice, occ: torch.Tensor, K: int, x=None, reach=None
                                  _dptr(x, torch.float32, lat.n + 1), _dptr(reach, torch.uint8, lat.n + 1),
                                  _stream(stream)))
     return x, reach
+
+
+def perc_first_passage(lat: Lattice, occ: torch.Tensor, M: int, f=None, stream=None):
+    """First-passage probabilities at move M from every tube (N float32, canonical order)."""
+    if f is None:
+        f = torch.empty(max(lat.n, 1), dtype=torch.float32, device=occ.device)
+    _check(_lib.perc_first_passage(lat.handle, _dptr(occ, torch.int32, lat.words), int(M),
+                                   _dptr(f, torch.float32, lat.n), _stream(stream)))
+    return f[: lat.n]
+
+
+def perc_steps_hist(perc: torch.Tensor, steps: torch.Tensor, nbins: int, hist=None, stream=None):
+    """Histogram of m* over the percolating entries (bins 0 .. nbins-1, last bin open)."""
+    n = perc.numel()
+    if hist is None:
+        hist = torch.zeros(nbins, dtype=torch.int64, device=perc.device)
+    _check(_lib.perc_steps_hist(_dptr(perc, torch.uint8, n), _dptr(steps, torch.int32, n), int(n), int(nbins),
+                                _dptr(hist, torch.int64, nbins), _stream(stream)))
+    return hist
 
 
 # ---------------------------------------------------------------------------------

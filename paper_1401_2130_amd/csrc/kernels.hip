@@ -1054,6 +1054,53 @@ __global__ void __launch_bounds__(256) k_export(DevShape sh, const float* __rest
     }
 }
 
+// Backward form of Eq. 3 over all sources: f^(1) of every tube, the probability that a
+// walker on it enters the detector at its next move (1/deg on metallic far-end tubes, 0
+// elsewhere), written over every word of the state, padding included. Later terms use
+// the forward step's map unchanged: f^(m)_i = (1/deg_i) sum over metallic contacts k of
+// f^(m-1)_k, the detector column excluded.
+__global__ void __launch_bounds__(256) k_backward_init(DevShape sh, const uint8_t* __restrict__ code,
+                                                       float* __restrict__ y) {
+    const int64_t total = (int64_t)((sh.U + 3) / 4) * sh.CP * 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = i >> 2;
+        const int grp = (int)(q / sh.CP), c = (int)(q - (int64_t)grp * sh.CP);
+        const int u = grp * 4 + (int)(i & 3);
+        float v = 0.0f;
+        if (c < sh.C && u < sh.U && u == top_of(sh, c)) {
+            const uint32_t cd = code[i];
+            if (cd > 0u && cd < 15u) v = 1.0f / (float)cd;
+        }
+        y[i] = v;
+    }
+}
+
+// The state words themselves (no degree factor), scattered to canonical order.
+__global__ void __launch_bounds__(256) k_export_raw(DevShape sh, const float* __restrict__ y,
+                                                    float* __restrict__ f_out) {
+    const int64_t total = (int64_t)sh.U * sh.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = i / sh.C, c = i - u * sh.C;
+        const int64_t s = u * sh.C + sh.rank[c];
+        if (s < sh.N) f_out[s] = mag(__float_as_uint(y[word_of(sh, (int)u, (int)c)]));
+    }
+}
+
+// Histogram of the stop step m* over the percolating configurations (the shortest
+// spanning path has m* tubes): bin min(m*, nbins - 1).
+__global__ void __launch_bounds__(256) k_steps_hist(const uint8_t* __restrict__ perc,
+                                                    const int32_t* __restrict__ steps, int64_t n, int32_t nbins,
+                                                    unsigned long long* __restrict__ hist) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!perc[i]) continue;
+        const int32_t m = steps[i];
+        const int32_t b = m < 0 ? 0 : (m >= nbins ? nbins - 1 : m);
+        atomicAdd(&hist[b], 1ull);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -1192,6 +1239,27 @@ hipError_t launch_export(const DevShape& sh, const float* y, const uint8_t* code
                          const uint32_t* det_reached, float* x_out, uint8_t* reach_out, hipStream_t s) {
     const int grid = (int)std::min<int64_t>(((int64_t)sh.U * sh.C + 1 + 255) / 256, 65536);
     hipLaunchKernelGGL(k_export, dim3(grid), dim3(256), 0, s, sh, y, code, det_mass, det_reached, x_out, reach_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_init(const DevShape& sh, const uint8_t* code, float* y, hipStream_t s) {
+    const int64_t total = (int64_t)((sh.U + 3) / 4) * sh.CP * 4;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_backward_init, dim3(grid), dim3(256), 0, s, sh, code, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_raw(const DevShape& sh, const float* y, float* f_out, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>(((int64_t)sh.U * sh.C + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_export_raw, dim3(grid), dim3(256), 0, s, sh, y, f_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_steps_hist(const uint8_t* perc, const int32_t* steps, int64_t n, int32_t nbins,
+                             unsigned long long* hist, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_steps_hist, dim3(grid), dim3(256), 0, s, perc, steps, n, nbins, hist);
     return hipGetLastError();
 }
 

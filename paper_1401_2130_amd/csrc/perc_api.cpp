@@ -1202,11 +1202,81 @@ int server_submit(perc_server* v, int32_t W, int32_t L, double p, uint64_t seed,
     return PERC_OK;
 }
 
+// Work buffers of the single-configuration entry points: the codes of occ_bits and its
+// forward initial state in ya, yb and the detector words zero, in the plain layout.
+struct OneRun {
+    Arena ar;
+    DevShape sh;
+    float* ya = nullptr;
+    float* yb = nullptr;
+    uint8_t* code = nullptr;
+    float* det = nullptr;
+    uint32_t* det_r = nullptr;
+    int32_t depth = 0, block = 0;
+};
+
+int one_setup(const perc_lattice* lat, const uint32_t* occ_bits, hipStream_t s, OneRun& r) {
+    const LatticeDesc& d = lat->d;
+    ShapeNeed nd;
+    nd.span_max = d.span_max;
+    nd.tile_max = d.tile_max;
+    nd.C = d.C;
+    nd.items = (int64_t)d.U * d.ntile;
+    r.block = block_for(nd);
+    PERC_TRY(check_walk(nd, r.block));
+    r.depth = cells_for(nd, FORM_PLAIN);
+    PERC_TRY(shape_for(lat, r.sh));
+    const int64_t cw = slot_words(d);
+    PERC_TRY(r.ar.reserve(Arena::align(sizeof(float) * cw) * 2 + Arena::align((size_t)cw) +
+                              Arena::align(sizeof(CfgState)) + Arena::align(sizeof(DevShape)) + Arena::align(64) * 8,
+                          s));
+    Arena& ar = r.ar;
+    r.ya = ar.take<float>(cw);
+    r.yb = ar.take<float>(cw);
+    r.code = ar.take<uint8_t>(cw);
+    CfgState* st = ar.take<CfgState>(1);
+    DevShape* d_shape = ar.take<DevShape>(1);
+    r.det = ar.take<float>(2);
+    r.det_r = reinterpret_cast<uint32_t*>(r.det + 1);
+    int32_t* hdr = ar.take<int32_t>(16);
+    int32_t* slot_shape = ar.take<int32_t>(1);
+    int64_t* slot_off = ar.take<int64_t>(2);
+    const uint32_t** slot_bits = ar.take<const uint32_t*>(1);
+    int64_t* chunk_off = ar.take<int64_t>(2);
+    HIP_TRY(hipMemcpyAsync(d_shape, &r.sh, sizeof(DevShape), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(slot_bits, &occ_bits, sizeof(void*), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(r.ya), cw, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(r.yb), cw, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(r.det), 2, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(hdr), 16, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(slot_shape), 1, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(slot_off), 4, 0u, s));
+    SpanArgs a{};
+    a.shapes = d_shape;
+    a.slot_shape = slot_shape;
+    a.slot_off = slot_off;
+    a.slot_bits = slot_bits;
+    a.ya = r.ya;
+    a.yb = r.yb;
+    a.code = r.code;
+    a.st = st;
+    a.chunk_off = chunk_off;
+    a.hdr = hdr;
+    a.n_slot = 1;
+    a.depth = r.depth;
+    a.block = r.block;
+    a.grid = (int)std::min<int64_t>(((d.U + r.depth - 1) / r.depth) * (int64_t)d.ntile, 65536);
+    a.lds = (int)lds_total(d.span_max);
+    HIP_TRY(launch_span_init_only(a, s));
+    return PERC_OK;
+}
+
 }  // namespace
 
 // =================================================================================
 // extern "C" entry points
 // =================================================================================
+
 extern "C" {
 
 perc_lattice* perc_lattice_create(int32_t W, int32_t L) {
@@ -1376,70 +1446,46 @@ int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t 
     if (K < 0) return fail(PERC_EINVAL, "K < 0");
     if (!occ_bits || !x_out || !reach_out) return fail(PERC_EINVAL, "NULL device pointer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const LatticeDesc& d = lat->d;
-    ShapeNeed nd;
-    nd.span_max = d.span_max;
-    nd.tile_max = d.tile_max;
-    nd.C = d.C;
-    nd.items = (int64_t)d.U * d.ntile;
-    const int32_t block = block_for(nd);
-    PERC_TRY(check_walk(nd, block));
-    const int32_t depth = cells_for(nd, FORM_PLAIN);
-    DevShape sh;
-    PERC_TRY(shape_for(lat, sh));
-    const int64_t cw = slot_words(d);
-    Arena ar;
-    PERC_TRY(ar.reserve(Arena::align(sizeof(float) * cw) * 2 + Arena::align((size_t)cw) +
-                            Arena::align(sizeof(CfgState)) + Arena::align(sizeof(DevShape)) + Arena::align(64) * 8,
-                        s));
-    float* ya = ar.take<float>(cw);
-    float* yb = ar.take<float>(cw);
-    uint8_t* code = ar.take<uint8_t>(cw);
-    CfgState* st = ar.take<CfgState>(1);
-    DevShape* d_shape = ar.take<DevShape>(1);
-    float* det = ar.take<float>(2);
-    uint32_t* det_r = reinterpret_cast<uint32_t*>(det + 1);
-    int32_t* hdr = ar.take<int32_t>(16);
-    int32_t* slot_shape = ar.take<int32_t>(1);
-    int64_t* slot_off = ar.take<int64_t>(2);
-    const uint32_t** slot_bits = ar.take<const uint32_t*>(1);
-    int64_t* chunk_off = ar.take<int64_t>(2);
-    HIP_TRY(hipMemcpyAsync(d_shape, &sh, sizeof(DevShape), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(slot_bits, &occ_bits, sizeof(void*), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ya), cw, 0u, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(yb), cw, 0u, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(det), 2, 0u, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(hdr), 16, 0u, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(slot_shape), 1, 0u, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(slot_off), 4, 0u, s));
-    SpanArgs a{};
-    a.shapes = d_shape;
-    a.slot_shape = slot_shape;
-    a.slot_off = slot_off;
-    a.slot_bits = slot_bits;
-    a.ya = ya;
-    a.yb = yb;
-    a.code = code;
-    a.st = st;
-    a.chunk_off = chunk_off;
-    a.hdr = hdr;
-    a.n_slot = 1;
-    a.depth = depth;
-    a.block = block;
-    a.grid = (int)std::min<int64_t>(((d.U + depth - 1) / depth) * (int64_t)d.ntile, 65536);
-    a.lds = (int)lds_total(d.span_max);
-    HIP_TRY(launch_span_init_only(a, s));
-    float* cur = ya;
-    float* nxt = yb;
+    OneRun r;
+    PERC_TRY(one_setup(lat, occ_bits, s, r));
+    float* cur = r.ya;
+    float* nxt = r.yb;
     for (int32_t m = 0; m < K; ++m) {
-        HIP_TRY(launch_far_sum(sh, cur, det, det_r, s));
-        HIP_TRY(launch_chunk_step(sh, cur, nxt, code, depth, block, s));
+        HIP_TRY(launch_far_sum(r.sh, cur, r.det, r.det_r, s));
+        HIP_TRY(launch_chunk_step(r.sh, cur, nxt, r.code, r.depth, r.block, s));
         std::swap(cur, nxt);
     }
-    HIP_TRY(launch_export(sh, cur, code, det, det_r, x_out, reach_out, s));
+    HIP_TRY(launch_export(r.sh, cur, r.code, r.det, r.det_r, x_out, reach_out, s));
     return PERC_OK;
 }
 
+int perc_first_passage(const perc_lattice* lat, const uint32_t* occ_bits, int32_t M, float* f_out, void* stream) {
+    PERC_TRY(validate_lat(lat));
+    if (M < 1) return fail(PERC_EINVAL, "M < 1");
+    if (!occ_bits || !f_out) return fail(PERC_EINVAL, "NULL device pointer");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    OneRun r;
+    PERC_TRY(one_setup(lat, occ_bits, s, r));
+    HIP_TRY(launch_backward_init(r.sh, r.code, r.ya, s));
+    float* cur = r.ya;
+    float* nxt = r.yb;
+    for (int32_t m = 1; m < M; ++m) {
+        HIP_TRY(launch_chunk_step(r.sh, cur, nxt, r.code, r.depth, r.block, s));
+        std::swap(cur, nxt);
+    }
+    HIP_TRY(launch_export_raw(r.sh, cur, f_out, s));
+    return PERC_OK;
+}
+
+int perc_steps_hist(const uint8_t* perc, const int32_t* steps, int64_t n, int32_t nbins, uint64_t* hist,
+                    void* stream) {
+    if (n < 0) return fail(PERC_EINVAL, "n < 0");
+    if (nbins < 1) return fail(PERC_EINVAL, "nbins < 1");
+    if (!hist || (n > 0 && (!perc || !steps))) return fail(PERC_EINVAL, "NULL device pointer");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(launch_steps_hist(perc, steps, n, nbins, reinterpret_cast<unsigned long long*>(hist), s));
+    return PERC_OK;
+}
 
 perc_server* perc_server_create(const perc_server_config* cfg, void* stream) {
     perc_server* v = new (std::nothrow) perc_server();
