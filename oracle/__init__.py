@@ -58,6 +58,8 @@ def _load():
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     lib.orc_lattice_new.restype = vp
     lib.orc_lattice_new.argtypes = [C.c_int, C.c_int]
+    lib.orc_lattice_new_ex.restype = vp
+    lib.orc_lattice_new_ex.argtypes = [C.c_int, C.c_int, C.c_int]
     lib.orc_lattice_free.argtypes = [vp]
     for f in ("orc_lattice_sites", "orc_lattice_bonds", "orc_lattice_nnz"):
         getattr(lib, f).restype = i64
@@ -115,11 +117,13 @@ def philox4x32_10(ctr, key) -> np.ndarray:
 
 
 class Lattice:
-    """Modified FCC fiber lattice of hex radius ``W`` and ``L`` (111) layers."""
+    """Modified FCC fiber lattice of hex radius ``W`` and ``L`` (111) layers; with
+    ``ends=False`` the regular FCC lattice of the same sites (no end contacts)."""
 
-    def __init__(self, W: int, L: int):
+    def __init__(self, W: int, L: int, ends: bool = True):
         lib = _load()
-        h = lib.orc_lattice_new(int(W), int(L))
+        h = lib.orc_lattice_new_ex(int(W), int(L), 1 if ends else 0)
+        self.ends = bool(ends)
         if not h:
             raise ValueError(f"oracle lattice W={W} L={L} rejected")
         self._h = h

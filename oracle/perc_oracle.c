@@ -102,7 +102,10 @@ void orc_lattice_free(orc_lattice *lat) {
     free(lat);
 }
 
-orc_lattice *orc_lattice_new(int W, int L) {
+/* ends = 1: the modified lattice of the paper (12 side + 2 end contacts); ends = 0:
+ * the regular FCC lattice of the same sites (12 side contacts only), the reference
+ * lattice the paper compares its threshold with (Sec. III). Surfaces are the same. */
+orc_lattice *orc_lattice_new_ex(int W, int L, int ends) {
     if (W < 0 || L < 1 || W > 4096 || L > (1 << 20)) return NULL;
     orc_lattice *lat = (orc_lattice *)calloc(1, sizeof(orc_lattice));
     if (!lat) return NULL;
@@ -150,7 +153,7 @@ orc_lattice *orc_lattice_new(int W, int L) {
             for (int dk = -3; dk <= 3; ++dk)
                 for (int dq = -2; dq <= 2; ++dq)
                     for (int dr = -2; dr <= 2; ++dr) {
-                        if (!is_side_contact(dq, dr, dk) && !is_end_contact(dq, dr, dk)) continue;
+                        if (!is_side_contact(dq, dr, dk) && !(ends && is_end_contact(dq, dr, dk))) continue;
                         int q2 = q + dq, r2 = r + dr, k2 = k + dk;
                         if (k2 < 0 || k2 >= L || hexdist(q2, r2) > W) continue;
                         int64_t j = index[((int64_t)k2 * S + (q2 + W)) * S + (r2 + W)];
@@ -173,6 +176,8 @@ orc_lattice *orc_lattice_new(int W, int L) {
     free(index);
     return lat;
 }
+
+orc_lattice *orc_lattice_new(int W, int L) { return orc_lattice_new_ex(W, L, 1); }
 
 int64_t orc_lattice_sites(const orc_lattice *lat) { return lat->n; }
 int64_t orc_lattice_bonds(const orc_lattice *lat) { return lat->n_bonds; }

@@ -99,6 +99,53 @@ def eq9(W, L, pc_inf: float, C0: float, C1: float, alpha: float, nu: float = NU_
 
 
 # ---------------------------------------------------------------------------------
+# Fixed-count ensemble (Sec. II.A) and its relation to the Bernoulli ensemble
+# ---------------------------------------------------------------------------------
+
+def binomial_window(N: int, p: float, eps: float = 1e-12) -> Tuple[int, int]:
+    """Smallest k range [lo, hi] outside which the Binomial(N, p) mass is below eps."""
+    from scipy.stats import binom
+    lo = int(binom.ppf(eps / 2, N, p))
+    hi = int(binom.isf(eps / 2, N, p))
+    return max(lo, 0), min(hi, N)
+
+
+def binomial_convolution(ks: Sequence[int], pi_k: Sequence[float], N: int, ps) -> Tuple[np.ndarray, np.ndarray]:
+    """Pi(p) of the Bernoulli ensemble from fixed-count probabilities: a Bernoulli(p)
+    configuration has k metallic tubes with probability C(N, k) p^k (1 - p)^(N - k) and,
+    given k, is a uniform k-subset, so Pi(p) = sum_k C(N, k) p^k (1 - p)^(N - k) Pi_k.
+    ks: the k at which Pi_k is known; returns (Pi(p), binomial mass not covered by ks)."""
+    from scipy.stats import binom
+    ks = np.asarray(ks, dtype=np.int64)
+    pk = np.asarray(pi_k, dtype=np.float64)
+    out, miss = [], []
+    for p in np.atleast_1d(np.asarray(ps, dtype=np.float64)):
+        w = binom.pmf(ks, N, p)
+        out.append(float((w * pk).sum()))
+        miss.append(max(0.0, 1.0 - float(w.sum())))
+    return np.array(out), np.array(miss)
+
+
+def pi_fixed_counts(W: int, L: int, ks: Sequence[int], n_cfg: int, seed: int, stream=None, **opts) -> np.ndarray:
+    """Percolating counts of the fixed-count ensemble (exactly k metallic tubes) at every
+    k in ks, n_cfg configurations each: device sampling with perc_sample_fixed, then one
+    perc_batch over all of them with one output group per k."""
+    import paper_1401_2130_amd as perc
+    lat = perc.Lattice(W, L)
+    N = lat.n
+    keep, jobs = [], []
+    for g, k in enumerate(ks):
+        if not 0 <= int(k) <= N:
+            raise ValueError(f"k = {k} outside [0, {N}]")
+        # K = floor(N p + 1/2) with p = k / N is k exactly (N p differs from k by < 1/2)
+        bits = perc.perc_sample_fixed(lat, int(k) / N, seed, n_cfg, stream=stream)
+        keep.append(bits)
+        jobs += [(lat, bits[c], g) for c in range(n_cfg)]
+    _, _, _, counts = perc.perc_batch(jobs, n_groups=len(ks), stream=stream, **opts)
+    return np.array(counts, dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------------
 # GPU sweeps (one batch each)
 # ---------------------------------------------------------------------------------
 

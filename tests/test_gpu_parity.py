@@ -382,3 +382,30 @@ def test_wide_fiber_many_tiles(perc):
     np.testing.assert_array_equal(r32.cpu().numpy().astype(bool), r64)
     big = x64 >= 2.0 ** -100
     np.testing.assert_allclose(x32.cpu().numpy().astype(np.float64)[big], x64[big], rtol=1e-5, atol=0)
+
+
+def test_fixed_count_curve_and_binomial_convolution(perc):
+    """Pi_k of the fixed-count ensemble on the GPU at every k of a 19-tube fiber (W=2,
+    L=3): counts equal the oracle's on the same configurations, agree with the exact
+    a_k / C(N, k) of the exhaustive enumeration within 5 sigma, and their binomial
+    convolution matches the exact Bernoulli Pi(p)."""
+    from math import comb
+    from paper_1401_2130_amd import fss
+    W, L, n, seed = 2, 3, 1024, 8
+    ref = oracle.Lattice(W, L)
+    N = ref.n
+    ks = list(range(N + 1))
+    counts = fss.pi_fixed_counts(W, L, ks, n, seed)
+    torch.cuda.synchronize()
+    a = ref.exhaustive()
+    exact = np.array([a[k] / comb(N, k) for k in ks])
+    for k in ks:
+        pm, _, _ = ref.inspect_markov(ref.sample_fixed(k / N, seed, n))
+        assert counts[k] == int(pm.sum()), k
+        sig = math.sqrt(max(exact[k] * (1 - exact[k]), 1.0 / n) / n)
+        assert abs(counts[k] / n - exact[k]) <= 5 * sig, (k, counts[k] / n, exact[k])
+    ps = [0.2, 0.4, 0.6]
+    got, miss = fss.binomial_convolution(ks, counts / n, N, ps)
+    want = np.array([oracle.pi_from_counts(a, p) for p in ps])
+    assert np.all(miss < 1e-12)
+    assert np.all(np.abs(got - want) <= 5 / math.sqrt(n))
