@@ -177,6 +177,64 @@ def first_passage_leg(perc, workloads, stream, M: int):
             "max_f": float(f.max().item()), "nonzero": int((f > 0).sum().item())}
 
 
+def ablation_leg(perc, workloads, stream):
+    """Regular FCC (no end contacts) against the modified lattice on the same Philox
+    configurations: Eq. 5 threshold per near-cubic shape, Eq. 7 intercept at the one
+    aspect ratio (literature value for regular FCC: 0.199)."""
+    from paper_1401_2130_amd import fss
+    wl = workloads.ABLATION
+    out = {"workload": f"shapes {list(wl.shapes)} (L = 1.5 W layers), p = 0.120..0.240 step 0.005 x {wl.n_cfg}, "
+                       f"Philox seed {wl.seed}, both lattice variants", "variants": {}}
+    n_cfg_total, wall = 0, 0.0
+    for ends, name in ((False, "regular_fcc"), (True, "modified")):
+        torch_sync()
+        t0 = time.perf_counter()
+        counts = fss.pi_table(wl.shapes, wl.ps, wl.n_cfg, wl.seed, stream=stream, ends=ends)
+        torch_sync()
+        wall += time.perf_counter() - t0
+        n_cfg_total += len(wl.shapes) * len(wl.ps) * wl.n_cfg
+        per = []
+        for (W, L) in wl.shapes:
+            pis = [counts[(W, L, float(p))] / wl.n_cfg for p in wl.ps]
+            try:
+                pc, T, cov = fss.fit_fermi_dirac(wl.ps, pis, wl.n_cfg)
+                per.append({"W": W, "L": L, "pc": pc, "T": T, "pc_err": float(cov[0, 0] ** 0.5)})
+            except Exception as e:  # a fit that does not converge is reported, not hidden
+                per.append({"W": W, "L": L, "error": str(e)})
+        ok = [r for r in per if "pc" in r]
+        pinf = fss.fit_eq7([r["W"] for r in ok], [r["L"] for r in ok], [r["pc"] for r in ok])[0] if len(ok) >= 2 else None
+        out["variants"][name] = {"per_shape": per, "pc_inf_eq7": pinf}
+    out["configs"] = n_cfg_total
+    out["configs_per_s"] = n_cfg_total / wall
+    return out
+
+
+def fig6a_leg(perc, workloads, stream):
+    """Pi against the fiber length at W = 3 (Fig. 6a): decay rate per p from ln Pi
+    linear in L, and the line -ln(rate) against p (its inset)."""
+    from paper_1401_2130_amd import fss
+    wl = workloads.FIG6A
+    torch_sync()
+    t0 = time.perf_counter()
+    counts = fss.pi_table(wl.shapes, wl.ps, wl.n_cfg, wl.seed, stream=stream)
+    torch_sync()
+    wall = time.perf_counter() - t0
+    Ls = [L for (_, L) in wl.shapes]
+    rows, lams, plist = {}, [], []
+    for p in wl.ps:
+        pis = [counts[(3, L, float(p))] / wl.n_cfg for L in Ls]
+        fit = fss.decay_rate(Ls, pis, wl.n_cfg)
+        rows[f"{p}"] = {"pi": pis, "decay": fit}
+        if fit and fit["lambda"] > 0:
+            lams.append(fit["lambda"])
+            plist.append(p)
+    line = fss.log_rate_slope(plist, lams)
+    n_jobs = len(wl.shapes) * len(wl.ps) * wl.n_cfg
+    return {"workload": f"W=3, L in {Ls} layers, p in {list(wl.ps)} x {wl.n_cfg}, Philox seed {wl.seed}",
+            "configs": n_jobs, "configs_per_s": n_jobs / wall, "per_p": rows,
+            "rate_unit": "per layer", "neg_log_rate_vs_p": None if line is None else {"b0": line[0], "b1": line[1]}}
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -232,6 +290,8 @@ def main():
     ap.add_argument("--batched", type=int, default=1, help="batched Pi(p) leg (W=16 L=256, 21 p x 4096)")
     ap.add_argument("--first-passage", type=int, default=1024,
                     help="moves of the backward all-sources leg on the headline fiber (0: skip)")
+    ap.add_argument("--ablation", type=int, default=1, help="regular FCC vs modified lattice thresholds")
+    ap.add_argument("--fig6a", type=int, default=1, help="Pi against L at W=3, decay rates")
     ap.add_argument("--uneven", type=int, default=1, help="uneven aspect-ratio sweep leg (35 shapes x 2 p x 1024)")
     args = ap.parse_args()
 
@@ -389,6 +449,15 @@ def main():
         log("uneven aspect-ratio leg ...")
         result["uneven"] = uneven_leg(perc, workloads, stream)
         log(f"uneven: {result['uneven']['configs_per_s']:.0f} configs/s, pc_inf {result['uneven']['pc_inf']}")
+    if args.ablation:
+        log("ablation leg (regular FCC) ...")
+        result["ablation"] = ablation_leg(perc, workloads, stream)
+        log(f"ablation: pc_inf regular {result['ablation']['variants']['regular_fcc']['pc_inf_eq7']}, "
+            f"modified {result['ablation']['variants']['modified']['pc_inf_eq7']}")
+    if args.fig6a:
+        log("Fig. 6a leg (Pi vs L at W=3) ...")
+        result["fig6a"] = fig6a_leg(perc, workloads, stream)
+        log(f"fig6a: {result['fig6a']['neg_log_rate_vs_p']}")
     if args.serve_requests > 0:
         log(f"serving: {args.serve_requests} requests at {workloads.SERVING.rate_hz:.0f}/s ...")
         result["serving"] = {"offered": serving_leg(perc, workloads, args.serve_requests, workloads.SERVING.rate_hz,

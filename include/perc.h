@@ -82,6 +82,15 @@ typedef struct perc_lattice perc_lattice;
  * bad argument or more than 2^31-1 sites. Owned by the caller; immutable; safe to use
  * from several threads and streams at once. */
 perc_lattice* perc_lattice_create(int32_t W, int32_t L);
+
+/* As perc_lattice_create with options: PERC_LATTICE_NO_END_CONTACTS drops the two end
+ * contacts of every tube, leaving the regular FCC lattice of the same sites (12 side
+ * contacts), the lattice the paper compares its threshold with (Sec. III). Sites, site
+ * order, surfaces, the detector edge and the sampler streams are those of the modified
+ * lattice, so both variants can be inspected on the same configurations. Unknown flag
+ * bits: NULL. */
+#define PERC_LATTICE_NO_END_CONTACTS 1
+perc_lattice* perc_lattice_create_ex(int32_t W, int32_t L, int32_t flags);
 void perc_lattice_destroy(perc_lattice* lat); /* NULL-safe */
 
 int64_t perc_lattice_sites(const perc_lattice* lat);   /* N */

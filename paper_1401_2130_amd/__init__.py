@@ -22,6 +22,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_build", "libperc.so")
 
 PERC_OK, PERC_EINVAL, PERC_ENOMEM, PERC_EHIP, PERC_EBUSY, PERC_ECANCELED, PERC_ECAP = 0, -1, -2, -3, -4, -5, -6
+PERC_LATTICE_NO_END_CONTACTS = 1
 FORM_AUTO, FORM_PLAIN, FORM_SPAN, FORM_PERSIST = 0, 1, 2, 3
 _FORMS = {"auto": FORM_AUTO, "plain": FORM_PLAIN, "span": FORM_SPAN, "persist": FORM_PERSIST}
 
@@ -80,6 +81,8 @@ def _load():
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     lib.perc_lattice_create.restype = vp
     lib.perc_lattice_create.argtypes = [i32, i32]
+    lib.perc_lattice_create_ex.restype = vp
+    lib.perc_lattice_create_ex.argtypes = [i32, i32, i32]
     lib.perc_lattice_destroy.argtypes = [vp]
     for f in ("perc_lattice_sites", "perc_lattice_words", "perc_lattice_state_bytes"):
         getattr(lib, f).restype = i64
@@ -115,7 +118,7 @@ def _load():
 
 _lib = _load()
 
-EXPORTED = ("perc_lattice_create", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
+EXPORTED = ("perc_lattice_create", "perc_lattice_create_ex", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
             "perc_last_error", "perc_sample", "perc_sample_fixed", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
             "perc_batch", "perc_state_after", "perc_first_passage", "perc_steps_hist", "perc_profile_enable", "perc_profile_read", "perc_autotune",
@@ -159,10 +162,12 @@ def _options(form="auto", depth=0, block=0, grid=0, graph_steps=0) -> perc_optio
 
 
 class Lattice:
-    """Handle of ``perc_lattice_create(W, L)`` (destroyed with the object)."""
+    """Handle of ``perc_lattice_create_ex(W, L, flags)`` (destroyed with the object);
+    ``ends=False`` gives the regular FCC lattice (PERC_LATTICE_NO_END_CONTACTS)."""
 
-    def __init__(self, W: int, L: int):
-        h = _lib.perc_lattice_create(int(W), int(L))
+    def __init__(self, W: int, L: int, ends: bool = True):
+        h = _lib.perc_lattice_create_ex(int(W), int(L), 0 if ends else PERC_LATTICE_NO_END_CONTACTS)
+        self.ends = bool(ends)
         if not h:
             raise PercError(PERC_EINVAL, perc_last_error())
         self._h = h
@@ -185,7 +190,7 @@ class Lattice:
             self._h = None
 
     def __repr__(self):
-        return f"Lattice(W={self.W}, L={self.L}, sites={self.n})"
+        return f"Lattice(W={self.W}, L={self.L}, sites={self.n}{'' if self.ends else ', regular FCC'})"
 
 
 def perc_lattice_create(W: int, L: int) -> Lattice:

@@ -302,7 +302,7 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
     const float s67 = mag(n[6]) + mag(n[7]);
     const float s89 = mag(n[8]) + mag(n[9]);
     const float sab = mag(n[10]) + mag(n[11]);
-    const float sud = mag(dn) + mag(up);
+    const float sud = sh.ends ? mag(dn) + mag(up) : 0.0f;
     const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
     // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its
     // own mass
@@ -438,7 +438,8 @@ __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, c
         load_occ_quad(sh, st, rk, bits, g + 2, is.next);
     }
     const uint32_t me = w.me[(K + 1) * kBlkCols];
-    uint32_t deg = w.me[K * kBlkCols] + w.me[(K + 2) * kBlkCols] + (u == w.top ? 1u : 0u);
+    // end contacts (same column, the cells below and above) unless the lattice is regular FCC
+    uint32_t deg = (sh.ends ? w.me[K * kBlkCols] + w.me[(K + 2) * kBlkCols] : 0u) + (u == w.top ? 1u : 0u);
 #pragma unroll
     for (int i = 0; i < kSide; ++i) deg += w.nb[i][K * kBlkCols];
     const uint32_t cd = me ? deg : 15u;

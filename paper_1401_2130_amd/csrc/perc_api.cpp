@@ -109,6 +109,7 @@ int shape_of(const LatticeDesc& d, DevShape& sh) {
     sh.sig = cd.sig;
     sh.C = d.C; sh.CP = d.CP; sh.U = d.U; sh.L = d.L;
     sh.ntile = d.ntile; sh.span_max = d.span_max; sh.tile_max = d.tile_max; sh.W = d.W;
+    sh.ends = d.ends; sh.pad0 = 0;
     sh.N = d.N; sh.words = d.words;
     return PERC_OK;
 }
@@ -1279,7 +1280,11 @@ int one_setup(const perc_lattice* lat, const uint32_t* occ_bits, hipStream_t s, 
 
 extern "C" {
 
-perc_lattice* perc_lattice_create(int32_t W, int32_t L) {
+perc_lattice* perc_lattice_create_ex(int32_t W, int32_t L, int32_t flags) {
+    if (flags & ~PERC_LATTICE_NO_END_CONTACTS) {
+        g_err = "unknown lattice flags";
+        return nullptr;
+    }
     perc_lattice* lat = new (std::nothrow) perc_lattice();
     if (!lat) {
         g_err = "out of host memory";
@@ -1291,8 +1296,11 @@ perc_lattice* perc_lattice_create(int32_t W, int32_t L) {
         delete lat;
         return nullptr;
     }
+    lat->d.ends = (flags & PERC_LATTICE_NO_END_CONTACTS) ? 0 : 1;
     return lat;
 }
+
+perc_lattice* perc_lattice_create(int32_t W, int32_t L) { return perc_lattice_create_ex(W, L, 0); }
 
 void perc_lattice_destroy(perc_lattice* lat) { delete lat; }
 
@@ -1331,8 +1339,10 @@ int perc_site_neighbors(const perc_lattice* lat, int64_t s, int64_t* nbr, int32_
         const int32_t v = cs.nb[(size_t)i * d.C + c];
         add(u + ((v & 3) - 1), v >> 2);
     }
-    add(u - 1, c);
-    add(u + 1, c);
+    if (d.ends) {
+        add(u - 1, c);
+        add(u + 1, c);
+    }
     std::sort(out.begin(), out.end());
     *count = (int32_t)out.size();
     for (size_t i = 0; i < out.size(); ++i) nbr[i] = out[i];

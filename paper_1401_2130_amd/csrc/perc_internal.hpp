@@ -77,6 +77,7 @@ struct LatticeDesc {
     int64_t N = 0;       // sites
     int64_t words = 0;   // ceil(N / 32)
     int32_t ntile = 1, span_max = 0, tile_max = 0;
+    int32_t ends = 1;    // 1: the two end contacts per tube; 0: regular FCC
     // cell of the far-end tube of column c (the highest layer k < L with k = sigma), or
     // -1 if the column holds no tube
     int32_t top(int32_t c) const {
@@ -123,6 +124,7 @@ struct DevShape {
     const int32_t* sig;     // [C]
     int32_t C, CP, U, L;
     int32_t ntile, span_max, tile_max, W;
+    int32_t ends, pad0;  // ends: 1 with end contacts (modified lattice), 0 regular FCC
     int64_t N, words;
 };
 

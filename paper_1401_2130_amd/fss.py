@@ -98,6 +98,39 @@ def eq9(W, L, pc_inf: float, C0: float, C1: float, alpha: float, nu: float = NU_
     return pc_inf + C0 * L ** (-1.0 / nu) + C1 * W ** alpha * L ** (-alpha - 1.0 / nu)
 
 
+def decay_rate(Ls: Sequence[float], pis: Sequence[float], n: int, min_count: int = 8) -> Optional[dict]:
+    """Block-product model of Sec. III (Fig. 6a): Pi = prod_i (1 - lambda_i) ~ exp(-lambda L)
+    for a long fiber. Weighted least squares of ln Pi = a - lambda L over the points with
+    at least min_count percolating and min_count non-percolating configurations out of n
+    (variance of ln Pi ~ (1 - Pi) / (n Pi)). Returns {lambda, a, lambda_err, points} or
+    None with fewer than two usable points."""
+    L = np.asarray(Ls, dtype=np.float64)
+    pi = np.asarray(pis, dtype=np.float64)
+    use = (pi * n >= min_count) & ((1.0 - pi) * n >= min_count)
+    if use.sum() < 2:
+        return None
+    L, pi = L[use], pi[use]
+    w = n * pi / (1.0 - pi)  # 1 / var(ln Pi)
+    A = np.stack([np.ones_like(L), -L], axis=1)
+    sw = np.sqrt(w)
+    sol, *_ = np.linalg.lstsq(A * sw[:, None], np.log(pi) * sw, rcond=None)
+    cov = np.linalg.inv((A * w[:, None]).T @ A)
+    return {"lambda": float(sol[1]), "a": float(sol[0]), "lambda_err": float(math.sqrt(cov[1, 1])),
+            "points": int(use.sum())}
+
+
+def log_rate_slope(ps: Sequence[float], lams: Sequence[float]) -> Optional[Tuple[float, float]]:
+    """Sec. III estimate -ln(lambda) ~ p (the inset of Fig. 6a): least-squares line
+    -ln(lambda) = b0 + b1 p over the positive rates; (b0, b1) or None."""
+    p = np.asarray(ps, dtype=np.float64)
+    lam = np.asarray(lams, dtype=np.float64)
+    ok = lam > 0
+    if ok.sum() < 2:
+        return None
+    b1, b0 = np.polyfit(p[ok], -np.log(lam[ok]), 1)
+    return float(b0), float(b1)
+
+
 # ---------------------------------------------------------------------------------
 # Fixed-count ensemble (Sec. II.A) and its relation to the Bernoulli ensemble
 # ---------------------------------------------------------------------------------
@@ -150,13 +183,13 @@ def pi_fixed_counts(W: int, L: int, ks: Sequence[int], n_cfg: int, seed: int, st
 # ---------------------------------------------------------------------------------
 
 def pi_table(shapes: Iterable[Tuple[int, int]], ps: Sequence[float], n_cfg: int, seed: int, stream=None,
-             **opts) -> Dict[Tuple[int, int, float], int]:
+             ends: bool = True, **opts) -> Dict[Tuple[int, int, float], int]:
     """Percolating counts for every (W, L) x p, configurations 0..n_cfg-1 of the Philox
     stream `seed` (common random numbers across p), all in one perc_batch call (mixed
     shapes in one work list). Returns {(W, L, p): count}."""
     import paper_1401_2130_amd as perc
     shapes = list(shapes)
-    lats = {s: perc.Lattice(*s) for s in shapes}
+    lats = {s: perc.Lattice(*s, ends=ends) for s in shapes}
     jobs, keys = [], []
     for (W, L) in shapes:
         for p in ps:
@@ -167,9 +200,10 @@ def pi_table(shapes: Iterable[Tuple[int, int]], ps: Sequence[float], n_cfg: int,
     return {k: int(c) for k, c in zip(keys, counts)}
 
 
-def pi_curve(W: int, L: int, ps: Sequence[float], n_cfg: int, seed: int, stream=None, **opts) -> np.ndarray:
-    """Pi(p) estimates of one fiber at every p (one batch)."""
-    t = pi_table([(W, L)], ps, n_cfg, seed, stream=stream, **opts)
+def pi_curve(W: int, L: int, ps: Sequence[float], n_cfg: int, seed: int, stream=None, ends: bool = True,
+             **opts) -> np.ndarray:
+    """Pi(p) estimates of one fiber at every p (one batch); ends=False: regular FCC."""
+    t = pi_table([(W, L)], ps, n_cfg, seed, stream=stream, ends=ends, **opts)
     return np.array([t[(W, L, float(p))] / n_cfg for p in ps])
 
 

@@ -39,6 +39,17 @@ UNEVEN = Workload("uneven aspect sweep", tuple((w, w * a) for w in (8, 12, 16, 2
                   (0.1533, 0.16), 4, 1024, "mixed shapes in one batch; finite-size scaling")
 
 
+# Ablation (Sec. III comparison with the regular FCC lattice, threshold 0.199 in the
+# literature): near-cubic fibers, L = 1.5 W layers (about 2.1 W tube spacings long against
+# a 2 W diameter), both lattice variants on the same Philox configurations.
+ABLATION = Workload("regular FCC vs modified", ((12, 18), (16, 24), (24, 36), (32, 48)),
+                    tuple((120 + 5 * i) / 1000.0 for i in range(25)), 6, 1024,
+                    "Pi(p) of both lattice variants; Eq. 5 per shape, Eq. 7 at one aspect ratio")
+# Fig. 6a: Pi against the fiber length at W = 3 for several p (exponential decay).
+FIG6A = Workload("Pi vs L at W=3", tuple((3, L) for L in (6, 12, 24, 48, 96, 192, 384, 768, 1536, 3072)),
+                 (0.2, 0.25, 0.3, 0.35, 0.4, 0.45, 0.5), 7, 2048, "decay rate per p; -ln(rate) against p")
+
+
 @dataclass(frozen=True)
 class ServingRecipe:
     rate_hz: float = 2000.0

@@ -1,0 +1,111 @@
+"""The regular FCC lattice (PERC_LATTICE_NO_END_CONTACTS, the Sec. III comparison) on the
+GPU through the C ABI, against the oracle's regular build: bits and steps bit-exact in
+every execution form, FP32 state and first-hit probability within the derived bounds,
+mixed batches of both lattice variants, and the bond-removal inequality on the device."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1401_2130_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+U24 = 2.0 ** -24
+FORMS = [("plain", 8), ("span", 8), ("span", 24), ("persist", 16)]
+SHAPES = [(0, 2), (0, 10), (1, 4), (2, 13), (3, 9), (4, 17), (7, 44), (16, 40)]
+
+
+@pytest.fixture(scope="module")
+def perc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1401_2130_amd as p
+    return p
+
+
+def dev(words: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(words).view(np.int32)).cuda()
+
+
+def check_hit(hit_gpu, hit_ref, perc_ref, steps_ref):
+    for i in np.nonzero(perc_ref)[0]:
+        ref = hit_ref[i]
+        if ref < 2.0 ** -100:
+            continue
+        assert abs(hit_gpu[i] - ref) <= (6 * steps_ref[i] + 24) * U24 * ref, (i, hit_gpu[i], ref)
+    assert np.all(hit_gpu[perc_ref == 0] == 0.0)
+
+
+@pytest.mark.parametrize("W,L", SHAPES)
+@pytest.mark.parametrize("form,depth", FORMS)
+def test_regular_fcc_inspect_matches_oracle(perc, W, L, form, depth):
+    lat = perc.Lattice(W, L, ends=False)
+    ref = oracle.Lattice(W, L, ends=False)
+    occ = np.concatenate([workloads.random_occupancy(ref.n, 24, p, seed + 10 * W + L)
+                          for p, seed in ((0.2, 1), (0.35, 2), (0.6, 3), (0.95, 4))])
+    pm, sm, hm = ref.inspect_markov(occ)
+    pg, sg, hg = perc.perc_inspect_ex(lat, dev(occ), hit=True, form=form, depth=depth)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pg.cpu().numpy(), pm)
+    np.testing.assert_array_equal(sg.cpu().numpy(), sm)
+    check_hit(hg.cpu().numpy().astype(np.float64), hm, pm, sm)
+
+
+@pytest.mark.parametrize("W,L,p,K", [(3, 13, 0.5, 1), (4, 16, 0.4, 16), (8, 50, 0.3, 16)])
+def test_regular_fcc_state_after(perc, W, L, p, K):
+    lat = perc.Lattice(W, L, ends=False)
+    ref = oracle.Lattice(W, L, ends=False)
+    occ = workloads.random_occupancy(ref.n, 1, p, 50 + K + W)
+    x64, r64 = ref.state_after(occ, K)
+    x32, r32 = perc.perc_state_after(lat, dev(occ[0]), K)
+    torch.cuda.synchronize()
+    x32 = x32.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(r32.cpu().numpy().astype(bool), r64)
+    big = x64 >= 2.0 ** -100
+    np.testing.assert_allclose(x32[big], x64[big], rtol=1e-5, atol=0)
+
+
+def test_regular_fcc_first_passage(perc):
+    W, L, M = 4, 20, 12
+    lat = perc.Lattice(W, L, ends=False)
+    ref = oracle.Lattice(W, L, ends=False)
+    occ = workloads.random_occupancy(ref.n, 1, 0.5, 91)
+    f64 = ref.first_passage_all(occ[0], M)
+    f32 = perc.perc_first_passage(lat, dev(occ[0]), M).cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(f32 - f64) <= (6 * M + 8) * U24 * f64 + (M + 1) * 2.0 ** -146)
+
+
+@pytest.mark.parametrize("form", ["span", "persist"])
+def test_mixed_variants_in_one_batch(perc, form):
+    """Jobs on both lattice variants of the same and of different shapes in one
+    perc_batch; Philox jobs draw the same configurations on both variants."""
+    shapes = [(3, 12), (5, 30)]
+    jobs, want_p, want_s = [], [], []
+    for (W, L) in shapes:
+        for ends in (True, False):
+            lat = perc.Lattice(W, L, ends=ends)
+            ref = oracle.Lattice(W, L, ends=ends)
+            bits = ref.sample(0.3, 6, 20)
+            pm, sm, _ = ref.inspect_markov(bits)
+            jobs += [(lat, 0.3, 6, c) for c in range(20)]
+            want_p.append(pm)
+            want_s.append(sm)
+    pg, sg, _, _ = perc.perc_batch(jobs, form=form)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pg.cpu().numpy(), np.concatenate(want_p))
+    np.testing.assert_array_equal(sg.cpu().numpy(), np.concatenate(want_s))
+
+
+def test_bond_removal_on_device(perc):
+    """Same Philox configurations on both variants: regular FCC percolation implies
+    modified-lattice percolation; counts of the Pi sweep are ordered the same way."""
+    W, L, n = 8, 64, 512
+    a, b = perc.Lattice(W, L), perc.Lattice(W, L, ends=False)
+    for p in (0.16, 0.2, 0.24):
+        pa, sa, _, _ = perc.perc_batch([(a, p, 3, c) for c in range(n)])
+        pb, sb, _, _ = perc.perc_batch([(b, p, 3, c) for c in range(n)])
+        pa, pb = pa.cpu().numpy(), pb.cpu().numpy()
+        assert np.all(pa >= pb)
+        both = (pa == 1) & (pb == 1)
+        assert np.all(sb.cpu().numpy()[both] >= sa.cpu().numpy()[both])

@@ -385,13 +385,13 @@ def test_wide_fiber_many_tiles(perc):
 
 
 def test_fixed_count_curve_and_binomial_convolution(perc):
-    """Pi_k of the fixed-count ensemble on the GPU at every k of a 19-tube fiber (W=2,
-    L=3): counts equal the oracle's on the same configurations, agree with the exact
+    """Pi_k of the fixed-count ensemble on the GPU at every k of a 21-tube fiber (W=1,
+    L=9): counts equal the oracle's on the same configurations, agree with the exact
     a_k / C(N, k) of the exhaustive enumeration within 5 sigma, and their binomial
     convolution matches the exact Bernoulli Pi(p)."""
     from math import comb
     from paper_1401_2130_amd import fss
-    W, L, n, seed = 2, 3, 1024, 8
+    W, L, n, seed = 1, 9, 1024, 8
     ref = oracle.Lattice(W, L)
     N = ref.n
     ks = list(range(N + 1))

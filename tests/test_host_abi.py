@@ -48,6 +48,23 @@ def test_descriptor_matches_oracle_geometry(W, L):
         assert perc.perc_site_neighbors(lat, s) == sorted(idx[ptr[s]:ptr[s + 1]].tolist())
 
 
+@pytest.mark.parametrize("W,L", [(0, 7), (1, 8), (3, 9), (5, 23)])
+def test_regular_fcc_descriptor_matches_oracle(W, L):
+    """PERC_LATTICE_NO_END_CONTACTS: same sites and order, contacts of the oracle's
+    regular FCC build."""
+    lat = perc.Lattice(W, L, ends=False)
+    ref = oracle.Lattice(W, L, ends=False)
+    assert lat.n == ref.n and lat.words == ref.words
+    ptr, idx = ref.adjacency()
+    for s in range(lat.n):
+        assert perc.perc_site_neighbors(lat, s) == sorted(idx[ptr[s]:ptr[s + 1]].tolist())
+
+
+def test_unknown_lattice_flags_rejected():
+    assert not perc._lib.perc_lattice_create_ex(2, 6, 2)
+    assert "flags" in perc.perc_last_error()
+
+
 def test_descriptor_large_sizes():
     for W, L, n in [(16, 256, 69716), (32, 1024, 1081686), (64, 4096, 17040724)]:
         lat = perc.Lattice(W, L)
