@@ -231,3 +231,221 @@ def uneven_analysis(counts: Dict[Tuple[int, int, float], int], n_cfg: int, nu: f
             except Exception as e:  # a fit that does not converge is reported, not raised
                 out["eq8"] = {"error": str(e)}
     return out
+
+
+# ---------------------------------------------------------------------------------
+# Paper-scale finite-size scaling (Fig. 3-5): per-shape Eq. 5 fits at 1,024
+# configurations per point on a p window found by a coarse pass, then Eq. 7-9
+# ---------------------------------------------------------------------------------
+
+def pi_keys(keys: Sequence[Tuple[int, int, float]], n_cfg: int, seed: int, stream=None, ends: bool = True,
+            **opts) -> Dict[Tuple[int, int, float], int]:
+    """Percolating counts for arbitrary (W, L, p) points, configurations 0..n_cfg-1 of the
+    Philox stream `seed`, all in one perc_batch call."""
+    import paper_1401_2130_amd as perc
+    lats: Dict[Tuple[int, int], object] = {}
+    jobs = []
+    for g, (W, L, p) in enumerate(keys):
+        if (W, L) not in lats:
+            lats[(W, L)] = perc.Lattice(W, L, ends=ends)
+        jobs += [(lats[(W, L)], float(p), seed, c, g) for c in range(n_cfg)]
+    _, _, _, counts = perc.perc_batch(jobs, n_groups=len(keys), stream=stream, **opts)
+    return {(int(W), int(L), float(p)): int(c) for (W, L, p), c in zip(keys, counts)}
+
+
+def fine_window(ps: Sequence[float], pis: Sequence[float], n: int, n_p: int, width: float = 3.0,
+                t_min: float = 0.002) -> List[float]:
+    """n_p points spanning p_c +- width T of a coarse Eq. 5 fit (p_c from the crossing of
+    1/2 if the fit fails; T at least half the coarse spacing), inside [0, 1], rounded to
+    1e-4."""
+    ps = np.asarray(ps, dtype=np.float64)
+    pis = np.asarray(pis, dtype=np.float64)
+    try:
+        pc, T, _ = fit_fermi_dirac(ps, pis, n)
+        if not (0.0 < pc < 1.0) or not (0.0 < T < 0.5):
+            raise ValueError("coarse fit out of range")
+    except Exception:
+        i = int(np.argmin(np.abs(pis - 0.5)))
+        pc, T = float(ps[i]), float(ps[1] - ps[0]) if len(ps) > 1 else 0.02
+    # the coarse grid cannot place p_c better than its spacing
+    if len(ps) > 1:
+        t_min = max(t_min, 0.5 * float(np.median(np.diff(np.sort(ps)))))
+    T = max(T, t_min)
+    lo, hi = max(pc - width * T, 1e-4), min(pc + width * T, 1.0 - 1e-4)
+    return [round(float(x), 4) for x in np.linspace(lo, hi, n_p)]
+
+
+def fss_analysis(counts: Dict[Tuple[int, int, float], int], n_cfg: int, nu: float = NU_3D,
+                 min_w: int = 0) -> dict:
+    """Eq. 5 per shape (p_c, T and the standard error of p_c); Eq. 7 with a common
+    intercept over the aspect ratios W/L that hold two or more shapes (weighted by
+    1/err^2, with the intercept's standard error); Eq. 8 on their slopes; Eq. 9
+    residuals of every shape; the Fig. 5 check (p_c linear in W^alpha at fixed L); and
+    the constants in the paper's length unit (unit cells = 3 layers). Shapes narrower than
+    min_w enter the per-shape table only (corrections to scaling are largest there)."""
+    from fractions import Fraction
+    by_shape: Dict[Tuple[int, int], List[Tuple[float, float]]] = {}
+    for (W, L, p), c in counts.items():
+        by_shape.setdefault((W, L), []).append((p, c / n_cfg))
+    rows = []
+    for (W, L), pts in sorted(by_shape.items()):
+        pts.sort()
+        ps, pis = [x[0] for x in pts], [x[1] for x in pts]
+        row = {"W": W, "L": L, "p": ps, "pi": pis}
+        try:
+            pc, T, cov = fit_fermi_dirac(ps, pis, n_cfg)
+            if not (ps[0] <= pc <= ps[-1]) or not (0.0 < T < 1.0):
+                raise ValueError(f"threshold {pc:.4g} outside the sampled window {ps[0]}..{ps[-1]}")
+            row.update(pc=pc, T=T, pc_err=float(math.sqrt(max(cov[0, 0], 0.0))))
+        except Exception as e:  # reported, not raised
+            row["error"] = str(e)
+        rows.append(row)
+    out: dict = {"shapes": rows, "n_cfg": n_cfg, "nu": nu}
+    ok = [r for r in rows if "pc" in r and r["pc_err"] > 0 and r["W"] >= min_w]
+    out["min_w"] = min_w
+    groups: Dict[Fraction, List[dict]] = {}
+    for r in ok:
+        groups.setdefault(Fraction(r["W"], r["L"]), []).append(r)
+    multi = [r for k, g in groups.items() if len(g) >= 2 for r in g]
+    if len(multi) >= 3:
+        keys = sorted({Fraction(r["W"], r["L"]) for r in multi})
+        A = np.zeros((len(multi), 1 + len(keys)))
+        A[:, 0] = 1.0
+        for i, r in enumerate(multi):
+            A[i, 1 + keys.index(Fraction(r["W"], r["L"]))] = r["L"] ** (-1.0 / nu)
+        y = np.array([r["pc"] for r in multi])
+        w = np.array([1.0 / r["pc_err"] ** 2 for r in multi])
+        AtWA = (A * w[:, None]).T @ A
+        sol = np.linalg.solve(AtWA, (A * w[:, None]).T @ y)
+        cov = np.linalg.inv(AtWA)
+        chi2 = float((((A @ sol) - y) ** 2 * w).sum())
+        dof = max(len(multi) - A.shape[1], 1)
+        scale = max(chi2 / dof, 1.0)  # inflate by the scatter beyond the binomial errors
+        out["pc_inf"] = float(sol[0])
+        out["pc_inf_err"] = float(math.sqrt(cov[0, 0] * scale))
+        out["eq7_chi2_per_dof"] = chi2 / dof
+        slopes = {float(k): float(sol[1 + j]) for j, k in enumerate(keys)}
+        out["slopes"] = {f"{k:.6g}": v for k, v in slopes.items()}
+        if len(slopes) >= 3:
+            try:
+                C0, C1, alpha = fit_eq8(list(slopes), list(slopes.values()))
+                out["eq8"] = {"C0": C0, "C1": C1, "alpha": alpha}
+                k = 3.0 ** (-1.0 / nu)
+                out["eq8_paper_units"] = {"C0": C0 * k, "C1": C1 * k * 3.0 ** (-alpha), "alpha": alpha}
+                res = []
+                for r in ok:
+                    pred = float(eq9(r["W"], r["L"], out["pc_inf"], C0, C1, alpha, nu))
+                    res.append((r["pc"] - pred) / r["pc_err"])
+                out["eq9_residual_sigma"] = {"rms": float(np.sqrt(np.mean(np.square(res)))),
+                                             "max": float(np.max(np.abs(res)))}
+                fig5 = {}
+                for L in sorted({r["L"] for r in ok}):
+                    g = [r for r in ok if r["L"] == L]
+                    if len(g) >= 3:
+                        xw = np.array([r["W"] ** alpha for r in g])
+                        b1, b0 = np.polyfit(xw, [r["pc"] for r in g], 1)
+                        fig5[str(L)] = {"slope": float(b1), "intercept": float(b0),
+                                        "eq9_slope": C1 * L ** (-alpha - 1.0 / nu), "shapes": len(g)}
+                out["fig5"] = fig5
+            except Exception as e:
+                out["eq8"] = {"error": str(e)}
+    return out
+
+
+def paper_scale_sweep(shapes: Sequence[Tuple[int, int]], seed: int, n_cfg: int = 1024, n_coarse: int = 128,
+                      n_mid: int = 256, coarse_ps: Optional[Sequence[float]] = None, n_p: int = 12, stream=None,
+                      log=None, ends: bool = True, **opts) -> dict:
+    """Four passes per shape: a coarse p grid (n_coarse configurations), two windows of n_p
+    points around the last Eq. 5 threshold (n_mid each), and the final window of n_p
+    points at p_c +- 3 T of the last fit (n_cfg configurations per point, the paper's
+    1,024).
+    Each pass runs in batches of similar-sized shapes (one perc_batch each, progress
+    reported per batch); the final counts go to fss_analysis. Passes use different
+    Philox seeds, so the final estimates do not reuse the configurations that placed
+    their window."""
+    import time
+    import paper_1401_2130_amd as perc
+    shapes = [tuple(s) for s in shapes]
+    if coarse_ps is None:
+        coarse_ps = [round(0.06 + 0.02 * i, 4) for i in range(33)]
+    log = log or (lambda *a: None)
+    size = {sh: perc.Lattice(*sh).n for sh in shapes}
+    order = sorted(shapes, key=lambda sh: size[sh])
+    t0 = time.perf_counter()
+    n_jobs = 0
+
+    def run(windows: Dict[Tuple[int, int], List[float]], n: int, pass_seed: int, name: str):
+        nonlocal n_jobs
+        budget = 5.0e12  # approximate tube-steps per batch (a few seconds of GPU time)
+        out: Dict[Tuple[int, int, float], int] = {}
+        batch: List[Tuple[int, int]] = []
+        acc = 0.0
+        for i, sh in enumerate(order):
+            batch.append(sh)
+            acc += size[sh] * n * len(windows[sh]) * sh[1]
+            if acc >= budget or i == len(order) - 1:
+                t1 = time.perf_counter()
+                keys = [(W, L, p) for (W, L) in batch for p in windows[(W, L)]]
+                out.update(pi_keys(keys, n, pass_seed, stream=stream, ends=ends, **opts))
+                n_jobs += len(keys) * n
+                log(f"{name}: {len(batch)} shapes up to {max(size[b] for b in batch)} tubes, {len(keys)} points x {n} "
+                    f"in {time.perf_counter() - t1:.1f} s")
+                batch, acc = [], 0.0
+        return out
+
+    def refine(counts, windows, n):
+        return {sh: fine_window(windows[sh], [counts[(sh[0], sh[1], float(p))] / n for p in windows[sh]], n, n_p)
+                for sh in shapes}
+
+    w = {sh: [float(p) for p in coarse_ps] for sh in shapes}
+    c = run(w, n_coarse, seed + 3000, "coarse pass")
+    w = refine(c, w, n_coarse)
+    for k in range(2):  # each middle pass narrows a window by up to the spacing it had
+        c = run(w, n_mid, seed + 2000 - 1000 * k, f"middle pass {k + 1}")
+        w = refine(c, w, n_mid)
+    counts = run(w, n_cfg, seed, "final pass")
+    out = fss_analysis(counts, n_cfg)
+    out["cuts"] = {}
+    for mw in (8, 16, 24):
+        a = fss_analysis(counts, n_cfg, min_w=mw)
+        out["cuts"][str(mw)] = {k: a.get(k) for k in ("pc_inf", "pc_inf_err", "eq7_chi2_per_dof", "eq8",
+                                                      "eq8_paper_units")}
+    out["wall_s"] = time.perf_counter() - t0
+    out["configs"] = n_jobs
+    out["largest_tubes"] = max(size.values())
+    out["passes"] = {"coarse": n_coarse, "middle": n_mid, "final": n_cfg, "points": n_p}
+    return out
+
+
+def _main(argv=None) -> int:
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="Paper-scale finite-size-scaling sweep (Fig. 3-5, Eq. 5-9) on one GPU")
+    ap.add_argument("--out", default="", help="write the result as JSON here")
+    ap.add_argument("--n-cfg", type=int, default=1024)
+    ap.add_argument("--n-p", type=int, default=12)
+    ap.add_argument("--regular-fcc", action="store_true", help="the lattice without end contacts")
+    ap.add_argument("--small", action="store_true", help="the reduced shape set (a quick check)")
+    a = ap.parse_args(argv)
+    import sys
+    import torch
+    from paper_1401_2130_amd import workloads
+    wl = workloads.FSS_SMALL if a.small else workloads.FSS_PAPER
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    res = paper_scale_sweep(wl.shapes, wl.seed, n_cfg=a.n_cfg, n_p=a.n_p, stream=stream, ends=not a.regular_fcc,
+                            log=lambda *m: print(*m, file=sys.stderr, flush=True))
+    res["workload"] = wl.name
+    res["lattice"] = "regular FCC" if a.regular_fcc else "modified FCC"
+    text = json.dumps(res)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(text + "\n")
+    print(json.dumps({k: res.get(k) for k in ("workload", "lattice", "pc_inf", "pc_inf_err", "eq7_chi2_per_dof", "eq8",
+                                               "eq8_paper_units", "eq9_residual_sigma", "cuts", "configs", "wall_s",
+                                               "largest_tubes")}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(_main())

@@ -50,6 +50,18 @@ FIG6A = Workload("Pi vs L at W=3", tuple((3, L) for L in (6, 12, 24, 48, 96, 192
                  (0.2, 0.25, 0.3, 0.35, 0.4, 0.45, 0.5), 7, 2048, "decay rate per p; -ln(rate) against p")
 
 
+# Paper-scale finite-size scaling (Sec. III, Fig. 3-5; 1,024 configurations per point,
+# lattices up to 2.7 M tubes): Fig. 3a W = 5 at L = 30..1920 layers; Fig. 3b L = 1200
+# layers (400 unit cells) at W = 3..32; Fig. 4 grid W in {4..48} x L/W in {3, 6, 12, 24}.
+FSS_PAPER = Workload("paper-scale FSS", tuple(dict.fromkeys(
+    [(5, L) for L in (30, 60, 120, 240, 480, 960, 1920)]
+    + [(W, 1200) for W in (3, 5, 8, 12, 16, 24, 32)]
+    + [(W, W * a) for W in (4, 6, 8, 12, 16, 24, 32, 48) for a in (3, 6, 12, 24)])),
+    (), 8, 1024, "p windows from a coarse pass; Eq. 5 per shape, Eq. 7-9")
+FSS_SMALL = Workload("paper-scale FSS (reduced)", tuple((W, W * a) for W in (4, 6, 8, 12) for a in (3, 6, 12)),
+                     (), 8, 256, "the same pipeline on small shapes")
+
+
 @dataclass(frozen=True)
 class ServingRecipe:
     rate_hz: float = 2000.0
