@@ -548,22 +548,22 @@ __device__ __forceinline__ void far_sum(const DevShape& sh, const float* __restr
     __syncthreads();
 }
 
-// Items [0, total) of a launch: the workgroups of one XCD share one contiguous range
-// and each takes a contiguous block of it, so a workgroup walks neighbouring tiles and
-// cell ranges of one configuration in turn.
+// Items [0, total) of a launch (tile index fastest): the workgroups of one XCD share one
+// contiguous range and deal it round-robin, so the workgroups that run side by side on
+// an XCD walk the neighbouring tiles of one cell range at the same time and read each
+// other's halo columns from that XCD's L2.
 struct ItemRange {
-    int64_t begin, end;
+    int64_t begin, end, stride;
 };
 __device__ __forceinline__ ItemRange my_items(int64_t total) {
     const int G = gridDim.x;
     if (G % kXcds != 0) {
         const int64_t b = total * blockIdx.x / G, e = total * (blockIdx.x + 1) / G;
-        return ItemRange{b, e};
+        return ItemRange{b, e, 1};
     }
     const int x = blockIdx.x % kXcds, lb = blockIdx.x / kXcds, per = G / kXcds;
     const int64_t xb = total * x / kXcds, xe = total * (x + 1) / kXcds;
-    const int64_t n = xe - xb;
-    return ItemRange{xb + n * lb / per, xb + n * (lb + 1) / per};
+    return ItemRange{xb + lb, xe, per};
 }
 
 __device__ __forceinline__ int items_of(const DevShape& sh, int ncells, int E) {
@@ -761,7 +761,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
     const int E = a.depth;
     const int n = init_count(a);
     const ItemRange it = my_items(uniform_i64(a.chunk_off + n));
-    for (int64_t g = it.begin; g < it.end; ++g) {
+    for (int64_t g = it.begin; g < it.end; g += it.stride) {
         const int i = find_entry(a.chunk_off, n, g);
         const int b = a.ids ? uniform_i32(a.ids + i) : i;
         const DevShape sh = uniform_load(a.shapes + uniform_i32(a.slot_shape + b));
@@ -875,7 +875,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
     int lo = find_entry(a.chunk_off, n_act, it.begin);
     int64_t lo_begin = uniform_i64(a.chunk_off + lo);
     int64_t lo_end = uniform_i64(a.chunk_off + lo + 1);
-    for (int64_t g = it.begin; g < it.end; ++g) {
+    for (int64_t g = it.begin; g < it.end; g += it.stride) {
         while (g >= lo_end) {  // next active slot
             ++lo;
             lo_begin = lo_end;
