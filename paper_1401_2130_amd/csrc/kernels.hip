@@ -579,6 +579,21 @@ __device__ __forceinline__ int find_entry(const int64_t* off, int n, int64_t g) 
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
+// The entry i >= lo with off[i] <= g < off[i + 1] (off non-decreasing, off[n] > g): 64
+// boundaries per probe, one load per lane and a ballot, so jumping over many short
+// entries costs one or two loads instead of one dependent load per entry. Every wave
+// computes the same (uniform) result.
+__device__ __forceinline__ int advance_entry(const int64_t* off, int n, int lo, int64_t g) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        const int idx = min(lo + 1 + lane, n);
+        const unsigned long long m = __ballot(off[idx] <= g);
+        const int c = __popcll(m);
+        lo += c;
+        if (c < 64) return __builtin_amdgcn_readfirstlane(lo);
+    }
+}
+
 // OR of a flag word over the workgroup, added to *dst: one atomic per wave that has a
 // flag (no barrier).
 __device__ __forceinline__ void flags_to(uint32_t* dst, uint32_t fl) {
@@ -761,8 +776,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
     const int E = a.depth;
     const int n = init_count(a);
     const ItemRange it = my_items(uniform_i64(a.chunk_off + n));
+    int i = it.begin < it.end ? find_entry(a.chunk_off, n, it.begin) : 0;
     for (int64_t g = it.begin; g < it.end; g += it.stride) {
-        const int i = find_entry(a.chunk_off, n, g);
+        i = advance_entry(a.chunk_off, n, i, g);
         const int b = a.ids ? uniform_i32(a.ids + i) : i;
         const DevShape sh = uniform_load(a.shapes + uniform_i32(a.slot_shape + b));
         const int local = (int)(g - uniform_i64(a.chunk_off + i));
@@ -876,9 +892,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
     int64_t lo_begin = uniform_i64(a.chunk_off + lo);
     int64_t lo_end = uniform_i64(a.chunk_off + lo + 1);
     for (int64_t g = it.begin; g < it.end; g += it.stride) {
-        while (g >= lo_end) {  // next active slot
-            ++lo;
-            lo_begin = lo_end;
+        if (g >= lo_end) {  // a later active slot
+            lo = advance_entry(a.chunk_off, n_act, lo, g);
+            lo_begin = uniform_i64(a.chunk_off + lo);
             lo_end = uniform_i64(a.chunk_off + lo + 1);
         }
         const int b = uniform_i32(a.active + lo);
