@@ -271,7 +271,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", default="span", choices=["span", "persist", "auto"])
+    ap.add_argument("--form", default="span", choices=["span", "span2", "persist", "auto"])
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--graph-steps", type=int, default=0)

@@ -60,8 +60,13 @@ enum {
     PERC_FORM_SPAN = 2,    /* many configurations at once, each spread over workgroups;
                               one launch per step over a device-built work list, replayed
                               as a HIP graph */
-    PERC_FORM_PERSIST = 3  /* one workgroup per configuration pulled from a device queue;
+    PERC_FORM_PERSIST = 3, /* one workgroup per configuration pulled from a device queue;
                               the whole inspection (sampling included) in one launch */
+    PERC_FORM_SPAN2 = 4    /* the span form advancing two steps per launch: the first step
+                              of a tile's halo range is kept in LDS and the second is
+                              computed from it, one pass over the state per two steps.
+                              PERC_EINVAL for fibers whose outer range (the halo of the
+                              halo range) exceeds two columns per thread or LDS */
 };
 
 typedef struct perc_options {

@@ -266,6 +266,29 @@ __device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
     return w;
 }
 
+// The update of one tube (Eq. 3 on the stored words y = x / deg): the 12 side contacts
+// and the two end contacts summed in one fixed pairwise order (in-layer pairs, up/down
+// layer pairs, then the end contacts), then the table entry of the tube's degree code.
+// Every walk calls this, so a tube gets the same bits whichever kernel computes it.
+__device__ __forceinline__ uint32_t tube_update(const uint32_t (&n)[kSide], uint32_t dn, uint32_t up, uint32_t own,
+                                                int32_t ends, const float4 t) {
+    const float s01 = mag(n[0]) + mag(n[1]);
+    const float s23 = mag(n[2]) + mag(n[3]);
+    const float s45 = mag(n[4]) + mag(n[5]);
+    const float s67 = mag(n[6]) + mag(n[7]);
+    const float s89 = mag(n[8]) + mag(n[9]);
+    const float sab = mag(n[10]) + mag(n[11]);
+    const float sud = ends ? mag(dn) + mag(up) : 0.0f;
+    const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
+    // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its own
+    // mass (self weight 1); for every other code the own word enters with weight 0
+    const float x = fmaf(__uint_as_float(own), t.z, sum);
+    // reached: metallic (the floor is 0 otherwise), and reached before or next to a
+    // reached tube. The new word is non-zero exactly for reached tubes: cells beyond
+    // the cut have no reached input, cells beyond U are coded insulating.
+    return __float_as_uint(fmaxf(x * t.x, (x != 0.0f || own != 0u) ? t.y : 0.0f));
+}
+
 struct StepState {
     uint4 next[kLoadCols];  // staged quads of the group after the current one
     uint32_t cq[2];         // code quads, by group parity
@@ -295,26 +318,7 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
     uint32_t n[kSide];
 #pragma unroll
     for (int i = 0; i < kSide; ++i) n[i] = w.nb[i][K * kBlkCols];
-    // fixed order: in-layer pairs, up/down-layer pairs, then the end contacts
-    const float s01 = mag(n[0]) + mag(n[1]);
-    const float s23 = mag(n[2]) + mag(n[3]);
-    const float s45 = mag(n[4]) + mag(n[5]);
-    const float s67 = mag(n[6]) + mag(n[7]);
-    const float s89 = mag(n[8]) + mag(n[9]);
-    const float sab = mag(n[10]) + mag(n[11]);
-    const float sud = sh.ends ? mag(dn) + mag(up) : 0.0f;
-    const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
-    // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its
-    // own mass
-    const float4 t = ct[cd];
-    // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its own
-    // mass (self weight 1); for every other code the own word enters with weight 0
-    const float x = fmaf(__uint_as_float(own), t.z, sum);
-    // reached: metallic (the floor is 0 otherwise), and reached before or next to a
-    // reached tube. The new word is non-zero exactly for reached tubes: cells beyond
-    // the cut have no reached input, cells beyond U are coded insulating.
-    const float yn = fmaxf(x * t.x, (x != 0.0f || own != 0u) ? t.y : 0.0f);
-    ss.res[k] = __float_as_uint(yn);
+    ss.res[k] = tube_update(n, dn, up, own, sh.ends, ct[cd]);
     ss.grew |= own == 0u ? ss.res[k] : 0u;
     if (k == 3) {
         const int u4 = u - 3;
@@ -372,6 +376,271 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
         step_cell<7>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
     }
     return (ss.grew ? F_GREW : 0u) | (ss.far ? F_FAR : 0u) | (ss.entered ? F_FRONT : 0u);
+}
+
+// ------------------------------------------------------------------------------
+// Two steps per pass. An item is a tile and a cell range, as for one step. The outer
+// ring R0 holds the input state of the tile's outer range [os, oe) (the halo of its halo
+// range); the first step is computed for every column of the halo range [hs, he) into
+// the inner ring R1, which has the layout of the one-step ring (so the one-step contact
+// table addresses it); the second step is computed for the tile's columns from R1 and
+// written to HBM. The first step runs one group of four cells ahead of the second, and
+// the cell ranges of neighbouring items overlap by one group of first-step work on each
+// side. Every tube is computed by tube_update, so the two steps give the bits of two
+// single steps; first-step words of a tube computed by several items are identical.
+// ------------------------------------------------------------------------------
+
+// Halo-range columns of this thread that compute the first step (up to kLoadCols).
+struct Prod {
+    const uint32_t* nb[kLoadCols][kSide];  // R0 word of each side contact (slot 0)
+    const uint32_t* me[kLoadCols];         // own column in R0 (row 0)
+    uint32_t* out[kLoadCols];              // own column in R1 (row 0)
+    int c[kLoadCols];
+    int top[kLoadCols];
+    bool ok[kLoadCols];  // a halo-range column (else a copy of the first one, not stored)
+    int n;               // column slots in use (uniform)
+};
+
+__device__ __forceinline__ Stage stage_range(int hs, int he, uint32_t* base) {
+    Stage st;
+    const int span = he - hs;
+    st.nj = (span + (int)blockDim.x - 1) / (int)blockDim.x;
+#pragma unroll
+    for (int j = 0; j < kLoadCols; ++j) {
+        const int lc = (int)threadIdx.x + j * (int)blockDim.x;
+        st.ok[j] = lc < span;
+        st.col[j] = st.ok[j] ? hs + lc : hs;
+        st.slot[j] = base + ring_word(0, st.ok[j] ? lc + 1 : 0);
+    }
+    return st;
+}
+
+__device__ __forceinline__ Prod prod_columns(const DevShape& sh, int k, const TileV& tv, int os,
+                                             const uint32_t* r0, uint32_t* r1) {
+    Prod p;
+    const int span = tv.he - tv.hs;
+    p.n = (span + (int)blockDim.x - 1) / (int)blockDim.x;
+    const uint32_t* tab = sh.nboff2 + (size_t)k * kSide * sh.span_max;
+#pragma unroll
+    for (int j = 0; j < kLoadCols; ++j) {
+        const int lc = (int)threadIdx.x + j * (int)blockDim.x;
+        p.ok[j] = lc < span;
+        const int l = p.ok[j] ? lc : 0;
+        p.c[j] = tv.hs + l;
+#pragma unroll
+        for (int i = 0; i < kSide; ++i) p.nb[j][i] = r0 + tab[i * sh.span_max + l];
+        p.me[j] = r0 + ring_word(0, p.c[j] - os + 1);
+        p.out[j] = r1 + ring_word(0, l + 1);
+        p.top[j] = top_of(sh, p.c[j]);
+    }
+    return p;
+}
+
+__device__ __forceinline__ Own own_column_in(const DevShape& sh, const TileV& tv, const uint32_t* base) {
+    Own w;
+    const bool cmp = (int)threadIdx.x < tv.te - tv.ts;
+    w.c = cmp ? tv.ts + (int)threadIdx.x : tv.ts;
+#pragma unroll
+    for (int i = 0; i < kSide; ++i) w.nb[i] = base + sh.nboff[i * sh.C + w.c];
+    w.me = base + ring_word(0, w.c - tv.hs + 1);
+    w.top = top_of(sh, w.c);
+    return w;
+}
+
+struct Step2State {
+    uint4 next[kLoadCols];        // staged outer quads of the group after the current one
+    uint32_t cq1[2][kLoadCols];   // halo-range code quads, by group parity
+    uint32_t cq2[2];              // tile code quads, by group parity
+    uint32_t r2[4];               // second-step words of the group before
+    uint32_t first0[kLoadCols];   // first-step words of the group's first cell (stored late)
+    uint32_t grew1 = 0, far1 = 0, ent1 = 0;
+    uint32_t grew2 = 0, far2 = 0, ent2a = 0, ent2b = 0;
+};
+
+// First step of cell u (ring slot K) for every halo-range column of this thread, written
+// to the same slot of R1 (with the mirror row of slots 0 and 7). Words outside [0, vmax1]
+// are set to zero: those cells hold no mass after the first step.
+template <int K>
+__device__ __forceinline__ void first_cell(const DevShape& sh, const Prod& p, const float4* ct, int u, int vmax1,
+                                           int front, float* __restrict__ far1, Step2State& ss) {
+    constexpr int k = K & 3, par = K >> 2;
+#pragma unroll
+    for (int j = 0; j < kLoadCols; ++j) {
+        if (j >= p.n) break;
+        const uint32_t cd = (ss.cq1[par][j] >> (8 * k)) & 0xffu;
+        const uint32_t own = p.me[j][(K + 1) * kBlkCols];
+        const uint32_t dn = p.me[j][K * kBlkCols];
+        const uint32_t up = p.me[j][(K + 2) * kBlkCols];
+        uint32_t n[kSide];
+#pragma unroll
+        for (int i = 0; i < kSide; ++i) n[i] = p.nb[j][i][K * kBlkCols];
+        uint32_t v = tube_update(n, dn, up, own, sh.ends, ct[cd]);
+        v = (u >= 0 && u <= vmax1) ? v : 0u;
+        if ((K & 3) == 0) {
+            ss.first0[j] = v;  // its R1 row may still be read before the next barrier
+        } else if (p.ok[j]) {
+            p.out[j][(K + 1) * kBlkCols] = v;
+            if (K == kRingCells - 1) p.out[j][0] = v;
+        }
+        ss.grew1 |= own == 0u ? v : 0u;
+        ss.ent1 |= u == front + 1 ? v : 0u;
+        if (u == p.top[j]) {
+            ss.far1 |= v;
+            if (far1 && p.ok[j]) far1[p.c[j]] = __uint_as_float(v);
+        }
+    }
+}
+
+// The first-step words of the first cell of a group (ring slot K), with the mirror row.
+template <int K>
+__device__ __forceinline__ void store_first0(const Prod& p, const Step2State& ss) {
+#pragma unroll
+    for (int j = 0; j < kLoadCols; ++j) {
+        if (j >= p.n) break;
+        if (!p.ok[j]) continue;
+        p.out[j][(K + 1) * kBlkCols] = ss.first0[j];
+        if (K == 0) p.out[j][(kRingCells + 1) * kBlkCols] = ss.first0[j];
+    }
+}
+
+// Second step of cell u (ring slot K of R1) for this thread's tile column; at the last
+// cell of the group its quad goes to HBM.
+template <int K>
+__device__ __forceinline__ void second_cell(const DevShape& sh, const Own& w, const float4* ct, int u, int front,
+                                            int top_min, float* __restrict__ yout, Step2State& ss) {
+    constexpr int k = K & 3, par = K >> 2;
+    const uint32_t cd = (ss.cq2[par] >> (8 * k)) & 0xffu;
+    const uint32_t own = w.me[(K + 1) * kBlkCols];
+    const uint32_t dn = w.me[K * kBlkCols];
+    const uint32_t up = w.me[(K + 2) * kBlkCols];
+    uint32_t n[kSide];
+#pragma unroll
+    for (int i = 0; i < kSide; ++i) n[i] = w.nb[i][K * kBlkCols];
+    ss.r2[k] = tube_update(n, dn, up, own, sh.ends, ct[cd]);
+    ss.grew2 |= own == 0u ? ss.r2[k] : 0u;
+    if (k == 3) {
+        const int u4 = u - 3;
+        reinterpret_cast<uint4*>(yout)[quad_of(sh, u4 >> 2, w.c)] = make_uint4(ss.r2[0], ss.r2[1], ss.r2[2], ss.r2[3]);
+        if (u4 + 3 >= top_min) {
+            const int kt = w.top - u4;
+            ss.far2 |= kt == 0 ? ss.r2[0] : kt == 1 ? ss.r2[1] : kt == 2 ? ss.r2[2] : kt == 3 ? ss.r2[3] : 0u;
+        }
+        const int ka = front + 1 - u4, kb = front + 2 - u4;
+        if (ka >= 0 && ka < 4) ss.ent2a |= ka == 0 ? ss.r2[0] : ka == 1 ? ss.r2[1] : ka == 2 ? ss.r2[2] : ss.r2[3];
+        if (kb >= 0 && kb < 4) ss.ent2b |= kb == 0 ? ss.r2[0] : kb == 1 ? ss.r2[1] : kb == 2 ? ss.r2[2] : ss.r2[3];
+    }
+}
+
+struct Walk2 {
+    const Stage* st;
+    const Prod* p;
+    const Own* w;
+    const float4* ct;
+    const float* yin;
+    float* yout;
+    const uint32_t* code4;
+    float* far1;
+    int front, vmax0, vmax1, top_min, last_q;
+};
+
+__device__ __forceinline__ int clamp_q(int g, int last_q) { return min(max(g, 0), last_q); }
+
+// Group G of the first step (R0 slots 4P..4P+3, written to the same slots of R1) and,
+// if `second`, group G-1 of the second step (R1 slots of the other parity). Three
+// barriers: before the outer group G+1 replaces G-1 in R0 and before any first-step word
+// of G replaces G-2 in R1 (second-step cells of G-2 may still read it until then: the
+// words of the first cell are held back to after it); before the last first-step cell,
+// which reads G+1 in R0 and replaces the last cell of G-2 in R1 (or its mirror), the
+// only R1 word of G-2 the first second-step cell reads; before the second-step cells
+// that read group G. The first three first-step cells write rows that no second-step
+// cell between the first two barriers reads.
+template <int P>
+__device__ __forceinline__ void half2(const DevShape& sh, const Walk2& k2, int G, bool second, Step2State& ss) {
+    constexpr int K0 = 4 * P, Q0 = 4 * (P ^ 1);
+    const int u = 4 * G;
+    first_cell<K0>(sh, *k2.p, k2.ct, u, k2.vmax1, k2.front, k2.far1, ss);
+    __syncthreads();
+    store_first0<K0>(*k2.p, ss);
+    put_quads<Q0>(*k2.st, G + 1, k2.vmax0, ss.next);
+    load_quads(sh, *k2.st, k2.yin, G + 2, k2.vmax0, ss.next);
+#pragma unroll
+    for (int j = 0; j < kLoadCols; ++j) {
+        if (j >= k2.p->n) break;
+        ss.cq1[P ^ 1][j] = k2.code4[quad_of(sh, clamp_q(G + 1, k2.last_q), k2.p->c[j])];
+    }
+    ss.cq2[P] = k2.code4[quad_of(sh, clamp_q(G, k2.last_q), k2.w->c)];
+    first_cell<K0 + 1>(sh, *k2.p, k2.ct, u + 1, k2.vmax1, k2.front, k2.far1, ss);
+    first_cell<K0 + 2>(sh, *k2.p, k2.ct, u + 2, k2.vmax1, k2.front, k2.far1, ss);
+    if (second) second_cell<Q0>(sh, *k2.w, k2.ct, u - 4, k2.front, k2.top_min, k2.yout, ss);
+    __syncthreads();
+    first_cell<K0 + 3>(sh, *k2.p, k2.ct, u + 3, k2.vmax1, k2.front, k2.far1, ss);
+    __syncthreads();
+    if (second) {
+        second_cell<Q0 + 1>(sh, *k2.w, k2.ct, u - 3, k2.front, k2.top_min, k2.yout, ss);
+        second_cell<Q0 + 2>(sh, *k2.w, k2.ct, u - 2, k2.front, k2.top_min, k2.yout, ss);
+        second_cell<Q0 + 3>(sh, *k2.w, k2.ct, u - 1, k2.front, k2.top_min, k2.yout, ss);
+    }
+}
+
+// Two steps of the tile's tubes in cells [ub, ue) (cut at min(U, front+3); ub a multiple
+// of 8): reads yin, writes the second step's words to yout and the first step's words of
+// the far-end tubes to far1 (indexed by column; nullable). Returns the first step's flags
+// and stores the second step's in *fl2.
+__device__ __forceinline__ uint32_t walk_step2(const DevShape& sh, int k, const TileV& tv, const float4* ct,
+                                               const float* __restrict__ yin, float* __restrict__ yout,
+                                               const uint8_t* __restrict__ code, float* __restrict__ far1, int ub,
+                                               int ue, int front, int r1_off, uint32_t* fl2) {
+    ue = min(ue, min(sh.U, front + 3));
+    *fl2 = 0u;
+    if (ub >= ue) return 0u;
+    uint32_t* r0 = reinterpret_cast<uint32_t*>(lds);
+    uint32_t* r1 = r0 + r1_off;
+    const int os = uniform_i32(sh.tile2 + 2 * k), oe = uniform_i32(sh.tile2 + 2 * k + 1);
+    const Stage st = stage_range(os, oe, r0);
+    const Prod p = prod_columns(sh, k, tv, os, r0, r1);
+    const Own w = own_column_in(sh, tv, r1);
+    Walk2 k2;
+    k2.st = &st;
+    k2.p = &p;
+    k2.w = &w;
+    k2.ct = ct;
+    k2.yin = yin;
+    k2.yout = yout;
+    k2.code4 = reinterpret_cast<const uint32_t*>(code);
+    k2.far1 = far1;
+    k2.front = front;
+    k2.vmax0 = min(front, sh.U - 1);
+    k2.vmax1 = min(front + 1, sh.U - 1);
+    k2.top_min = (sh.L - 3) / 3;
+    k2.last_q = (sh.U + 3) / 4 - 1;
+    const int g0 = ub >> 2, gl = (ue - 1) >> 2;
+    __syncthreads();  // the rings may still be read by a previous item
+    if (threadIdx.x < (unsigned)kRows) {
+        r0[ring_word((int)threadIdx.x, 0)] = 0u;
+        r1[ring_word((int)threadIdx.x, 0)] = 0u;
+    }
+    Step2State ss;
+    uint4 q[kLoadCols];
+    load_quads(sh, st, yin, g0 - 2, k2.vmax0, q);
+    put_quads<0>(st, g0 - 2, k2.vmax0, q);
+    load_quads(sh, st, yin, g0 - 1, k2.vmax0, q);
+    put_quads<4>(st, g0 - 1, k2.vmax0, q);
+    load_quads(sh, st, yin, g0, k2.vmax0, ss.next);
+#pragma unroll
+    for (int j = 0; j < kLoadCols; ++j) {
+        if (j >= p.n) break;
+        ss.cq1[1][j] = k2.code4[quad_of(sh, clamp_q(g0 - 1, k2.last_q), p.c[j])];
+    }
+    __syncthreads();
+    half2<1>(sh, k2, g0 - 1, false, ss);
+    half2<0>(sh, k2, g0, false, ss);
+    for (int G = g0 + 1; G <= gl + 1; G += 2) {
+        half2<1>(sh, k2, G, true, ss);
+        if (G + 1 > gl + 1) break;
+        half2<0>(sh, k2, G + 1, true, ss);
+    }
+    *fl2 = (ss.grew2 ? F_GREW : 0u) | (ss.far2 ? F_FAR : 0u) | (ss.ent2a ? F_FRONT : 0u) | (ss.ent2b ? F_FRONT2 : 0u);
+    return (ss.grew1 ? F_GREW : 0u) | (ss.far1 ? F_FAR : 0u) | (ss.ent1 ? F_FRONT : 0u);
 }
 
 // ------------------------------------------------------------------------------
@@ -548,6 +817,35 @@ __device__ __forceinline__ void far_sum(const DevShape& sh, const float* __restr
     __syncthreads();
 }
 
+// far_sum over words given per column (the far-end word of column c at w[c]), in the same
+// order as far_sum, so the result has the same bits as far_sum over a state holding them.
+__device__ __forceinline__ void far_sum_cols(const DevShape& sh, const float* __restrict__ wc, int front, float* part,
+                                             uint32_t* reached, float* result) {
+    __syncthreads();
+    if (threadIdx.x == 0) *reached = 0;
+    __syncthreads();
+    for (int v = threadIdx.x; v < 256; v += blockDim.x) {
+        float s = 0.0f;
+        uint32_t r = 0;
+        for (int c = v; c < sh.C; c += 256) {
+            const int u = top_of(sh, c);
+            if (u < 0 || u > front) continue;
+            const uint32_t w = __float_as_uint(wc[c]);
+            s += mag(w);
+            r |= w != 0u ? 1u : 0u;
+        }
+        part[v] = s;
+        if (r) atomicOr(reached, 1u);
+    }
+    __syncthreads();
+    for (int width = 128; width >= 1; width >>= 1) {
+        for (int v = threadIdx.x; v < width; v += blockDim.x) part[v] = part[v] + part[v + width];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *result = part[0];
+    __syncthreads();
+}
+
 // Items [0, total) of a launch (tile index fastest): the workgroups of one XCD share one
 // contiguous range and deal it round-robin, so the workgroups that run side by side on
 // an XCD walk the neighbouring tiles of one cell range at the same time and read each
@@ -603,6 +901,8 @@ __device__ __forceinline__ void flags_to(uint32_t* dst, uint32_t fl) {
     if (__ballot(fl & F_FAR)) w |= F_FAR;
     if (__ballot(fl & F_NONEMPTY)) w |= F_NONEMPTY;
     if (__ballot(fl & F_STEPPED)) w |= F_STEPPED;
+    if (__ballot(fl & F_FUSED)) w |= F_FUSED;
+    if (__ballot(fl & F_FRONT2)) w |= F_FRONT2;
     if (w && (threadIdx.x & 63) == 0) atomicOr(dst, w);
 }
 
@@ -750,7 +1050,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_layout(SpanArgs a) {
         const int b = init_slot(a, i);
         const DevShape& sh = a.shapes[a.slot_shape[b]];
         mine += items_of(sh, sh.U, a.depth);
-        a.st[b] = CfgState{0, -1, 0, 0u};  // m = -1: initialised, not yet decided
+        a.st[b] = CfgState{0, -1, 0, 0u, 0u, 0};  // m = -1: initialised, not yet decided
     }
     sums[tid] = mine;
     __syncthreads();
@@ -816,8 +1116,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         const int b = first ? i : a.active[i];
         const DevShape& sh = a.shapes[a.slot_shape[b]];
         CfgState s = a.st[b];
-        const uint32_t f = s.flags;
+        const uint32_t f = s.flags, f2 = s.flags2;
         s.flags = 0;
+        s.flags2 = 0;
         int dec = -1;  // -1 continue, 0 no, 1 yes
         int32_t steps = 0;
         if (s.m < 0) {
@@ -825,10 +1126,20 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
             if (!(f & F_NONEMPTY)) { dec = 0; steps = 0; }
             else if (f & F_FAR) { dec = 1; steps = 1; }
         } else if (f & F_STEPPED) {
+            s.par ^= 1;  // every step launch writes the other buffer
             s.m += 1;
             if (f & F_FRONT) s.front += 1;
-            if (f & F_FAR) { dec = 1; steps = s.m + 1; }
+            if (f & F_FAR) { dec = 1; steps = s.m + 1; if (f & F_FUSED) s.done = 3; }
             else if (!(f & F_GREW)) { dec = 0; steps = s.m; }
+            else if (f & F_FUSED) {
+                // the second step of a two-step launch, decided as a step of its own; its
+                // front flags are relative to the front before the first step
+                s.m += 1;
+                if ((f & F_FRONT) ? (f2 & F_FRONT2) : (f2 & F_FRONT)) s.front += 1;
+                if (f2 & F_FAR) { dec = 1; steps = s.m + 1; }
+                else if (!(f2 & F_GREW)) { dec = 0; steps = s.m; }
+                else if (s.m > sh.N) { dec = 0; steps = s.m; s.done = 2; a.hdr[2] = 1; }
+            }
             else if (s.m > sh.N) { dec = 0; steps = s.m; s.done = 2; a.hdr[2] = 1; }
         }
         if (dec >= 0) {
@@ -838,7 +1149,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
             if (a.fin) a.fin[atomicAdd(a.hdr + 3, 1)] = b;
         } else {
             keep += 1;
-            chunks += items_of(sh, min(sh.U, s.front + 2), E);
+            chunks += items_of(sh, min(sh.U, s.front + (a.fused ? 3 : 2)), E);
         }
         a.st[b] = s;
     }
@@ -867,8 +1178,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         a.active2[kpos] = b;
         a.chunk_off[kpos] = cpos;
         kpos += 1;
-        cpos += items_of(sh, min(sh.U, s.front + 2), E);
-        tubes += (unsigned long long)min(sh.U, s.front + 2) * (unsigned long long)sh.C;
+        cpos += items_of(sh, min(sh.U, s.front + (a.fused ? 3 : 2)), E);
+        // tube slots advanced by one step each; a two-step launch counts its window twice
+        tubes += (unsigned long long)min(sh.U, s.front + 2) * (unsigned long long)sh.C * (a.fused ? 2ull : 1ull);
     }
     if (a.work && tubes) atomicAdd(a.work, tubes);
     __syncthreads();
@@ -903,11 +1215,44 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
         const int r = local / sh.ntile, k = local - r * sh.ntile;
         const CfgState s = uniform_load(a.st + b);
         const int64_t off = uniform_i64(a.slot_off + b);
-        const float* yin = ((s.m & 1) ? a.yb : a.ya) + off;
-        float* yout = ((s.m & 1) ? a.ya : a.yb) + off;
+        const float* yin = (s.par ? a.yb : a.ya) + off;
+        float* yout = (s.par ? a.ya : a.yb) + off;
         const uint32_t fl = walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, a.code + off, r * E, r * E + E,
                                       s.front);
         flags_to(&a.st[b].flags, fl | (threadIdx.x < 64 ? F_STEPPED : 0u));
+    }
+}
+
+// Two steps over the work list (two-step form): items (active slot, cell range, tile).
+__global__ void __launch_bounds__(kMaxBlock) k_span_step2(SpanArgs a) {
+    const Tail tl = lds_tail(a.lds);
+    fill_codes(tl.ct);
+    const int n_act = uniform_i32(a.hdr);
+    const int E = a.depth;
+    const ItemRange it = my_items(uniform_i32(a.hdr + 1));
+    if (it.begin >= it.end) return;
+    int lo = find_entry(a.chunk_off, n_act, it.begin);
+    int64_t lo_begin = uniform_i64(a.chunk_off + lo);
+    int64_t lo_end = uniform_i64(a.chunk_off + lo + 1);
+    for (int64_t g = it.begin; g < it.end; g += it.stride) {
+        if (g >= lo_end) {
+            lo = advance_entry(a.chunk_off, n_act, lo, g);
+            lo_begin = uniform_i64(a.chunk_off + lo);
+            lo_end = uniform_i64(a.chunk_off + lo + 1);
+        }
+        const int b = uniform_i32(a.active + lo);
+        const DevShape sh = uniform_load(a.shapes + uniform_i32(a.slot_shape + b));
+        const int local = (int)(g - lo_begin);
+        const int r = local / sh.ntile, k = local - r * sh.ntile;
+        const CfgState s = uniform_load(a.st + b);
+        const int64_t off = uniform_i64(a.slot_off + b);
+        const float* yin = (s.par ? a.yb : a.ya) + off;
+        float* yout = (s.par ? a.ya : a.yb) + off;
+        uint32_t fl2 = 0;
+        const uint32_t fl = walk_step2(sh, k, load_tile(sh, k), tl.ct, yin, yout, a.code + off,
+                                       a.far1 + (int64_t)b * a.far1_stride, r * E, r * E + E, s.front, a.r1_off, &fl2);
+        flags_to(&a.st[b].flags, fl | (threadIdx.x < 64 ? (F_STEPPED | F_FUSED) : 0u));
+        flags_to(&a.st[b].flags2, fl2);
     }
 }
 
@@ -942,9 +1287,11 @@ __global__ void __launch_bounds__(256) k_span_finish(SpanArgs a) {
             continue;
         }
         const DevShape sh = a.shapes[a.slot_shape[b]];
-        const int m = a.out.steps[b] - 1;  // state after m steps sits in ya if m even
-        const float* y = ((m & 1) ? a.yb : a.ya) + a.slot_off[b];
-        far_sum(sh, y, a.st[b].front, part, &reached, &result);
+        const CfgState st = a.st[b];
+        if (st.done == 3)  // after the first step of a two-step launch: its far-end words
+            far_sum_cols(sh, a.far1 + (int64_t)b * a.far1_stride, st.front, part, &reached, &result);
+        else  // the state after steps - 1 steps, the newest one
+            far_sum(sh, (st.par ? a.yb : a.ya) + a.slot_off[b], st.front, part, &reached, &result);
         if (threadIdx.x == 0) a.out.hit[b] = result;
         __syncthreads();
     }
@@ -1153,6 +1500,7 @@ hipError_t prepare_kernels(int device) {
     if (cur != device) return hipErrorInvalidDevice;
     e = allow_lds(k_span_init);
     if (e == hipSuccess) e = allow_lds(k_span_step);
+    if (e == hipSuccess) e = allow_lds(k_span_step2);
     if (e == hipSuccess) e = allow_lds(k_chunk_step);
     if (e == hipSuccess) e = allow_lds(k_persist);
     return e;
@@ -1216,6 +1564,7 @@ hipError_t launch_span_init(const SpanArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_span_step(const SpanArgs& a, hipStream_t s) {
+    if (a.fused) return launch_span_step2(a, s);
     hipLaunchKernelGGL(k_span_step, dim3(a.grid), dim3(a.block), a.lds, s, a);
     return hipGetLastError();
 }
@@ -1230,6 +1579,11 @@ hipError_t launch_span_finish(const SpanArgs& a, hipStream_t s) {
     const int grid = std::min(a.fin ? std::max(a.n_slot, 1) : a.n_slot, 4096);
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_span_finish, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_span_step2(const SpanArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_span_step2, dim3(a.grid), dim3(a.block), a.lds, s, a);
     return hipGetLastError();
 }
 

@@ -100,6 +100,35 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
                 d.contact[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col - hs + 1) : 0u;
             }
     }
+    // outer ranges: every column a halo-range column contacts
+    d.tile2.assign((size_t)nt * 2, 0);
+    d.span2_max = 0;
+    for (int k = 0; k < nt; ++k) {
+        const int hs = d.tile[k * 4 + 2], he = d.tile[k * 4 + 3];
+        int os = hs, oe = he;
+        for (int c = hs; c < he; ++c)
+            for (int i = 0; i < kSide; ++i) {
+                const int col = d.nb[(size_t)i * C + c] >> 2;
+                if (col < C) { os = std::min(os, col); oe = std::max(oe, col + 1); }
+            }
+        d.tile2[(size_t)k * 2 + 0] = os;
+        d.tile2[(size_t)k * 2 + 1] = oe;
+        d.span2_max = std::max(d.span2_max, oe - os);
+    }
+    if (d.span_max <= kMaxSpan2 && d.span2_max <= kMaxSpan2) {
+        const size_t sm = (size_t)d.span_max;
+        d.contact2.assign((size_t)nt * kSide * sm, 0u);
+        for (int k = 0; k < nt; ++k) {
+            const int hs = d.tile[k * 4 + 2], he = d.tile[k * 4 + 3], os = d.tile2[k * 2];
+            for (int c = hs; c < he; ++c)
+                for (int i = 0; i < kSide; ++i) {
+                    const int32_t v = d.nb[(size_t)i * C + c];
+                    const int32_t col = v >> 2, dcp1 = v & 3;
+                    d.contact2[((size_t)k * kSide + i) * sm + (size_t)(c - hs)] =
+                        col < C ? (uint32_t)ring_word(dcp1, col - os + 1) : 0u;
+                }
+        }
+    }
     return cs;
 }
 

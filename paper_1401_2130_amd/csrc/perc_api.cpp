@@ -92,6 +92,10 @@ int column_device(const ColumnSet& cs, int dev, ColumnDevice& out) {
     PERC_TRY(upload(&n.tile, cs.tile));
     PERC_TRY(upload(&n.rank, cs.rank));
     PERC_TRY(upload(&n.sig, cs.sig));
+    if (!cs.contact2.empty()) {
+        PERC_TRY(upload(&n.nboff2, cs.contact2));
+        PERC_TRY(upload(&n.tile2, cs.tile2));
+    }
     g_coldev.emplace(std::make_pair(dev, cs.W), n);
     out = n;
     return PERC_OK;
@@ -107,9 +111,12 @@ int shape_of(const LatticeDesc& d, DevShape& sh) {
     sh.tile = cd.tile;
     sh.rank = cd.rank;
     sh.sig = cd.sig;
+    sh.nboff2 = cd.nboff2;
+    sh.tile2 = cd.tile2;
     sh.C = d.C; sh.CP = d.CP; sh.U = d.U; sh.L = d.L;
     sh.ntile = d.ntile; sh.span_max = d.span_max; sh.tile_max = d.tile_max; sh.W = d.W;
-    sh.ends = d.ends; sh.pad0 = 0;
+    sh.ends = d.ends;
+    sh.span2_max = d.cs->span2_max;
     sh.N = d.N; sh.words = d.words;
     return PERC_OK;
 }
@@ -243,7 +250,10 @@ int32_t size_bucket(int64_t n) {
 
 struct ShapeNeed {
     int32_t span_max = 0, tile_max = 0, C = 0;
-    int64_t items = 0;  // column tiles x cells of the largest shape
+    int64_t items = 0;   // column tiles x cells of the largest shape
+    int32_t span2_max = 0;
+    bool two_step = true;  // every shape has the two-step contact table
+    int32_t CP = 0;
 };
 
 // Threads per workgroup for these shapes: one per column of the widest tile, and the
@@ -270,6 +280,21 @@ int check_walk(const ShapeNeed& nd, int32_t block) {
     return PERC_OK;
 }
 
+// The two-step form also stages the outer range (two columns per thread at most) and
+// holds two rings in LDS.
+bool two_step_fits(const ShapeNeed& nd, int32_t block) {
+    return nd.two_step && block >= nd.tile_max && nd.span_max <= 2 * block && nd.span2_max <= 2 * block &&
+           lds_total2(nd.span_max, nd.span2_max) <= kMaxLds;
+}
+
+int check_walk2(const ShapeNeed& nd, int32_t block) {
+    PERC_TRY(check_walk(nd, block));
+    if (!two_step_fits(nd, block))
+        return fail(PERC_EINVAL, "the two-step form needs the outer range (" + std::to_string(nd.span2_max) +
+                                     " columns) within two columns per thread and both rings in LDS");
+    return PERC_OK;
+}
+
 int resolve(const ShapeNeed& nd, int64_t state_words, int64_t n_jobs, const perc_options* opt, Tuning& tu,
             const TuneKey* key) {
     tu = Tuning{};
@@ -280,7 +305,7 @@ int resolve(const ShapeNeed& nd, int64_t state_words, int64_t n_jobs, const perc
         tu.grid = opt->grid;
         tu.graph_steps = opt->graph_steps;
     }
-    if (tu.form < FORM_AUTO || tu.form > FORM_PERSIST) return fail(PERC_EINVAL, "unknown execution form");
+    if (tu.form < FORM_AUTO || tu.form > FORM_SPAN2) return fail(PERC_EINVAL, "unknown execution form");
     if (tu.form == FORM_AUTO && key) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune.find(*key);
@@ -302,7 +327,7 @@ int resolve(const ShapeNeed& nd, int64_t state_words, int64_t n_jobs, const perc
     if (tu.block == 0) tu.block = block_for(nd);
     if (tu.block < 64 || tu.block > 1024 || tu.block % 64)
         return fail(PERC_EINVAL, "block must be 64..1024, a multiple of 64");
-    PERC_TRY(check_walk(nd, tu.block));
+    PERC_TRY(tu.form == FORM_SPAN2 ? check_walk2(nd, tu.block) : check_walk(nd, tu.block));
     if (tu.graph_steps == 0) tu.graph_steps = 8;
     if (tu.graph_steps < 1 || tu.graph_steps > 256) return fail(PERC_EINVAL, "graph_steps must be 1..256");
     if (tu.grid < 0) return fail(PERC_EINVAL, "grid must be >= 0");
@@ -349,6 +374,9 @@ void collect_shapes(const std::vector<HostJob>& jobs, Shapes& S) {
         S.need.tile_max = std::max(S.need.tile_max, d.tile_max);
         S.need.C = std::max(S.need.C, d.C);
         S.need.items = std::max<int64_t>(S.need.items, (int64_t)d.U * d.ntile);
+        S.need.span2_max = std::max(S.need.span2_max, d.cs->span2_max);
+        S.need.two_step = S.need.two_step && !d.cs->contact2.empty();
+        S.need.CP = std::max(S.need.CP, d.CP);
         S.max_state = std::max<int64_t>(S.max_state, state_words(d));
         S.max_words = std::max<int64_t>(S.max_words, d.words);
     }
@@ -376,12 +404,13 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
     if (n == 0) return PERC_OK;
     if (stream_capturing(s)) return fail(PERC_EINVAL, "the span and plain forms synchronise; not capturable");
     const bool plain = tu.form == FORM_PLAIN;
+    const bool fused = tu.form == FORM_SPAN2;
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     const int64_t budget = std::min<int64_t>((int64_t)(free_b / 2), 48ll << 30);
     if (!g_pinned.h) return fail(PERC_ENOMEM, "pinned host buffer");
     int32_t* h = g_pinned.h;
-    const int lds = (int)lds_total(S.need.span_max);
+    const int lds = (int)(fused ? lds_total2(S.need.span_max, S.need.span2_max) : lds_total(S.need.span_max));
     Arena shape_ar;
     PERC_TRY(shape_ar.reserve(sizeof(DevShape) * S.dev.size(), s));
     DevShape* d_shapes = shape_ar.take<DevShape>(S.dev.size());
@@ -396,7 +425,7 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
             const LatticeDesc& d = jobs[w1].lat->d;
             const int64_t sw = slot_words(d);
             const int64_t bw = jobs[w1].bits ? 0 : bits_words(d);
-            const int64_t bytes = (words + sw) * 9 + (bitw + bw) * 4 + (w1 - w0 + 1) * 96;
+            const int64_t bytes = (words + sw) * 9 + (bitw + bw) * 4 + (w1 - w0 + 1) * (96 + 4 * S.need.CP);
             if (w1 > w0 && (bytes > budget || plain || w1 - w0 >= (1 << 20))) break;
             words += sw;
             bitw += bw;
@@ -424,7 +453,8 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
         const size_t bytes = Arena::align(sizeof(float) * off) * 2 + Arena::align((size_t)off) +
                              Arena::align(sizeof(uint32_t) * boff) + Arena::align(sizeof(CfgState) * nb) +
                              Arena::align(sizeof(int32_t) * nb) * 4 + Arena::align(sizeof(int64_t) * (nb + 1)) * 2 +
-                             Arena::align(sizeof(void*) * nb) + Arena::align(sizeof(Job) * nb) + Arena::align(64);
+                             Arena::align(sizeof(void*) * nb) + Arena::align(sizeof(Job) * nb) + Arena::align(64) +
+                             (fused ? Arena::align(sizeof(float) * (size_t)nb * S.need.CP) : 0);
         PERC_TRY(ar.reserve(bytes, s));
         SpanArgs a{};
         a.shapes = d_shapes;
@@ -442,6 +472,12 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
         uint32_t** d_bits = ar.take<uint32_t*>(nb);
         Job* d_jobs = ar.take<Job>(nb);
         a.hdr = ar.take<int32_t>(16);
+        if (fused) {
+            a.fused = 1;
+            a.far1_stride = S.need.CP;
+            a.far1 = ar.take<float>((size_t)nb * S.need.CP);
+            a.r1_off = (int32_t)lds_ring2_words(S.need.span2_max);
+        }
         std::vector<const uint32_t*> h_bits(nb);
         for (int32_t b = 0; b < nb; ++b) h_bits[b] = h_jobs[b].bits ? h_jobs[b].bits : scratch_bits + h_boff[b];
         HIP_TRY(hipMemcpyAsync(d_shape, h_shape.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
@@ -690,6 +726,8 @@ int autotune(const std::vector<HostJob>& hj, int64_t n_target, perc_options* bes
         if (b0 + 64 <= 1024) cands.push_back(perc_options{FORM_SPAN, depth, b0 + 64, 0, 16});
         cands.push_back(perc_options{FORM_PERSIST, depth, b0, 0, 0});
     }
+    if (two_step_fits(S.need, b0))
+        for (int32_t depth : {64, 128}) cands.push_back(perc_options{FORM_SPAN2, depth, b0, 0, 16});
     const int64_t n = (int64_t)hj.size();
     Arena ar;
     PERC_TRY(ar.reserve(Arena::align((size_t)n) + Arena::align(4 * (size_t)n), s));

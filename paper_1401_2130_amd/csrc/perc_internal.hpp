@@ -62,7 +62,16 @@ struct ColumnSet {
     int32_t span_max = 0;            // widest halo range
     int32_t tile_max = 0;            // widest tile
     std::vector<uint32_t> contact;   // contact table (layout below)
+    // Two steps per pass: the first step is computed on the whole halo range [hs, he) of
+    // a tile, which reads the outer range [hs2, he2) (the halo of the halo range).
+    std::vector<int32_t> tile2;      // [ntile][2]: outer first, outer end
+    int32_t span2_max = 0;           // widest outer range
+    // [ntile][kSide][span_max]: LDS word (ring of the outer range) of side contact i of
+    // halo-range column lc of tile k, as in `contact`; empty when span_max or span2_max
+    // exceeds kMaxSpan2 (the two-step form is not offered for such widths)
+    std::vector<uint32_t> contact2;
 };
+constexpr int32_t kMaxSpan2 = 2048;
 
 // The column set of hex radius W, built on first use and kept for the process (one per
 // distinct W; thread safe). Null with a message for a bad W.
@@ -122,9 +131,12 @@ struct DevShape {
     const int32_t* tile;    // [ntile][4]
     const int32_t* rank;    // [C]
     const int32_t* sig;     // [C]
+    const uint32_t* nboff2; // [ntile][kSide][span_max] two-step contact table (null: none)
+    const int32_t* tile2;   // [ntile][2] outer ranges (null: none)
     int32_t C, CP, U, L;
     int32_t ntile, span_max, tile_max, W;
-    int32_t ends, pad0;  // ends: 1 with end contacts (modified lattice), 0 regular FCC
+    int32_t ends;           // 1 with end contacts (modified lattice), 0 regular FCC
+    int32_t span2_max;      // widest outer range (two-step form)
     int64_t N, words;
 };
 
@@ -134,6 +146,8 @@ struct ColumnDevice {
     int32_t* tile = nullptr;
     int32_t* rank = nullptr;
     int32_t* sig = nullptr;
+    uint32_t* nboff2 = nullptr;
+    int32_t* tile2 = nullptr;
 };
 
 // Dynamic LDS of the walking kernels: the ring from address 0, 1 + span columns (pad
@@ -145,6 +159,14 @@ PERC_HD inline uint32_t lds_total(int32_t span) {
     const uint32_t blocks = (uint32_t)(span + 1 + kBlkCols - 1) / kBlkCols;
     return blocks * kBlkWords * 4u + kLdsTail;
 }
+// Two steps per pass: the outer ring (outer range) from address 0, the inner ring (halo
+// range) from word lds_ring2_words(span2), then the tail.
+PERC_HD inline uint32_t lds_ring2_words(int32_t span2) {
+    return (uint32_t)((span2 + 1 + kBlkCols - 1) / kBlkCols) * kBlkWords;
+}
+PERC_HD inline uint32_t lds_total2(int32_t span, int32_t span2) {
+    return lds_ring2_words(span2) * 4u + lds_total(span);
+}
 
 // ---------------------------------------------------------------------------------
 // Execution forms and tuning knobs.
@@ -155,6 +177,7 @@ enum Form : int32_t {
     FORM_SPAN = 2,     // many configurations, each spread over many workgroups, one
                        // launch per step over a device-built work list, graph-replayed
     FORM_PERSIST = 3,  // one workgroup per configuration, whole inspection in one launch
+    FORM_SPAN2 = 4,    // the span form with two steps per launch (one pass over HBM)
 };
 
 struct Tuning {
@@ -167,10 +190,14 @@ struct Tuning {
 
 // Per-configuration device state of the span and plain forms.
 struct CfgState {
-    int32_t front;   // largest cell holding a reached tube
-    int32_t m;       // steps done
-    int32_t done;    // 0 = active, 1 = decided, 2 = cap reached (error)
-    uint32_t flags;  // OR of the flags of the last launch; cleared by the planner
+    int32_t front;    // largest cell holding a reached tube
+    int32_t m;        // steps done
+    int32_t done;     // 0 = active, 1 = decided, 2 = cap reached (error), 3 = decided with a
+                      // detector hit after the first step of a two-step launch (the far-end
+                      // words of that step are in SpanArgs::far1)
+    uint32_t flags;   // OR of the flags of the last launch (its first step); cleared by the planner
+    uint32_t flags2;  // second-step flags of a two-step launch; cleared by the planner
+    int32_t par;      // state buffer holding the newest state: 0 = ya, 1 = yb
 };
 
 constexpr uint32_t F_GREW = 1u;      // some tube joined the reached set
@@ -178,6 +205,8 @@ constexpr uint32_t F_FRONT = 2u;     // the reached set entered cell front+1
 constexpr uint32_t F_FAR = 4u;       // a far-end tube is reached: detector next step
 constexpr uint32_t F_NONEMPTY = 8u;  // (initialisation) some start tube is metallic
 constexpr uint32_t F_STEPPED = 16u;  // the last step launch advanced the configuration
+constexpr uint32_t F_FUSED = 32u;    // ... by two steps (flags2 holds the second step's flags)
+constexpr uint32_t F_FRONT2 = 64u;   // (second step) the reached set entered cell front+2
 
 // Outputs, device pointers indexed by slot (span) or job (persistent).
 struct BatchOut {
@@ -239,11 +268,16 @@ struct SpanArgs {
     int32_t block;
     int32_t grid;
     int32_t lds;               // dynamic LDS bytes of the walking kernels
+    int32_t fused;             // 1: each step launch does two steps (k_span_step2)
+    int32_t r1_off;            // two-step form: LDS word offset of the inner ring
+    float* far1;               // two-step form: [n_slot][far1_stride] first-step far-end words
+    int32_t far1_stride;
 };
 
 hipError_t launch_span_init(const SpanArgs& a, hipStream_t s);       // codes, y0, first plan
 hipError_t launch_span_init_only(const SpanArgs& a, hipStream_t s);  // codes and y0 only
-hipError_t launch_span_step(const SpanArgs& a, hipStream_t s);       // one step over the work list
+hipError_t launch_span_step(const SpanArgs& a, hipStream_t s);       // one step (two if a.fused) over the work list
+hipError_t launch_span_step2(const SpanArgs& a, hipStream_t s);      // two steps over the work list
 hipError_t launch_span_plan(const SpanArgs& a, hipStream_t s);       // decide, compact, plan
 hipError_t launch_span_finish(const SpanArgs& a, hipStream_t s);     // first-hit probabilities, counts
 

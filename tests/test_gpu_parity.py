@@ -47,7 +47,8 @@ def check_hit(hit_gpu, hit_ref, perc_ref, steps_ref):
 
 
 # (form, cells per work item); the library rounds up to a multiple of 16
-FORMS = [("plain", 8), ("span", 8), ("span", 5), ("span", 24), ("persist", 8), ("persist", 16), ("persist", 64)]
+FORMS = [("plain", 8), ("span", 8), ("span", 5), ("span", 24), ("persist", 8), ("persist", 16), ("persist", 64),
+         ("span2", 8), ("span2", 24), ("span2", 64)]
 
 
 # --------------------------------------------------------------------------------
@@ -409,3 +410,27 @@ def test_fixed_count_curve_and_binomial_convolution(perc):
     want = np.array([oracle.pi_from_counts(a, p) for p in ps])
     assert np.all(miss < 1e-12)
     assert np.all(np.abs(got - want) <= 5 / math.sqrt(n))
+
+
+@pytest.mark.parametrize("p", [0.14, 0.1533, 0.17])
+def test_two_step_form_bitwise_at_full_size(perc, p):
+    """W=32, L=1024 (7 column tiles): the two-step form gives the bits, steps and FP32
+    first-hit probabilities of the one-step span form, configuration by configuration,
+    and the oracle's bits and steps on a sample."""
+    W, L = workloads.LARGE.shapes[0]
+    lat = perc.Lattice(W, L)
+    n = 48
+    occ = perc.perc_sample(lat, p, 21, n)
+    p1, s1, h1 = perc.perc_inspect_ex(lat, occ, n, hit=True, form="span", depth=64)
+    p2, s2, h2 = perc.perc_inspect_ex(lat, occ, n, hit=True, form="span2", depth=64)
+    p3, s3, h3 = perc.perc_inspect_ex(lat, occ, n, hit=True, form="span2", depth=128)
+    torch.cuda.synchronize()
+    for a, b in ((p1, p2), (s1, s2), (p1, p3), (s1, s3)):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    np.testing.assert_array_equal(h1.cpu().numpy().view(np.uint32), h2.cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(h1.cpu().numpy().view(np.uint32), h3.cpu().numpy().view(np.uint32))
+    ref = oracle.Lattice(W, L)
+    pick = [0, 17, 40]
+    pm, sm, _ = ref.inspect_markov(host_words(occ)[pick])
+    np.testing.assert_array_equal(p2.cpu().numpy()[pick], pm)
+    np.testing.assert_array_equal(s2.cpu().numpy()[pick], sm)
