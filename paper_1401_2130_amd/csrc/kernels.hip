@@ -157,12 +157,20 @@ __device__ __forceinline__ TileV load_tile(const DevShape& sh, int k) {
 // State layout in HBM: the cells of a configuration are taken in groups of four
 // (cells 4g .. 4g+3); word k of the 16-byte quad (g, c) holds cell 4g+k of column c,
 // quads in [group][CP] order, so one 16-byte load or store moves four cells of a
-// column and a wave's 64 columns are 1 KiB contiguous. The degree codes use the same
-// layout with bytes (one 32-bit word per quad).
+// column and a wave's 64 columns are 1 KiB contiguous.
 // ------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t quad_of(const DevShape& sh, int g, int c) { return (uint32_t)g * sh.CP + c; }
 __device__ __forceinline__ uint32_t word_of(const DevShape& sh, int u, int c) {
     return quad_of(sh, u >> 2, c) * 4u + (uint32_t)(u & 3);
+}
+// Degree codes: four bits per tube (0..14 the degree of a metallic tube, 15 insulating
+// or absent), eight cells 8o..8o+7 of column c in one 32-bit word, cell u in bits
+// 4 (u mod 8) .. +3, words in [octet][CP] order. The word holding group g:
+__device__ __forceinline__ uint32_t code_word_g(const DevShape& sh, int g, int c) {
+    return (uint32_t)(g >> 1) * sh.CP + c;
+}
+__device__ __forceinline__ uint32_t code_of(const uint32_t* __restrict__ code8, const DevShape& sh, int u, int c) {
+    return (code8[(uint32_t)(u >> 3) * sh.CP + c] >> (4 * (u & 7))) & 0xfu;
 }
 
 // ------------------------------------------------------------------------------
@@ -291,7 +299,7 @@ __device__ __forceinline__ uint32_t tube_update(const uint32_t (&n)[kSide], uint
 
 struct StepState {
     uint4 next[kLoadCols];  // staged quads of the group after the current one
-    uint32_t cq[2];         // code quads, by group parity
+    uint32_t cq[2];         // code words of the current and the next eight cells
     uint32_t res[4];        // new words of the current group
     uint32_t grew = 0;      // OR of the new words of tubes that were not reached before
     uint32_t far = 0, entered = 0;
@@ -309,9 +317,11 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
     if (k == 1) {
         put_quads<(par ^ 1) * 4>(st, g + 1, vmax, ss.next);
         load_quads(sh, st, yin, g + 2, vmax, ss.next);
-        ss.cq[par ^ 1] = code4[quad_of(sh, min(g + 1, (sh.U + 3) / 4 - 1), w.c)];
+        // the code word of the next eight cells, once per eight cells
+        if (K == 1) ss.cq[1] = code4[(uint32_t)min((u8 >> 3) + 1, (sh.U - 1) >> 3) * sh.CP + w.c];
     }
-    const uint32_t cd = (ss.cq[par] >> (8 * k)) & 0xffu;
+    const uint32_t cd = (ss.cq[0] >> (4 * K)) & 0xfu;
+    if (K == 7) ss.cq[0] = ss.cq[1];
     const uint32_t own = w.me[(K + 1) * kBlkCols];
     const uint32_t dn = w.me[K * kBlkCols];
     const uint32_t up = w.me[(K + 2) * kBlkCols];
@@ -361,8 +371,8 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
     load_quads(sh, st, yin, g0, vmax, q);
     put_quads<0>(st, g0, vmax, q);
     load_quads(sh, st, yin, g0 + 1, vmax, ss.next);
-    ss.cq[0] = code4[quad_of(sh, g0, w.c)];
-    ss.cq[1] = 0xffffffffu;
+    ss.cq[0] = code4[code_word_g(sh, g0, w.c)];
+    ss.cq[1] = 0xffffffffu;  // (g0 is even: the first word covers g0 and g0 + 1)
     __syncthreads();
     for (int u8 = ub; u8 < ue; u8 += kRingCells) {
         step_cell<0>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
@@ -449,8 +459,8 @@ __device__ __forceinline__ Own own_column_in(const DevShape& sh, const TileV& tv
 
 struct Step2State {
     uint4 next[kLoadCols];        // staged outer quads of the group after the current one
-    uint32_t cq1[2][kLoadCols];   // halo-range code quads, by group parity
-    uint32_t cq2[2];              // tile code quads, by group parity
+    uint32_t cq1[2][kLoadCols];   // halo-range code words, by group parity
+    uint32_t cq2[2];              // tile code words, by group parity
     uint32_t r2[4];               // second-step words of the group before
     uint32_t first0[kLoadCols];   // first-step words of the group's first cell (stored late)
     uint32_t grew1 = 0, far1 = 0, ent1 = 0;
@@ -467,7 +477,7 @@ __device__ __forceinline__ void first_cell(const DevShape& sh, const Prod& p, co
 #pragma unroll
     for (int j = 0; j < kLoadCols; ++j) {
         if (j >= p.n) break;
-        const uint32_t cd = (ss.cq1[par][j] >> (8 * k)) & 0xffu;
+        const uint32_t cd = (ss.cq1[par][j] >> (4 * K)) & 0xfu;
         const uint32_t own = p.me[j][(K + 1) * kBlkCols];
         const uint32_t dn = p.me[j][K * kBlkCols];
         const uint32_t up = p.me[j][(K + 2) * kBlkCols];
@@ -509,7 +519,7 @@ template <int K>
 __device__ __forceinline__ void second_cell(const DevShape& sh, const Own& w, const float4* ct, int u, int front,
                                             int top_min, float* __restrict__ yout, Step2State& ss) {
     constexpr int k = K & 3, par = K >> 2;
-    const uint32_t cd = (ss.cq2[par] >> (8 * k)) & 0xffu;
+    const uint32_t cd = (ss.cq2[par] >> (4 * K)) & 0xfu;
     const uint32_t own = w.me[(K + 1) * kBlkCols];
     const uint32_t dn = w.me[K * kBlkCols];
     const uint32_t up = w.me[(K + 2) * kBlkCols];
@@ -566,9 +576,9 @@ __device__ __forceinline__ void half2(const DevShape& sh, const Walk2& k2, int G
 #pragma unroll
     for (int j = 0; j < kLoadCols; ++j) {
         if (j >= k2.p->n) break;
-        ss.cq1[P ^ 1][j] = k2.code4[quad_of(sh, clamp_q(G + 1, k2.last_q), k2.p->c[j])];
+        ss.cq1[P ^ 1][j] = k2.code4[code_word_g(sh, clamp_q(G + 1, k2.last_q), k2.p->c[j])];
     }
-    ss.cq2[P] = k2.code4[quad_of(sh, clamp_q(G, k2.last_q), k2.w->c)];
+    ss.cq2[P] = k2.code4[code_word_g(sh, clamp_q(G, k2.last_q), k2.w->c)];
     first_cell<K0 + 1>(sh, *k2.p, k2.ct, u + 1, k2.vmax1, k2.front, k2.far1, ss);
     first_cell<K0 + 2>(sh, *k2.p, k2.ct, u + 2, k2.vmax1, k2.front, k2.far1, ss);
     if (second) second_cell<Q0>(sh, *k2.w, k2.ct, u - 4, k2.front, k2.top_min, k2.yout, ss);
@@ -629,7 +639,7 @@ __device__ __forceinline__ uint32_t walk_step2(const DevShape& sh, int k, const 
 #pragma unroll
     for (int j = 0; j < kLoadCols; ++j) {
         if (j >= p.n) break;
-        ss.cq1[1][j] = k2.code4[quad_of(sh, clamp_q(g0 - 1, k2.last_q), p.c[j])];
+        ss.cq1[1][j] = k2.code4[code_word_g(sh, clamp_q(g0 - 1, k2.last_q), p.c[j])];
     }
     __syncthreads();
     half2<1>(sh, k2, g0 - 1, false, ss);
@@ -689,7 +699,7 @@ __device__ __forceinline__ void put_occ_quad(const DevShape& sh, const Stage& st
 
 struct InitState {
     uint32_t next[4][kLoadCols];  // raw occupancy words of the group after the current one
-    uint32_t cq = 0;              // codes of the current group
+    uint32_t cq = 0;              // codes of the current eight cells
     float y0 = 0.0f;
     uint32_t fl = 0;
 };
@@ -712,15 +722,19 @@ __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, c
 #pragma unroll
     for (int i = 0; i < kSide; ++i) deg += w.nb[i][K * kBlkCols];
     const uint32_t cd = me ? deg : 15u;
-    is.cq |= cd << (8 * k);
+    is.cq |= cd << (4 * K);
     if (u == 0 && me) {
         is.y0 = x0 * ct[cd].x;
         is.fl |= F_NONEMPTY;
         if (u == w.top) is.fl |= F_FAR;
     }
-    if (k == 3) {
-        code4[quad_of(sh, g, w.c)] = is.cq;
+    // one code word per eight cells; a walk ending after four cells ends the fiber, whose
+    // cells beyond it are coded absent
+    if (K == 7 || (K == 3 && u8 + 4 >= ue)) {
+        code4[code_word_g(sh, g, w.c)] = K == 7 ? is.cq : (is.cq | 0xffff0000u);
         is.cq = 0;
+    }
+    if (k == 3) {
         if (g == 0)
             reinterpret_cast<uint4*>(y0)[quad_of(sh, 0, w.c)] = make_uint4(__float_as_uint(is.y0), 0u, 0u, 0u);
     }
@@ -1410,7 +1424,7 @@ __global__ void __launch_bounds__(256) k_export(DevShape sh, const float* __rest
         if (s >= sh.N) continue;
         const uint32_t g = word_of(sh, (int)u, (int)c);
         const uint32_t w = __float_as_uint(y[g]);
-        const uint32_t cd = code[g];
+        const uint32_t cd = code_of(reinterpret_cast<const uint32_t*>(code), sh, (int)u, (int)c);
         float x = 0.0f;
         if (cd < 15u) x = mag(w) * (cd == 0u ? 1.0f : (float)cd);
         x_out[s] = x;
@@ -1433,7 +1447,7 @@ __global__ void __launch_bounds__(256) k_backward_init(DevShape sh, const uint8_
         const int u = grp * 4 + (int)(i & 3);
         float v = 0.0f;
         if (c < sh.C && u < sh.U && u == top_of(sh, c)) {
-            const uint32_t cd = code[i];
+            const uint32_t cd = code_of(reinterpret_cast<const uint32_t*>(code), sh, u, c);
             if (cd > 0u && cd < 15u) v = 1.0f / (float)cd;
         }
         y[i] = v;
