@@ -149,31 +149,32 @@ def hist_summary(h) -> dict:
             "min": int(nz[0]), "max": int(nz[-1])}
 
 
-def first_passage_leg(perc, workloads, stream, M: int):
-    """Backward all-sources form of Eq. 3 on one configuration of the headline fiber:
-    M moves timed with HIP events on the launching stream (setup, backward init, M - 1
-    full-fiber steps and the export inside the timed region)."""
+def first_passage_leg(perc, workloads, stream, M: int, n_cfg: int = 64):
+    """Backward all-sources form of Eq. 3 on n_cfg configurations of the headline fiber in
+    one call: M moves timed with HIP events on the launching stream (set-up, backward
+    init, M - 1 steps over all configurations and the export inside the timed region)."""
     import torch
     wl = workloads.LARGE
     (W, L) = wl.shapes[0]
     lat = perc.Lattice(W, L)
     p = wl.ps[-1]
-    occ = perc.perc_sample(lat, p, wl.seed, 1, stream=stream)
-    f = torch.empty(lat.n, dtype=torch.float32, device="cuda")
-    perc.perc_first_passage(lat, occ, 8, f=f, stream=stream)  # warm-up
+    occ = perc.perc_sample(lat, p, wl.seed, n_cfg, stream=stream)
+    f = torch.empty((n_cfg, lat.n), dtype=torch.float32, device="cuda")
+    perc.perc_first_passage_batch(lat, occ, 8, f=f, stream=stream)  # warm-up
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    perc.perc_first_passage(lat, occ, M, f=f, stream=stream)
+    perc.perc_first_passage_batch(lat, occ, M, f=f, stream=stream)
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1)
     cols = perc.perc_lattice_columns(lat)
     cells = (L + 2) // 3
-    slot_moves = float(M) * cols * cells
-    return {"workload": f"W={W} L={L} ({lat.n} tubes), p = {p}, Philox seed {wl.seed}, configuration 0",
-            "M": M, "ms": ms, "moves_per_s": M / (ms / 1e3), "site_updates_per_s": float(M) * lat.n / (ms / 1e3),
+    slot_moves = float(M) * cols * cells * n_cfg
+    return {"workload": f"W={W} L={L} ({lat.n} tubes), p = {p}, Philox seed {wl.seed}, configurations 0..{n_cfg - 1}",
+            "M": M, "configs": n_cfg, "ms": ms, "ms_per_move": ms / M,
+            "site_updates_per_s": float(M) * lat.n * n_cfg / (ms / 1e3),
             "achieved_gbs": slot_moves * BYTES_PER_TUBE_STEP / (ms / 1e3) / 1e9,
-            "kernel": "k_chunk_step (every cell of the fiber per move)",
+            "kernel": "k_chunk_step (every cell of every configuration per move)",
             "max_f": float(f.max().item()), "nonzero": int((f > 0).sum().item())}
 
 
@@ -274,6 +275,7 @@ def main():
     ap.add_argument("--form", default="span", choices=["span", "span2", "persist", "auto"])
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0, help="workgroups per step launch (0: the library's choice)")
     ap.add_argument("--graph-steps", type=int, default=0)
     ap.add_argument("--plain-sample", type=int, default=4, help="configurations per p for the plain form")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -314,7 +316,7 @@ def main():
     stream = torch.cuda.Stream()
     bufs = [(torch.empty(n, dtype=torch.uint8, device="cuda"), torch.empty(n, dtype=torch.int32, device="cuda"),
              torch.empty(n, dtype=torch.float32, device="cuda")) for _ in wl.ps]
-    opts = dict(form=args.form, depth=args.depth, block=args.block, graph_steps=args.graph_steps)
+    opts = dict(form=args.form, depth=args.depth, block=args.block, graph_steps=args.graph_steps, grid=args.grid)
 
     def step():
         counts = []

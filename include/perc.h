@@ -216,6 +216,14 @@ int perc_state_after(const perc_lattice* lat, const uint32_t* occ_bits, int32_t 
  * pointers, PERC_ENOMEM, PERC_EHIP. */
 int perc_first_passage(const perc_lattice* lat, const uint32_t* occ_bits, int32_t M, float* f_out, void* stream);
 
+/* perc_first_passage for n_cfg configurations of one lattice at once (occ_bits: device,
+ * n_cfg x words; f_out: device, n_cfg x N floats, configuration i at i * N): every move
+ * is one launch over all of them. Results equal perc_first_passage's bit for bit. The
+ * call returns after its set-up copies; the computation is async on `stream`. Errors:
+ * as perc_first_passage, and PERC_EINVAL for n_cfg outside [0, 2^20]. */
+int perc_first_passage_batch(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, int32_t M,
+                             float* f_out, void* stream);
+
 /* Histogram of the stop step m* (Sec. III: the first step with a non-zero detector
  * probability is the length of the shortest spanning path, m* tubes) over the
  * percolating configurations of an inspection: hist[min(m*, nbins - 1)] += 1 for every

@@ -100,6 +100,7 @@ def _load():
     lib.perc_pi_ex.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), C.POINTER(perc_options), vp]
     lib.perc_state_after.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.perc_first_passage.argtypes = [vp, vp, i32, vp, vp]
+    lib.perc_first_passage_batch.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.perc_steps_hist.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.perc_batch.argtypes = [C.POINTER(perc_job), i64, vp, vp, vp, vp, i32, C.POINTER(perc_options), vp]
     lib.perc_profile_enable.argtypes = [i32]
@@ -121,7 +122,7 @@ _lib = _load()
 EXPORTED = ("perc_lattice_create", "perc_lattice_create_ex", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
             "perc_last_error", "perc_sample", "perc_sample_fixed", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
-            "perc_batch", "perc_state_after", "perc_first_passage", "perc_steps_hist", "perc_profile_enable", "perc_profile_read", "perc_autotune",
+            "perc_batch", "perc_state_after", "perc_first_passage", "perc_first_passage_batch", "perc_steps_hist", "perc_profile_enable", "perc_profile_read", "perc_autotune",
             "perc_server_create",
             "perc_server_destroy", "perc_server_submit", "perc_server_tick", "perc_server_poll",
             "perc_server_stats_read", "perc_server_run")
@@ -384,6 +385,19 @@ def perc_first_passage(lat: Lattice, occ: torch.Tensor, M: int, f=None, stream=N
     _check(_lib.perc_first_passage(lat.handle, _dptr(occ, torch.int32, lat.words), int(M),
                                    _dptr(f, torch.float32, lat.n), _stream(stream)))
     return f[: lat.n]
+
+
+def perc_first_passage_batch(lat: Lattice, occ: torch.Tensor, M: int, n_cfg: Optional[int] = None, f=None,
+                             stream=None):
+    """First-passage probabilities at move M from every tube of n_cfg configurations
+    ([n_cfg, N] float32)."""
+    if n_cfg is None:
+        n_cfg = occ.numel() // lat.words
+    if f is None:
+        f = torch.empty((n_cfg, lat.n), dtype=torch.float32, device=occ.device)
+    _check(_lib.perc_first_passage_batch(lat.handle, _dptr(occ, torch.int32, n_cfg * lat.words), int(n_cfg), int(M),
+                                         _dptr(f, torch.float32, n_cfg * lat.n), _stream(stream)))
+    return f
 
 
 def perc_steps_hist(perc: torch.Tensor, steps: torch.Tensor, nbins: int, hist=None, stream=None):

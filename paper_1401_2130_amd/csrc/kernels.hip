@@ -1270,15 +1270,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step2(SpanArgs a) {
     }
 }
 
-// One step of one configuration over all cells (test hook): workgroup g walks cell
-// range g / ntile of tile g % ntile with the same device code as the batches; every
-// cell is processed (the state buffers are zero where nothing was written).
+// One step of n_cfg configurations of one shape over all cells (state, codes of
+// configuration i at i * stride words / bytes): items (configuration, cell range, tile),
+// dealt as in the span form, each walked with the same device code as the batches;
+// every cell is processed (the state buffers are zero where nothing was written).
 __global__ void __launch_bounds__(kMaxBlock) k_chunk_step(DevShape sh, const float* yin, float* yout,
-                                                          const uint8_t* code, int E, int lds_bytes) {
+                                                          const uint8_t* code, int64_t stride, int n_cfg, int E,
+                                                          int lds_bytes) {
     const Tail tl = lds_tail(lds_bytes);
     fill_codes(tl.ct);
-    const int r = blockIdx.x / sh.ntile, k = blockIdx.x - r * sh.ntile;
-    (void)walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, code, r * E, r * E + E, sh.U);
+    const int per_cfg = ((sh.U + E - 1) / E) * sh.ntile;
+    const ItemRange it = my_items((int64_t)per_cfg * n_cfg);
+    for (int64_t g = it.begin; g < it.end; g += it.stride) {
+        const int i = (int)(g / per_cfg), local = (int)(g - (int64_t)i * per_cfg);
+        const int r = local / sh.ntile, k = local - r * sh.ntile;
+        const int64_t off = (int64_t)i * stride;
+        (void)walk_step(sh, load_tile(sh, k), tl.ct, yin + off, yout + off, code + off, r * E, r * E + E, sh.U);
+    }
 }
 
 // Per slot: first-hit probability of a percolating configuration (the detector mass at
@@ -1437,11 +1445,14 @@ __global__ void __launch_bounds__(256) k_export(DevShape sh, const float* __rest
 // elsewhere), written over every word of the state, padding included. Later terms use
 // the forward step's map unchanged: f^(m)_i = (1/deg_i) sum over metallic contacts k of
 // f^(m-1)_k, the detector column excluded.
-__global__ void __launch_bounds__(256) k_backward_init(DevShape sh, const uint8_t* __restrict__ code,
-                                                       float* __restrict__ y) {
+__global__ void __launch_bounds__(256) k_backward_init(DevShape sh, const uint8_t* __restrict__ code0,
+                                                       float* __restrict__ y0, int64_t stride, int n_cfg) {
     const int64_t total = (int64_t)((sh.U + 3) / 4) * sh.CP * 4;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total * n_cfg;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cfg = t / total, i = t - cfg * total;
+        const uint8_t* code = code0 + cfg * stride;
+        float* y = y0 + cfg * stride;
         const int64_t q = i >> 2;
         const int grp = (int)(q / sh.CP), c = (int)(q - (int64_t)grp * sh.CP);
         const int u = grp * 4 + (int)(i & 3);
@@ -1455,14 +1466,15 @@ __global__ void __launch_bounds__(256) k_backward_init(DevShape sh, const uint8_
 }
 
 // The state words themselves (no degree factor), scattered to canonical order.
-__global__ void __launch_bounds__(256) k_export_raw(DevShape sh, const float* __restrict__ y,
-                                                    float* __restrict__ f_out) {
+__global__ void __launch_bounds__(256) k_export_raw(DevShape sh, const float* __restrict__ y0,
+                                                    float* __restrict__ f_out, int64_t stride, int n_cfg) {
     const int64_t total = (int64_t)sh.U * sh.C;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total * n_cfg;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cfg = t / total, i = t - cfg * total;
         const int64_t u = i / sh.C, c = i - u * sh.C;
         const int64_t s = u * sh.C + sh.rank[c];
-        if (s < sh.N) f_out[s] = mag(__float_as_uint(y[word_of(sh, (int)u, (int)c)]));
+        if (s < sh.N) f_out[cfg * sh.N + s] = mag(__float_as_uint(y0[cfg * stride + word_of(sh, (int)u, (int)c)]));
     }
 }
 
@@ -1603,9 +1615,16 @@ hipError_t launch_span_step2(const SpanArgs& a, hipStream_t s) {
 
 hipError_t launch_chunk_step(const DevShape& sh, const float* yin, float* yout, const uint8_t* code, int depth,
                              int block, hipStream_t s) {
+    return launch_multi_step(sh, yin, yout, code, 0, 1, depth, block, s);
+}
+
+hipError_t launch_multi_step(const DevShape& sh, const float* yin, float* yout, const uint8_t* code, int64_t stride,
+                             int n_cfg, int depth, int block, hipStream_t s) {
     const int lds = (int)lds_total(sh.span_max);
-    const int grid = ((sh.U + depth - 1) / depth) * sh.ntile;
-    hipLaunchKernelGGL(k_chunk_step, dim3(grid), dim3(block), lds, s, sh, yin, yout, code, depth, lds);
+    const int64_t items = (int64_t)((sh.U + depth - 1) / depth) * sh.ntile * n_cfg;
+    // several items per workgroup when there are many (whole multiples of the XCD count)
+    const int grid = items <= 4096 ? (int)items : 4096;
+    hipLaunchKernelGGL(k_chunk_step, dim3(grid), dim3(block), lds, s, sh, yin, yout, code, stride, n_cfg, depth, lds);
     return hipGetLastError();
 }
 
@@ -1627,16 +1646,18 @@ hipError_t launch_export(const DevShape& sh, const float* y, const uint8_t* code
     return hipGetLastError();
 }
 
-hipError_t launch_backward_init(const DevShape& sh, const uint8_t* code, float* y, hipStream_t s) {
-    const int64_t total = (int64_t)((sh.U + 3) / 4) * sh.CP * 4;
+hipError_t launch_backward_init(const DevShape& sh, const uint8_t* code, float* y, int64_t stride, int n_cfg,
+                                hipStream_t s) {
+    const int64_t total = (int64_t)((sh.U + 3) / 4) * sh.CP * 4 * n_cfg;
     const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_backward_init, dim3(grid), dim3(256), 0, s, sh, code, y);
+    hipLaunchKernelGGL(k_backward_init, dim3(grid), dim3(256), 0, s, sh, code, y, stride, n_cfg);
     return hipGetLastError();
 }
 
-hipError_t launch_export_raw(const DevShape& sh, const float* y, float* f_out, hipStream_t s) {
-    const int grid = (int)std::min<int64_t>(((int64_t)sh.U * sh.C + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_export_raw, dim3(grid), dim3(256), 0, s, sh, y, f_out);
+hipError_t launch_export_raw(const DevShape& sh, const float* y, float* f_out, int64_t stride, int n_cfg,
+                             hipStream_t s) {
+    const int grid = (int)std::min<int64_t>(((int64_t)sh.U * sh.C * n_cfg + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_export_raw, dim3(grid), dim3(256), 0, s, sh, y, f_out, stride, n_cfg);
     return hipGetLastError();
 }
 

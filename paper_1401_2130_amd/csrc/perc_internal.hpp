@@ -308,8 +308,12 @@ hipError_t launch_chunk_step(const DevShape& sh, const float* yin, float* yout, 
                              int block, hipStream_t s);
 hipError_t launch_far_sum(const DevShape& sh, const float* y, float* det_mass, uint32_t* det_reached,
                           hipStream_t s);
-hipError_t launch_backward_init(const DevShape& sh, const uint8_t* code, float* y, hipStream_t s);
-hipError_t launch_export_raw(const DevShape& sh, const float* y, float* f_out, hipStream_t s);
+hipError_t launch_backward_init(const DevShape& sh, const uint8_t* code, float* y, int64_t stride, int n_cfg,
+                                hipStream_t s);
+hipError_t launch_export_raw(const DevShape& sh, const float* y, float* f_out, int64_t stride, int n_cfg,
+                             hipStream_t s);
+hipError_t launch_multi_step(const DevShape& sh, const float* yin, float* yout, const uint8_t* code, int64_t stride,
+                             int n_cfg, int depth, int block, hipStream_t s);
 hipError_t launch_steps_hist(const uint8_t* perc, const int32_t* steps, int64_t n, int32_t nbins,
                              unsigned long long* hist, hipStream_t s);
 hipError_t launch_export(const DevShape& sh, const float* y, const uint8_t* code, const float* det_mass,

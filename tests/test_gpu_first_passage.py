@@ -115,3 +115,17 @@ def test_steps_hist_bit_exact(perc, W, L, p, n, nbins):
     for i in np.nonzero(pm)[0]:
         want[min(int(sm[i]), nbins - 1)] += 1
     np.testing.assert_array_equal(hist.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("W,L,p,M,n", [(3, 13, 0.5, 7, 5), (16, 37, 0.3, 12, 3), (2, 9, 0.6, 1, 4)])
+def test_first_passage_batch(perc, W, L, p, M, n):
+    """Several configurations in one call: each equals the oracle within the bound and the
+    one-configuration call bit for bit."""
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    occ = workloads.random_occupancy(ref.n, n, p, 900 + W + L)
+    fb = perc.perc_first_passage_batch(lat, dev(occ), M).cpu().numpy()
+    for i in range(n):
+        check_fp(fb[i], ref.first_passage_all(occ[i], M), M)
+        f1 = perc.perc_first_passage(lat, dev(occ[i]), M).cpu().numpy()
+        np.testing.assert_array_equal(f1.view(np.uint32), fb[i].view(np.uint32))
