@@ -1110,6 +1110,30 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
     }
 }
 
+// Inclusive scan of one value per thread over the workgroup (blockDim a multiple of 64):
+// shuffles inside each wave, then the wave totals through `tot` (one slot per wave, LDS);
+// *all receives the sum over the workgroup. One barrier; `tot` may be reused only after
+// another barrier.
+template <typename T>
+__device__ __forceinline__ T block_scan(T v, T* tot, T* all) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    if (lane == 63) tot[wid] = v;
+    __syncthreads();
+    T base = 0, sum = 0;
+    for (int w = 0; w < nw; ++w) {
+        const T x = tot[w];
+        base += w < wid ? x : (T)0;
+        sum += x;
+    }
+    *all = sum;
+    return v + base;
+}
+
 // Decide every listed configuration (all slots if first, else the active list) from
 // its flags, write the outputs of those that stopped (and list them in a.fin), and lay
 // out the items of the next step for the rest. A slot just initialised (m = -1) gets
@@ -1117,8 +1141,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
 // decision; any other keeps its state (it is only laid out again). One workgroup of
 // kMaxBlock threads.
 __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) {
-    __shared__ int32_t keep_s[kMaxBlock];
-    __shared__ int64_t chunk_s[kMaxBlock];
+    __shared__ int32_t keep_s[kMaxBlock / 64];
+    __shared__ int64_t chunk_s[kMaxBlock / 64];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int n_act = first ? a.n_slot : a.hdr[0];
     const int per = (n_act + nt - 1) / nt;
@@ -1167,22 +1191,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         }
         a.st[b] = s;
     }
-    keep_s[tid] = keep;
-    chunk_s[tid] = chunks;
-    __syncthreads();
-    // inclusive scans over the threads (Hillis-Steele)
-    for (int off = 1; off < nt; off <<= 1) {
-        const int32_t kv = tid >= off ? keep_s[tid - off] : 0;
-        const int64_t cv = tid >= off ? chunk_s[tid - off] : 0;
-        __syncthreads();
-        keep_s[tid] += kv;
-        chunk_s[tid] += cv;
-        __syncthreads();
-    }
-    int32_t kpos = keep_s[tid] - keep;
-    int64_t cpos = chunk_s[tid] - chunks;
-    const int32_t n_keep = keep_s[nt - 1];
-    const int64_t n_chunks = chunk_s[nt - 1];
+    int32_t n_keep;
+    int64_t n_chunks;
+    int32_t kpos = block_scan(keep, keep_s, &n_keep) - keep;
+    int64_t cpos = block_scan(chunks, chunk_s, &n_chunks) - chunks;
     unsigned long long tubes = 0;
     for (int i = i0; i < i1; ++i) {
         const int b = first ? i : a.active[i];
