@@ -434,3 +434,20 @@ def test_two_step_form_bitwise_at_full_size(perc, p):
     pm, sm, _ = ref.inspect_markov(host_words(occ)[pick])
     np.testing.assert_array_equal(p2.cpu().numpy()[pick], pm)
     np.testing.assert_array_equal(s2.cpu().numpy()[pick], sm)
+
+
+@pytest.mark.parametrize("form", ["span", "plain"])
+def test_largest_serving_fiber(perc, form):
+    """W=64, L=4096 (17,040,724 tubes, the largest fiber of the serving mix): bits and
+    steps of Philox configurations on both sides of its threshold against the oracle's
+    breadth-first search (steps = shortest path + 1, pinned equal to the Markov count)."""
+    W, L = 64, 4096
+    lat = perc.Lattice(W, L)
+    ref = oracle.Lattice(W, L)
+    for p in (0.16, 0.17):
+        occ = perc.perc_sample(lat, p, 5, 2)
+        pg, sg, _ = perc.perc_inspect_ex(lat, occ, 2, form=form)
+        torch.cuda.synchronize()
+        pb, sb = ref.inspect_bfs(host_words(occ))
+        np.testing.assert_array_equal(pg.cpu().numpy(), pb)
+        np.testing.assert_array_equal(sg.cpu().numpy(), sb)
