@@ -417,6 +417,11 @@ def main():
                                "configurations, Philox seed 2",
                    "form": args.form, "depth": args.depth, "block": args.block},
         "site_updates_per_s": site_updates / (elapsed / args.steps),
+        # the work-independent count (N x steps per configuration) priced at the same
+        # 8.375 B: the kernel touches only the cells up to front + 1 of each step, so this
+        # exceeds the bytes it moves; the roofline below uses the cells it does process
+        "site_update_bytes": {"gbs": site_updates / (elapsed / args.steps) * BYTES_PER_TUBE_STEP / 1e9,
+                              "frac": site_updates / (elapsed / args.steps) * BYTES_PER_TUBE_STEP / 1e9 / HBM_PEAK_GBS},
         "graph_replay": {"configs_per_s": n_total * args.steps / elapsed_graph,
                          "ms_per_step": elapsed_graph / args.steps * 1e3,
                          "note": "same steps from captured HIP graphs, no per-launch events"},
