@@ -294,7 +294,12 @@ __device__ __forceinline__ uint32_t tube_update(const uint32_t (&n)[kSide], uint
     // reached: metallic (the floor is 0 otherwise), and reached before or next to a
     // reached tube. The new word is non-zero exactly for reached tubes: cells beyond
     // the cut have no reached input, cells beyond U are coded insulating.
-    return __float_as_uint(fmaxf(x * t.x, (x != 0.0f || own != 0u) ? t.y : 0.0f));
+    // All words are non-negative floats (never -0), ordered like their bit patterns, so
+    // max(x / deg, floor if x != 0 or own != 0) is an unsigned maximum, and the floor's
+    // bits (0 or 1) against the bits of x | own (0 exactly when neither is reached) an
+    // unsigned minimum.
+    const uint32_t floor_w = min(__float_as_uint(t.y), __float_as_uint(x) | own);
+    return max(__float_as_uint(x * t.x), floor_w);
 }
 
 struct StepState {
