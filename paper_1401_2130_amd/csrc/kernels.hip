@@ -279,7 +279,7 @@ __device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
 // layer pairs, then the end contacts), then the table entry of the tube's degree code.
 // Every walk calls this, so a tube gets the same bits whichever kernel computes it.
 __device__ __forceinline__ uint32_t tube_update(const uint32_t (&n)[kSide], uint32_t dn, uint32_t up, uint32_t own,
-                                                int32_t ends, const float4 t) {
+                                                int32_t ends, const float4* ct, uint32_t cd) {
     const float s01 = mag(n[0]) + mag(n[1]);
     const float s23 = mag(n[2]) + mag(n[3]);
     const float s45 = mag(n[4]) + mag(n[5]);
@@ -288,9 +288,14 @@ __device__ __forceinline__ uint32_t tube_update(const uint32_t (&n)[kSide], uint
     const float sab = mag(n[10]) + mag(n[11]);
     const float sud = ends ? mag(dn) + mag(up) : 0.0f;
     const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
+    // the table entry's 1/deg from LDS; its self weight (1 for degree 0) and reach floor
+    // (2^-149, bits 1, for a metallic tube) follow from the code itself
+    const float rcp = ct[cd].x;
+    const float self = cd == 0u ? 1.0f : 0.0f;
+    const uint32_t floor_bits = cd < 15u ? 1u : 0u;
     // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its own
     // mass (self weight 1); for every other code the own word enters with weight 0
-    const float x = fmaf(__uint_as_float(own), t.z, sum);
+    const float x = fmaf(__uint_as_float(own), self, sum);
     // reached: metallic (the floor is 0 otherwise), and reached before or next to a
     // reached tube. The new word is non-zero exactly for reached tubes: cells beyond
     // the cut have no reached input, cells beyond U are coded insulating.
@@ -298,8 +303,8 @@ __device__ __forceinline__ uint32_t tube_update(const uint32_t (&n)[kSide], uint
     // max(x / deg, floor if x != 0 or own != 0) is an unsigned maximum, and the floor's
     // bits (0 or 1) against the bits of x | own (0 exactly when neither is reached) an
     // unsigned minimum.
-    const uint32_t floor_w = min(__float_as_uint(t.y), __float_as_uint(x) | own);
-    return max(__float_as_uint(x * t.x), floor_w);
+    const uint32_t floor_w = min(floor_bits, __float_as_uint(x) | own);
+    return max(__float_as_uint(x * rcp), floor_w);
 }
 
 struct StepState {
@@ -333,7 +338,7 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
     uint32_t n[kSide];
 #pragma unroll
     for (int i = 0; i < kSide; ++i) n[i] = w.nb[i][K * kBlkCols];
-    ss.res[k] = tube_update(n, dn, up, own, sh.ends, ct[cd]);
+    ss.res[k] = tube_update(n, dn, up, own, sh.ends, ct, cd);
     ss.grew |= own == 0u ? ss.res[k] : 0u;
     if (k == 3) {
         const int u4 = u - 3;
@@ -489,7 +494,7 @@ __device__ __forceinline__ void first_cell(const DevShape& sh, const Prod& p, co
         uint32_t n[kSide];
 #pragma unroll
         for (int i = 0; i < kSide; ++i) n[i] = p.nb[j][i][K * kBlkCols];
-        uint32_t v = tube_update(n, dn, up, own, sh.ends, ct[cd]);
+        uint32_t v = tube_update(n, dn, up, own, sh.ends, ct, cd);
         v = (u >= 0 && u <= vmax1) ? v : 0u;
         if ((K & 3) == 0) {
             ss.first0[j] = v;  // its R1 row may still be read before the next barrier
@@ -531,7 +536,7 @@ __device__ __forceinline__ void second_cell(const DevShape& sh, const Own& w, co
     uint32_t n[kSide];
 #pragma unroll
     for (int i = 0; i < kSide; ++i) n[i] = w.nb[i][K * kBlkCols];
-    ss.r2[k] = tube_update(n, dn, up, own, sh.ends, ct[cd]);
+    ss.r2[k] = tube_update(n, dn, up, own, sh.ends, ct, cd);
     ss.grew2 |= own == 0u ? ss.r2[k] : 0u;
     if (k == 3) {
         const int u4 = u - 3;
