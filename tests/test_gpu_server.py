@@ -107,3 +107,30 @@ def test_idle_ticks_and_reuse(perc):
         if len(results) == len(reqs):
             break
     check_against_alone_and_oracle(perc, reqs, results)
+
+
+def test_serving_recipe_sample(perc):
+    """The first 96 requests of the serving workload (W 8..64, L 64..4096, p 0.12..0.19,
+    Philox seed = request id) through the server in the configuration the benchmark
+    uses: every request with N <= 1e6 and a fixed sample of larger ones (every 48th)
+    against the oracle's breadth-first search (bits and steps)."""
+    from paper_1401_2130_amd import workloads
+    base = workloads.serving_requests(96)
+    reqs = [(t * 0.0, W, L, p, i, 0, i) for (t, W, L, p, i) in base]  # all arrive at once
+    stream = torch.cuda.Stream()
+    srv = perc.perc_server(hbm_bytes=32 << 30, max_slots=256, tick_steps=16,
+                           max_w=workloads.SERVING.w_range[1], stream=stream)
+    res = {r["tag"]: r for r in srv.run(reqs)}
+    assert sorted(res) == list(range(96))
+    checked = 0
+    for (_, W, L, p, seed, cfg, tag) in reqs:
+        n = perc.Lattice(W, L).n
+        if n > 1_000_000 and tag % 48:
+            continue
+        ref = oracle.Lattice(W, L)
+        pb, sb = ref.inspect_bfs(ref.sample(p, seed, 1, cfg0=cfg))
+        r = res[tag]
+        assert r["status"] == 0
+        assert (r["perc"], r["steps"]) == (int(pb[0]), int(sb[0])), (tag, W, L, p, r)
+        checked += 1
+    assert checked >= 10
