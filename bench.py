@@ -241,7 +241,7 @@ def torch_sync():
     torch.cuda.synchronize()
 
 
-def serving_leg(perc, workloads, n: int, rate_hz: float, stream):
+def serving_leg(perc, workloads, n: int, rate_hz: float, stream, grid: int = 0, tick: int = 16):
     """Serve the first n requests of the serving recipe (W, L, p per request; Philox seed
     = request id, configuration 0) with arrivals rescaled to rate_hz; latency = completion
     minus scheduled arrival on the host steady clock."""
@@ -249,8 +249,8 @@ def serving_leg(perc, workloads, n: int, rate_hz: float, stream):
     base = workloads.serving_requests(n)
     scale = workloads.SERVING.rate_hz / rate_hz
     reqs = [(t * scale, W, L, p, i, 0, i) for (t, W, L, p, i) in base]
-    srv = perc.perc_server(hbm_bytes=96 << 30, max_slots=2048, tick_steps=16, max_w=workloads.SERVING.w_range[1],
-                           stream=stream)
+    srv = perc.perc_server(hbm_bytes=96 << 30, max_slots=2048, tick_steps=tick, max_w=workloads.SERVING.w_range[1],
+                           grid=grid, stream=stream)
     t0 = time.perf_counter()
     res = srv.run(reqs)
     wall = time.perf_counter() - t0
@@ -263,7 +263,7 @@ def serving_leg(perc, workloads, n: int, rate_hz: float, stream):
             "completed_per_s": n / wall, "site_updates_per_s": upd / wall,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "max_ms": float(lat.max()), "percolating": float(np.mean([r["perc"] for r in res])),
-            "ticks": st["ticks"], "tick_steps": 16, "max_slots": 2048,
+            "ticks": st["ticks"], "tick_steps": tick, "max_slots": 2048, "grid": grid,
             "overloaded": bool(wall > 1.5 * span + 1.0)}
 
 
@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--serve-low-rate", type=float, default=150.0,
                     help="serving leg at a sustainable rate: the same request mix at this many per second")
     ap.add_argument("--serve-low-requests", type=int, default=450)
+    ap.add_argument("--serve-grid", type=int, default=0, help="server step-launch workgroups (0: library default)")
+    ap.add_argument("--serve-tick", type=int, default=16, help="steps per server tick")
     ap.add_argument("--batched", type=int, default=1, help="batched Pi(p) leg (W=16 L=256, 21 p x 4096)")
     ap.add_argument("--first-passage", type=int, default=1024,
                     help="moves of the backward all-sources leg on the headline fiber (0: skip)")
@@ -468,11 +470,11 @@ def main():
     if args.serve_requests > 0:
         log(f"serving: {args.serve_requests} requests at {workloads.SERVING.rate_hz:.0f}/s ...")
         result["serving"] = {"offered": serving_leg(perc, workloads, args.serve_requests, workloads.SERVING.rate_hz,
-                                                    stream)}
+                                                    stream, args.serve_grid, args.serve_tick)}
         if args.serve_low_requests > 0:
             log(f"serving: {args.serve_low_requests} requests at {args.serve_low_rate:.0f}/s ...")
             result["serving"]["sustainable"] = serving_leg(perc, workloads, args.serve_low_requests,
-                                                           args.serve_low_rate, stream)
+                                                           args.serve_low_rate, stream, args.serve_grid, args.serve_tick)
         result["serving"]["workload"] = ("Poisson arrivals (seed 5), W uniform 8..64, L uniform 64..4096, "
                                          "p uniform 0.12..0.19, Philox seed = request id, configuration 0")
         log(f"serving p50/p99: {result['serving']['offered']['p50_ms']:.1f} / "
