@@ -99,11 +99,25 @@ def batched_leg(perc, workloads, stream):
     _, st, _, counts = perc.perc_batch(jobs, n_groups=len(wl.ps), stream=stream, **opts)
     torch_sync()
     wall = time.perf_counter() - t0
+    # the same batch once more with the step profiler: kernel time and tube slots
+    perc.perc_profile_enable(True)
+    perc.perc_batch(jobs, n_groups=len(wl.ps), stream=stream, **opts)
+    torch_sync()
+    prof = perc.perc_profile_read()
+    perc.perc_profile_enable(False)
     steps = st.cpu().numpy().astype(np.int64)
     pis = np.array(counts) / n
     out = {"workload": f"W={W} L={L} ({lat.n} tubes), p = 0.100..0.200 step 0.005 x {n}, Philox seed {seed}",
            "configs": len(jobs), "configs_per_s": len(jobs) / wall, "wall_s": wall,
            "site_updates_per_s": float(steps.sum()) * lat.n / wall, "autotune": tuned,
+           "kernel_roofline": {"achieved_gbs": prof["tube_steps"] * BYTES_PER_TUBE_STEP / (prof["step_ms"] / 1e3) / 1e9
+                               if prof["step_ms"] > 0 else None,
+                               "frac": prof["tube_steps"] * BYTES_PER_TUBE_STEP / (prof["step_ms"] / 1e3) / 1e9
+                               / HBM_PEAK_GBS if prof["step_ms"] > 0 else None,
+                               "launches": prof["step_launches"], "kernel_ms": prof["step_ms"],
+                               "tube_steps": prof["tube_steps"],
+                               "note": "tube slots of the steps x 8.375 B over the step-kernel time "
+                                       "(the persistent form's one launch also samples and initialises)"},
            "pi": {f"{p:.3f}": float(v) for p, v in zip(wl.ps, pis)}}
     try:
         pc, T, cov = fss.fit_fermi_dirac(wl.ps, pis, n)

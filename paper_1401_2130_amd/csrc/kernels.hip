@@ -1348,6 +1348,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
     float* ya = a.ya + blockIdx.x * a.state_stride;
     float* yb = a.yb + blockIdx.x * a.state_stride;
     uint8_t* code = a.code + blockIdx.x * a.state_stride;
+    unsigned long long work = 0;  // tube slots advanced by this workgroup's steps
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1357,7 +1358,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
         }
         __syncthreads();
         const int64_t j = (int64_t)(((uint64_t)tl.misc[3] << 32) | tl.misc[2]);
-        if (j >= a.n_jobs) break;
+        if (j >= a.n_jobs) {
+            if (threadIdx.x == 0 && a.work && work) atomicAdd(a.work, work);
+            break;
+        }
         const Job job = uniform_load(a.jobs + j);
         const DevShape sh = uniform_load(a.shapes + job.shape);
         const uint32_t* bits;
@@ -1390,6 +1394,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
             const float* yin = (mm & 1) ? yb : ya;
             float* yout = (mm & 1) ? ya : yb;
             const int ulim = min(sh.U, front + 2);
+            work += (unsigned long long)ulim * (unsigned long long)sh.C;
             uint32_t fl = 0;
             for (int ub = 0; ub < ulim; ub += E)
                 for (int k = 0; k < sh.ntile; ++k)

@@ -612,8 +612,10 @@ int run_persist(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out,
     a.bits_stride = bw;
     Job* d_jobs = ar.take<Job>(n);
     DevShape* d_shapes = ar.take<DevShape>(S.dev.size());
-    a.queue = ar.take<unsigned long long>(2);
+    a.queue = ar.take<unsigned long long>(3);
     a.err = reinterpret_cast<uint32_t*>(a.queue + 1);
+    const bool prof = profiling();
+    if (prof) a.work = a.queue + 2;
     HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_shapes, S.dev.data(), sizeof(DevShape) * S.dev.size(), hipMemcpyHostToDevice, s));
     a.shapes = d_shapes;
@@ -624,8 +626,31 @@ int run_persist(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out,
     a.block = tu.block;
     a.grid = grid;
     a.lds = lds;
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.queue), 4, 0u, s));
-    HIP_TRY(launch_persist(a, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.queue), 6, 0u, s));
+    if (!prof) {
+        HIP_TRY(launch_persist(a, s));
+        return PERC_OK;
+    }
+    // profiled: the launch between HIP events on its stream, and the tube slots its
+    // steps advanced (synchronous)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_persist(a, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    unsigned long long tubes = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&tubes, a.work, sizeof(tubes), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(e);
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    g_prof.launches += 1;
+    g_prof.ms += ms;
+    g_prof.tube_steps += (int64_t)tubes;
     return PERC_OK;
 }
 

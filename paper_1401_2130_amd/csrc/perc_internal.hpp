@@ -294,6 +294,7 @@ struct PersistArgs {
     int64_t state_stride;
     unsigned long long* queue;  // next job to take
     uint32_t* err;              // set when a configuration reached the step cap
+    unsigned long long* work;   // tube slots the steps advanced (nullable)
     BatchOut out;
     int32_t depth;
     int32_t block;
