@@ -955,8 +955,9 @@ int server_init(perc_server* v, const perc_server_config* cfg, hipStream_t s) {
         HIP_TRY(hipMemGetInfo(&free_b, &total_b));
         c.hbm_bytes = std::min<int64_t>((int64_t)(free_b / 2), 64ll << 30);
     }
-    // pool: per state word 9 bytes (two FP32 buffers, one code byte), occupancy words an
-    // eighth of the state words (a tube needs 1/32 of a word, rounded per request)
+    // pool: per state word 9 bytes (two FP32 buffers, and one byte of code region, of
+    // which the four-bit codes use half), occupancy words an eighth of the state words (a
+    // tube needs 1/32 of a word, rounded per request)
     const int64_t unit = 9 * 16 + 2 * 4;
     const int64_t blocks = c.hbm_bytes / unit;
     v->state_cap = blocks * 16;
