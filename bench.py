@@ -224,6 +224,45 @@ def ablation_leg(perc, workloads, stream):
     return out
 
 
+def fixed_count_leg(perc, workloads, stream):
+    """Fixed-count ensemble (Sec. II.A) on the batched fiber (W=16 L=256): the device
+    sampler alone (exactly K metallic tubes, the K smallest of N Philox keys) timed with
+    HIP events, then Pi_k at 11 k around the fiber's threshold (one batch) and their
+    binomial convolution (Pi_k interpolated linearly in k) to Pi(p) at three p."""
+    import numpy as np
+    import torch
+    from paper_1401_2130_amd import fss
+    wl = workloads.BATCH
+    (W, L), seed = wl.shapes[0], wl.seed
+    lat = perc.Lattice(W, L)
+    N, n = lat.n, 1024
+    out = torch.empty((n, lat.words), dtype=torch.int32, device="cuda")
+    perc.perc_sample_fixed(lat, 0.18, seed, 64, out=out[:64], stream=stream)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    perc.perc_sample_fixed(lat, 0.18, seed, n, out=out, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    ks = [int(round(N * (0.170 + 0.0025 * i))) for i in range(11)]
+    torch_sync()
+    t0 = time.perf_counter()
+    counts = fss.pi_fixed_counts(W, L, ks, n, seed, stream=stream)
+    torch_sync()
+    wall = time.perf_counter() - t0
+    pk = counts / n
+    ps = [0.1775, 0.18, 0.1825]
+    # Pi_k is smooth in k: linear interpolation between the measured k gives every k of
+    # the window the binomial weights need
+    kk = np.arange(ks[0], ks[-1] + 1)
+    conv, miss = fss.binomial_convolution(kk, np.interp(kk, ks, pk), N, ps)
+    return {"workload": f"W={W} L={L} ({N} tubes), Philox seed {seed}",
+            "sampler": {"configs": n, "ms": ms, "configs_per_s": n / (ms / 1e3), "keys_per_s": n * N / (ms / 1e3)},
+            "pi_k": {"k": ks, "pi_k": pk.tolist(), "configs": n * len(ks), "wall_s": wall,
+                     "configs_per_s": n * len(ks) / wall},
+            "convolution": {f"{p}": {"pi": float(v), "uncovered_mass": float(m)} for p, v, m in zip(ps, conv, miss)}}
+
+
 def fig6a_leg(perc, workloads, stream):
     """Pi against the fiber length at W = 3 (Fig. 6a): decay rate per p from ln Pi
     linear in L, and the line -ln(rate) against p (its inset)."""
@@ -310,6 +349,7 @@ def main():
                     help="moves of the backward all-sources leg on the headline fiber (0: skip)")
     ap.add_argument("--ablation", type=int, default=1, help="regular FCC vs modified lattice thresholds")
     ap.add_argument("--fig6a", type=int, default=1, help="Pi against L at W=3, decay rates")
+    ap.add_argument("--fixed-count", type=int, default=1, help="fixed-count ensemble sampler and Pi_k leg")
     ap.add_argument("--uneven", type=int, default=1, help="uneven aspect-ratio sweep leg (35 shapes x 2 p x 1024)")
     args = ap.parse_args()
 
@@ -477,6 +517,10 @@ def main():
         result["ablation"] = ablation_leg(perc, workloads, stream)
         log(f"ablation: pc_inf regular {result['ablation']['variants']['regular_fcc']['pc_inf_eq7']}, "
             f"modified {result['ablation']['variants']['modified']['pc_inf_eq7']}")
+    if args.fixed_count:
+        log("fixed-count ensemble leg ...")
+        result["fixed_count"] = fixed_count_leg(perc, workloads, stream)
+        log(f"fixed count: sampler {result['fixed_count']['sampler']['configs_per_s']:.0f} configs/s")
     if args.fig6a:
         log("Fig. 6a leg (Pi vs L at W=3) ...")
         result["fig6a"] = fig6a_leg(perc, workloads, stream)
