@@ -312,7 +312,7 @@ struct StepState {
     uint32_t cq[2];         // code words of the current and the next eight cells
     uint32_t res[4];        // new words of the current group
     uint32_t grew = 0;      // OR of the new words of tubes that were not reached before
-    uint32_t far = 0, entered = 0;
+    uint32_t far = 0, entered = 0, entered2 = 0;
 };
 
 // Cell u = u8 + K (ring slot K) of a step walk.
@@ -348,14 +348,18 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
             const int kt = w.top - u4;
             ss.far |= kt == 0 ? ss.res[0] : kt == 1 ? ss.res[1] : kt == 2 ? ss.res[2] : kt == 3 ? ss.res[3] : 0u;
         }
-        const int kf = front + 1 - u4;
+        const int kf = front + 1 - u4, kf2 = front + 2 - u4;
         if (kf >= 0 && kf < 4)
             ss.entered |= kf == 0 ? ss.res[0] : kf == 1 ? ss.res[1] : kf == 2 ? ss.res[2] : ss.res[3];
+        if (kf2 >= 0 && kf2 < 4)
+            ss.entered2 |= kf2 == 0 ? ss.res[0] : kf2 == 1 ? ss.res[1] : kf2 == 2 ? ss.res[2] : ss.res[3];
     }
 }
 
 // One Jacobi step of the tile's tubes in cells [ub, ue) (cut at min(U, front+2); ub a
-// multiple of 8), reading yin and writing yout. Returns this thread's step flags. The
+// multiple of 8), reading yin, whose reached tubes lie in cells <= front, and writing
+// yout. Returns this thread's step flags; the front flags tell whether the new state
+// reaches cell front_chk+1 (F_FRONT) and front_chk+2 (F_FRONT2). The
 // 14 contributions are summed in one fixed pairwise order, so a tube gets the same
 // FP32 result in every execution form, item layout and batch composition. The words
 // written for cells of the last group at or beyond the cut are zero (their inputs are
@@ -363,7 +367,8 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
 // reader uses them.
 __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& tv, const float4* ct,
                                               const float* __restrict__ yin, float* __restrict__ yout,
-                                              const uint8_t* __restrict__ code, int ub, int ue, int front) {
+                                              const uint8_t* __restrict__ code, int ub, int ue, int front,
+                                              int front_chk) {
     ue = min(ue, min(sh.U, front + 2));
     if (ub >= ue) return 0u;
     const int vmax = min(front, sh.U - 1);
@@ -385,17 +390,18 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
     ss.cq[1] = 0xffffffffu;  // (g0 is even: the first word covers g0 and g0 + 1)
     __syncthreads();
     for (int u8 = ub; u8 < ue; u8 += kRingCells) {
-        step_cell<0>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
-        step_cell<1>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
-        step_cell<2>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
-        step_cell<3>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
+        step_cell<0>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
+        step_cell<1>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
+        step_cell<2>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
+        step_cell<3>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
         if (u8 + 4 >= ue) break;
-        step_cell<4>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
-        step_cell<5>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
-        step_cell<6>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
-        step_cell<7>(sh, st, w, ct, yin, yout, code4, u8, front, vmax, top_min, ss);
+        step_cell<4>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
+        step_cell<5>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
+        step_cell<6>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
+        step_cell<7>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
     }
-    return (ss.grew ? F_GREW : 0u) | (ss.far ? F_FAR : 0u) | (ss.entered ? F_FRONT : 0u);
+    return (ss.grew ? F_GREW : 0u) | (ss.far ? F_FAR : 0u) | (ss.entered ? F_FRONT : 0u) |
+           (ss.entered2 ? F_FRONT2 : 0u);
 }
 
 // ------------------------------------------------------------------------------
@@ -1174,10 +1180,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
             if (!(f & F_NONEMPTY)) { dec = 0; steps = 0; }
             else if (f & F_FAR) { dec = 1; steps = 1; }
         } else if (f & F_STEPPED) {
-            s.par ^= 1;  // every step launch writes the other buffer
+            // a step launch writes the other buffer; a pair of launches writes both, the
+            // newest state back in the buffer the pair started from
+            if (!a.pair) s.par ^= 1;
             s.m += 1;
             if (f & F_FRONT) s.front += 1;
-            if (f & F_FAR) { dec = 1; steps = s.m + 1; if (f & F_FUSED) s.done = 3; }
+            if (f & F_FAR) { dec = 1; steps = s.m + 1; if (f & F_FUSED) s.done = a.pair ? 4 : 3; }
             else if (!(f & F_GREW)) { dec = 0; steps = s.m; }
             else if (f & F_FUSED) {
                 // the second step of a two-step launch, decided as a step of its own; its
@@ -1197,7 +1205,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
             if (a.fin) a.fin[atomicAdd(a.hdr + 3, 1)] = b;
         } else {
             keep += 1;
-            chunks += items_of(sh, min(sh.U, s.front + (a.fused ? 3 : 2)), E);
+            chunks += items_of(sh, min(sh.U, s.front + (a.fused || a.pair ? 3 : 2)), E);
         }
         a.st[b] = s;
     }
@@ -1214,9 +1222,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         a.active2[kpos] = b;
         a.chunk_off[kpos] = cpos;
         kpos += 1;
-        cpos += items_of(sh, min(sh.U, s.front + (a.fused ? 3 : 2)), E);
-        // tube slots advanced by one step each; a two-step launch counts its window twice
-        tubes += (unsigned long long)min(sh.U, s.front + 2) * (unsigned long long)sh.C * (a.fused ? 2ull : 1ull);
+        cpos += items_of(sh, min(sh.U, s.front + (a.fused || a.pair ? 3 : 2)), E);
+        // tube slots advanced by one step each; two steps per plan count the window twice
+        tubes += (unsigned long long)min(sh.U, s.front + 2) * (unsigned long long)sh.C * (a.fused || a.pair ? 2ull : 1ull);
     }
     if (a.work && tubes) atomicAdd(a.work, tubes);
     __syncthreads();
@@ -1251,11 +1259,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
         const int r = local / sh.ntile, k = local - r * sh.ntile;
         const CfgState s = uniform_load(a.st + b);
         const int64_t off = uniform_i64(a.slot_off + b);
-        const float* yin = (s.par ? a.yb : a.ya) + off;
-        float* yout = (s.par ? a.ya : a.yb) + off;
+        // the second launch of a pair reads the first one's output and writes the buffer
+        // the pair started from; its input reaches one cell further
+        const int par = s.par ^ a.sub;
+        const float* yin = (par ? a.yb : a.ya) + off;
+        float* yout = (par ? a.ya : a.yb) + off;
         const uint32_t fl = walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, a.code + off, r * E, r * E + E,
-                                      s.front);
-        flags_to(&a.st[b].flags, fl | (threadIdx.x < 64 ? F_STEPPED : 0u));
+                                      s.front + a.sub, s.front);
+        if (a.sub) {
+            flags_to(&a.st[b].flags, threadIdx.x < 64 ? F_FUSED : 0u);
+            flags_to(&a.st[b].flags2, fl);
+        } else {
+            flags_to(&a.st[b].flags, (fl & ~F_FRONT2) | (threadIdx.x < 64 ? F_STEPPED : 0u));
+        }
     }
 }
 
@@ -1307,7 +1323,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_chunk_step(DevShape sh, const flo
         const int i = (int)(g / per_cfg), local = (int)(g - (int64_t)i * per_cfg);
         const int r = local / sh.ntile, k = local - r * sh.ntile;
         const int64_t off = (int64_t)i * stride;
-        (void)walk_step(sh, load_tile(sh, k), tl.ct, yin + off, yout + off, code + off, r * E, r * E + E, sh.U);
+        (void)walk_step(sh, load_tile(sh, k), tl.ct, yin + off, yout + off, code + off, r * E, r * E + E, sh.U,
+                        sh.U);
     }
 }
 
@@ -1334,6 +1351,8 @@ __global__ void __launch_bounds__(256) k_span_finish(SpanArgs a) {
         const CfgState st = a.st[b];
         if (st.done == 3)  // after the first step of a two-step launch: its far-end words
             far_sum_cols(sh, a.far1 + (int64_t)b * a.far1_stride, st.front, part, &reached, &result);
+        else if (st.done == 4)  // after the first launch of a pair: the other buffer
+            far_sum(sh, (st.par ? a.ya : a.yb) + a.slot_off[b], st.front, part, &reached, &result);
         else  // the state after steps - 1 steps, the newest one
             far_sum(sh, (st.par ? a.yb : a.ya) + a.slot_off[b], st.front, part, &reached, &result);
         if (threadIdx.x == 0) a.out.hit[b] = result;
@@ -1398,7 +1417,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
             uint32_t fl = 0;
             for (int ub = 0; ub < ulim; ub += E)
                 for (int k = 0; k < sh.ntile; ++k)
-                    fl |= walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, code, ub, ub + E, front);
+                    fl |= walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, code, ub, ub + E, front, front);
             __syncthreads();
             if (threadIdx.x == 0) tl.misc[0] = 0;
             __syncthreads();

@@ -53,6 +53,9 @@ int hip_fail(hipError_t e, const char* what) {
     } while (0)
 
 constexpr size_t kMaxLds = 160 * 1024;
+// The span form advances every configuration by two one-step launches between plans.
+constexpr bool kSpanPairs = true;
+
 // Workgroups per span step launch (16 per CU, a multiple of the 8 XCDs): enough that the
 // tiles of several cell ranges run side by side on every XCD (measured at W=32 L=1024:
 // 1024 -> 178.5 us, 2048 -> 158.8, 4096 -> 153.9, 8192 -> 154.1 per step).
@@ -403,6 +406,13 @@ int64_t slot_words(const LatticeDesc& d) { return (state_words(d) + 63) & ~(int6
 int64_t bits_words(const LatticeDesc& d) { return (d.words + 63) & ~(int64_t)63; }
 
 // Span and plain forms: waves of slots sized to the memory budget.
+// The second launch of a pair: the same work list, reading the first launch's output.
+SpanArgs second_of(const SpanArgs& a) {
+    SpanArgs b = a;
+    b.sub = 1;
+    return b;
+}
+
 int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, const Tuning& tu, hipStream_t s) {
     const int64_t n = (int64_t)jobs.size();
     if (n == 0) return PERC_OK;
@@ -476,6 +486,9 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
         uint32_t** d_bits = ar.take<uint32_t*>(nb);
         Job* d_jobs = ar.take<Job>(nb);
         a.hdr = ar.take<int32_t>(16);
+        // the span form runs two one-step launches between plans (the planner decides
+        // both steps), which halves the planner launches
+        a.pair = (!fused && !plain && kSpanPairs) ? 1 : 0;
         if (fused) {
             a.fused = 1;
             a.far1_stride = S.need.CP;
@@ -523,6 +536,7 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
                 hipError_t ce = hipSuccess;
                 for (int i = 0; i < tu.graph_steps && ce == hipSuccess; ++i) {
                     ce = launch_span_step(a, s);
+                    if (ce == hipSuccess && a.pair) ce = launch_span_step(second_of(a), s);
                     if (ce == hipSuccess) ce = launch_span_plan(a, s);
                 }
                 hipError_t ee = hipStreamEndCapture(s, &graph);
@@ -545,6 +559,7 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
                     } else {
                         for (int i = 0; i < tu.graph_steps && rc == PERC_OK; ++i) {
                             hipError_t e = timer.step(a, s);
+                            if (e == hipSuccess && a.pair) e = timer.step(second_of(a), s);
                             if (e == hipSuccess) e = launch_span_plan(a, s);
                             if (e != hipSuccess) rc = hip_fail(e, "span step");
                         }

@@ -194,7 +194,8 @@ struct CfgState {
     int32_t m;        // steps done
     int32_t done;     // 0 = active, 1 = decided, 2 = cap reached (error), 3 = decided with a
                       // detector hit after the first step of a two-step launch (the far-end
-                      // words of that step are in SpanArgs::far1)
+                      // words of that step are in SpanArgs::far1), 4 = the same after the
+                      // first launch of a pair (that state is in the buffer not named by par)
     uint32_t flags;   // OR of the flags of the last launch (its first step); cleared by the planner
     uint32_t flags2;  // second-step flags of a two-step launch; cleared by the planner
     int32_t par;      // state buffer holding the newest state: 0 = ya, 1 = yb
@@ -269,6 +270,8 @@ struct SpanArgs {
     int32_t grid;
     int32_t lds;               // dynamic LDS bytes of the walking kernels
     int32_t fused;             // 1: each step launch does two steps (k_span_step2)
+    int32_t pair;              // 1: two one-step launches between plans (sub 0, then sub 1)
+    int32_t sub;               // this launch's place in a pair
     int32_t r1_off;            // two-step form: LDS word offset of the inner ring
     float* far1;               // two-step form: [n_slot][far1_stride] first-step far-end words
     int32_t far1_stride;
