@@ -1049,8 +1049,10 @@ int server_init(perc_server* v, const perc_server_config* cfg, hipStream_t s) {
     a.block = tu.block;
     a.grid = tu.grid ? tu.grid : kSpanGrid;
     a.lds = (int)lds_total(nd.span_max);
+    // an even tick runs pairs of step launches between plans
+    a.pair = (kSpanPairs && v->cfg.tick_steps % 2 == 0) ? 1 : 0;
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.hdr), 16, 0u, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.st), (int64_t)M * 4, 0u, s));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.st), (int64_t)M * (int64_t)(sizeof(CfgState) / 4), 0u, s));
     const size_t pin_bytes =
         64 + (size_t)M * (4 + 1 + 4 + 4 + 4) + (size_t)M * (sizeof(Job) + sizeof(void*) + sizeof(CfgState)) + 1024;
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&v->pin), pin_bytes, hipHostMallocDefault));
@@ -1211,8 +1213,9 @@ int server_tick(perc_server* v) {
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             hipError_t ce = hipSuccess;
-            for (int i = 0; i < v->cfg.tick_steps && ce == hipSuccess; ++i) {
+            for (int i = 0; i < v->cfg.tick_steps && ce == hipSuccess; i += a.pair ? 2 : 1) {
                 ce = launch_span_step(a, s);
+                if (ce == hipSuccess && a.pair) ce = launch_span_step(second_of(a), s);
                 if (ce == hipSuccess) ce = launch_span_plan(a, s);
             }
             hipError_t ee = hipStreamEndCapture(s, &graph);
@@ -1228,8 +1231,9 @@ int server_tick(perc_server* v) {
         if (v->exec) {
             HIP_TRY(hipGraphLaunch(v->exec, s));
         } else {
-            for (int i = 0; i < v->cfg.tick_steps; ++i) {
+            for (int i = 0; i < v->cfg.tick_steps; i += a.pair ? 2 : 1) {
                 HIP_TRY(launch_span_step(a, s));
+                if (a.pair) HIP_TRY(launch_span_step(second_of(a), s));
                 HIP_TRY(launch_span_plan(a, s));
             }
         }
