@@ -117,6 +117,15 @@ __device__ __forceinline__ void fill_codes(float4* ct) {
 
 __device__ __forceinline__ float mag(uint32_t w) { return __uint_as_float(w & 0x7fffffffu); }
 
+// A new state quad to HBM as a streaming (non-temporal) store: it is read again only by
+// the next step, so it should not take L2 lines from the input state, whose halo
+// columns neighbouring tiles of the same cells read again.
+__device__ __forceinline__ void store_quad_nt(float* y, uint32_t q, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const v4u v = {a, b, c, d};
+    __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(y) + q);
+}
+
 // Cell of the far-end tube of column c: the highest layer k < L with k = sigma (mod 3),
 // or -1 if the column holds no tube.
 __device__ __forceinline__ int top_of(const DevShape& sh, int c) {
@@ -342,7 +351,7 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
     ss.grew |= own == 0u ? ss.res[k] : 0u;
     if (k == 3) {
         const int u4 = u - 3;
-        reinterpret_cast<uint4*>(yout)[quad_of(sh, g, w.c)] = make_uint4(ss.res[0], ss.res[1], ss.res[2], ss.res[3]);
+        store_quad_nt(yout, quad_of(sh, g, w.c), ss.res[0], ss.res[1], ss.res[2], ss.res[3]);
         // far-end tubes lie in the last cells of the fiber; the front cell in one group
         if (u4 + 3 >= top_min) {
             const int kt = w.top - u4;
@@ -546,7 +555,7 @@ __device__ __forceinline__ void second_cell(const DevShape& sh, const Own& w, co
     ss.grew2 |= own == 0u ? ss.r2[k] : 0u;
     if (k == 3) {
         const int u4 = u - 3;
-        reinterpret_cast<uint4*>(yout)[quad_of(sh, u4 >> 2, w.c)] = make_uint4(ss.r2[0], ss.r2[1], ss.r2[2], ss.r2[3]);
+        store_quad_nt(yout, quad_of(sh, u4 >> 2, w.c), ss.r2[0], ss.r2[1], ss.r2[2], ss.r2[3]);
         if (u4 + 3 >= top_min) {
             const int kt = w.top - u4;
             ss.far2 |= kt == 0 ? ss.r2[0] : kt == 1 ? ss.r2[1] : kt == 2 ? ss.r2[2] : kt == 3 ? ss.r2[3] : 0u;
