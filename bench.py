@@ -71,13 +71,35 @@ def cpu_baseline(wl, budget_s: float):
             per_p[p] += cores
             done += cores
             upd += int(np.sum(steps.astype(np.int64))) * ref.n
+    # the same oracle on one thread: the next configuration at each p
+    t1, upd1 = 0.0, 0
+    for p in wl.ps:
+        t0 = time.perf_counter()
+        occ = ref.sample(p, seed, 1, cfg0=per_p[p])
+        _, steps, _ = ref.inspect_markov(occ, nthreads=1)
+        t1 += time.perf_counter() - t0
+        upd1 += int(np.sum(steps.astype(np.int64))) * ref.n
     return {
         "value": done / t_total, "unit": "configs/s", "cores": cores, "kind": "oracle",
         "site_updates_per_s": upd / t_total,
         "sample": (f"configurations 0..{per_p[wl.ps[0]] - 1} at each p of the same workload "
                    f"({done} configurations, {t_total:.1f} s): host Philox sampling + explicit CSR "
                    f"FP64 Markov iteration, one configuration per OpenMP thread"),
+        "single_thread": {"value": len(wl.ps) / t1, "unit": "configs/s", "site_updates_per_s": upd1 / t1,
+                          "sample": f"configuration {per_p[wl.ps[0]]} at each p ({len(wl.ps)} configurations, {t1:.1f} s)"},
+        "host": {"cpu": cpu_model(), "logical_cpus": os.cpu_count()},
     }
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def batched_leg(perc, workloads, stream):
