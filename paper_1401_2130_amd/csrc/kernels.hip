@@ -1168,6 +1168,7 @@ __device__ __forceinline__ T block_scan(T v, T* tot, T* all) {
 __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) {
     __shared__ int32_t keep_s[kMaxBlock / 64];
     __shared__ int64_t chunk_s[kMaxBlock / 64];
+    __shared__ int64_t chunk2_s[kMaxBlock / 64];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int n_act = first ? a.n_slot : a.hdr[0];
     const int per = (n_act + nt - 1) / nt;
@@ -1222,6 +1223,27 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
     int64_t n_chunks;
     int32_t kpos = block_scan(keep, keep_s, &n_keep) - keep;
     int64_t cpos = block_scan(chunks, chunk_s, &n_chunks) - chunks;
+    // A work list shorter than what the device runs at once (the last, slowest
+    // configurations of a batch): items of a half, a quarter or an eighth of the depth
+    // (whole octets of cells), as long as the list stays within that size, so that the
+    // walks spread over more workgroups. Results do not depend on the item depth.
+    int Eu = E;
+    if (!a.fused && a.resident > 0 && n_chunks > 0) {
+        int f = 1;
+        while (f < 8 && E / (2 * f) >= 8 && n_chunks * (2 * f) <= (int64_t)a.resident) f *= 2;
+        if (f > 1) {
+            Eu = (E / f) & ~7;
+            chunks = 0;
+            for (int i = i0; i < i1; ++i) {
+                const int b = first ? i : a.active[i];
+                const CfgState s = a.st[b];
+                if (s.done) continue;
+                const DevShape& sh = a.shapes[a.slot_shape[b]];
+                chunks += items_of(sh, min(sh.U, s.front + (a.pair ? 3 : 2)), Eu);
+            }
+            cpos = block_scan(chunks, chunk2_s, &n_chunks) - chunks;
+        }
+    }
     unsigned long long tubes = 0;
     for (int i = i0; i < i1; ++i) {
         const int b = first ? i : a.active[i];
@@ -1231,7 +1253,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         a.active2[kpos] = b;
         a.chunk_off[kpos] = cpos;
         kpos += 1;
-        cpos += items_of(sh, min(sh.U, s.front + (a.fused || a.pair ? 3 : 2)), E);
+        cpos += items_of(sh, min(sh.U, s.front + (a.fused || a.pair ? 3 : 2)), Eu);
         // tube slots advanced by one step each; two steps per plan count the window twice
         tubes += (unsigned long long)min(sh.U, s.front + 2) * (unsigned long long)sh.C * (a.fused || a.pair ? 2ull : 1ull);
     }
@@ -1242,6 +1264,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         a.chunk_off[n_keep] = n_chunks;
         a.hdr[0] = n_keep;
         a.hdr[1] = (int32_t)min(n_chunks, (int64_t)INT32_MAX);
+        a.hdr[5] = Eu;
     }
 }
 
@@ -1250,7 +1273,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step(SpanArgs a) {
     const Tail tl = lds_tail(a.lds);
     fill_codes(tl.ct);
     const int n_act = uniform_i32(a.hdr);
-    const int E = a.depth;
+    const int E = uniform_i32(a.hdr + 5);  // the planned cells per item
     const ItemRange it = my_items(uniform_i32(a.hdr + 1));
     if (it.begin >= it.end) return;
     int lo = find_entry(a.chunk_off, n_act, it.begin);
@@ -1585,6 +1608,14 @@ hipError_t prepare_kernels(int device) {
     if (e == hipSuccess) e = allow_lds(k_chunk_step);
     if (e == hipSuccess) e = allow_lds(k_persist);
     return e;
+}
+
+int32_t span_step_resident(int32_t block, int32_t lds) {
+    int n = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_span_step, block, lds) != hipSuccess) return 0;
+    return n * cus;
 }
 
 int persist_resident_per_cu(int block, int lds_bytes) {

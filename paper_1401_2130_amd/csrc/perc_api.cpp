@@ -516,6 +516,8 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
         a.block = tu.block;
         a.grid = tu.grid ? tu.grid : kSpanGrid;
         a.lds = lds;
+        // the planner shortens the items of work lists smaller than the device holds
+        a.resident = fused ? 0 : span_step_resident(a.block, a.lds);
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.hdr), 16, 0u, s));
         if (boff) HIP_TRY(launch_sample_slots(d_shapes, d_jobs, nb, d_bits, s));
         HIP_TRY(launch_span_init(a, s));
@@ -1049,6 +1051,7 @@ int server_init(perc_server* v, const perc_server_config* cfg, hipStream_t s) {
     a.block = tu.block;
     a.grid = tu.grid ? tu.grid : kSpanGrid;
     a.lds = (int)lds_total(nd.span_max);
+    a.resident = span_step_resident(a.block, a.lds);
     // an even tick runs pairs of step launches between plans
     a.pair = (kSpanPairs && v->cfg.tick_steps % 2 == 0) ? 1 : 0;
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.hdr), 16, 0u, s));

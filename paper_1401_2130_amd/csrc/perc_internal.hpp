@@ -258,7 +258,8 @@ struct SpanArgs {
     int32_t* active;           // [n_slot] active slots
     int32_t* active2;          // scratch for compaction
     int64_t* chunk_off;        // [n_slot + 1] prefix sums of items per active slot
-    int32_t* hdr;              // [16]: n_active, total items, error flag, finished count
+    int32_t* hdr;              // [16]: n_active, total items, error flag, finished count, -,
+                               // cells per item of the planned step (the planner's choice)
     unsigned long long* work;  // tube slots scheduled over all steps (planner adds)
     BatchOut out;
     const int32_t* ids;        // slots to initialise (null: all n_slot)
@@ -275,7 +276,14 @@ struct SpanArgs {
     int32_t r1_off;            // two-step form: LDS word offset of the inner ring
     float* far1;               // two-step form: [n_slot][far1_stride] first-step far-end words
     int32_t far1_stride;
+    int32_t resident;          // step-kernel workgroups the device holds at once (0: items
+                               // always `depth` cells; else the planner shortens the items of
+                               // short work lists so that they spread over the device)
 };
+
+// Workgroups of k_span_step with this block size and dynamic LDS that the current device
+// runs at once (0 if the runtime cannot tell).
+int32_t span_step_resident(int32_t block, int32_t lds);
 
 hipError_t launch_span_init(const SpanArgs& a, hipStream_t s);       // codes, y0, first plan
 hipError_t launch_span_init_only(const SpanArgs& a, hipStream_t s);  // codes and y0 only
