@@ -380,3 +380,32 @@ def test_philox_output_uniform():
     b = oracle.philox4x32_10([1, 0, 0, 0], [0, 0])
     c = oracle.philox4x32_10([0, 0, 0, 0], [1, 0])
     assert not np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_philox_key_schedule_shift():
+    """Pins the round count and key schedule of the oracle's Philox4x32-10 (Salmon et
+    al., SC'11) against the closed forms of the published Weyl increments,
+    w0 = floor(2^32 (phi - 1)) and w1 = floor(2^32 (sqrt(3) - 1)): ten rounds f with keys
+    k, k + w, ..., k + 9w satisfy round_{k+10w}(f(c, k)) == f(round_k(c), k + w). A wrong
+    increment, a wrong round count or a key bumped at the wrong place breaks it."""
+    w0 = math.isqrt(5 << 62) - (1 << 31)  # 2^31 (sqrt 5 - 1)
+    w1 = math.isqrt(3 << 64) - (1 << 32)  # 2^32 (sqrt 3 - 1)
+    m32 = 0xFFFFFFFF
+
+    def rnd(c, k):  # one Philox4x32 round (the published multipliers)
+        p0 = 0xD2511F53 * int(c[0])
+        p1 = 0xCD9E8D57 * int(c[2])
+        return [((p1 >> 32) ^ int(c[1]) ^ k[0]) & m32, p1 & m32, ((p0 >> 32) ^ int(c[3]) ^ k[1]) & m32, p0 & m32]
+
+    def bump(k, n):
+        return [(k[0] + n * w0) & m32, (k[1] + n * w1) & m32]
+
+    rng = np.random.default_rng(17)
+    for _ in range(64):
+        c = [int(x) for x in rng.integers(0, 1 << 32, size=4, dtype=np.uint64)]
+        k = [int(x) for x in rng.integers(0, 1 << 32, size=2, dtype=np.uint64)]
+        lhs = rnd(oracle.philox4x32_10(c, k), bump(k, 10))
+        rhs = [int(x) for x in oracle.philox4x32_10(rnd(c, k), bump(k, 1))]
+        assert lhs == rhs
+        # the identity discriminates: nine increments do not satisfy it
+        assert rnd(oracle.philox4x32_10(c, k), bump(k, 9)) != rhs
