@@ -244,7 +244,9 @@ typedef struct perc_profile {
 
 /* Process-wide switch; resets the counters. While on, the span form launches its steps
  * directly (HIP reports no elapsed time for events recorded as graph nodes) with an
- * event pair around each step launch, on the caller's stream; the persistent form times
+ * event pair around each step launch, or around each pair of step launches that run
+ * back to back between two plans (counted as two launches), on the caller's stream; the
+ * persistent form times
  * its one launch (sampling, initialisation and finishing included, so its rate is a
  * lower bound) and counts the tube slots of its steps, and runs synchronously. */
 int perc_profile_enable(int32_t on);
