@@ -71,3 +71,38 @@ def test_uneven_workload_counts(perc):
         for p in wl.ps:
             pb, _ = ref.inspect_bfs(ref.sample(p, wl.seed, wl.n_cfg))
             assert counts[(W, L, float(p))] == int(pb.sum()), (W, L, p)
+
+
+def test_profiler_counts_and_results(perc):
+    """The step profiler (perc_profile_*): a profiled batch launches its steps directly and
+    gives the bits, steps and FP32 first-hit probabilities of the graph-replayed batch;
+    the span form's launches come in pairs, the timed milliseconds are positive, and the
+    tube slots it counts lie between what the configurations' step counts allow."""
+    import numpy as np
+    from paper_1401_2130_amd import workloads
+
+    W, L = 6, 40
+    lat = perc.Lattice(W, L)
+    occ = workloads.random_occupancy(lat.n, 160, 0.34, 91)
+    d_occ = torch.from_numpy(np.ascontiguousarray(occ).view(np.int32)).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        p0, s0, h0 = perc.perc_inspect_ex(lat, d_occ, hit=True, form="span", depth=8, stream=s)
+        s.synchronize()
+        perc.perc_profile_enable(True)
+        try:
+            p1, s1, h1 = perc.perc_inspect_ex(lat, d_occ, hit=True, form="span", depth=8, stream=s)
+            s.synchronize()
+            prof = perc.perc_profile_read()
+        finally:
+            perc.perc_profile_enable(False)
+    np.testing.assert_array_equal(p0.cpu().numpy(), p1.cpu().numpy())
+    np.testing.assert_array_equal(s0.cpu().numpy(), s1.cpu().numpy())
+    np.testing.assert_array_equal(h0.cpu().numpy().view(np.uint32), h1.cpu().numpy().view(np.uint32))
+    assert prof["step_launches"] > 0 and prof["step_launches"] % 2 == 0
+    assert prof["step_ms"] > 0.0
+    steps = s1.cpu().numpy().astype(np.int64)
+    U, C = (L + 2) // 3, lat.columns
+    lo = int(np.sum(np.maximum(steps - 1, 0))) * min(U, 2) * C
+    hi = int(np.sum(steps + 2)) * U * C
+    assert lo <= prof["tube_steps"] <= hi, (lo, prof["tube_steps"], hi)
