@@ -61,7 +61,9 @@ enum {
                               one launch per step over a device-built work list, replayed
                               as a HIP graph */
     PERC_FORM_PERSIST = 3, /* one workgroup per configuration pulled from a device queue;
-                              the whole inspection (sampling included) in one launch */
+                              the whole inspection (sampling included) in one launch;
+                              it reports PERC_ECAP from the synchronous calls only
+                              (perc_pi, perc_pi_ex, perc_batch with groups) */
     PERC_FORM_SPAN2 = 4    /* the span form advancing two steps per launch: the first step
                               of a tile's halo range is kept in LDS and the second is
                               computed from it, one pass over the state per two steps.
@@ -83,9 +85,10 @@ typedef struct perc_lattice perc_lattice;
 
 /* ---- lattice (Sec. II.A, Fig. 1) ------------------------------------------------ */
 
-/* Build the fiber lattice of hex radius W >= 0 and L >= 1 layers. Returns NULL on a
- * bad argument or more than 2^31-1 sites. Owned by the caller; immutable; safe to use
- * from several threads and streams at once. */
+/* Build the fiber lattice of hex radius 0 <= W <= 1024 and 1 <= L <= 65535 layers
+ * (the sampler's stream tag W<<16 | L is then distinct for every shape). Returns NULL
+ * on a bad argument or more than 2^31-1 sites. Owned by the caller; immutable; safe to
+ * use from several threads and streams at once. */
 perc_lattice* perc_lattice_create(int32_t W, int32_t L);
 
 /* As perc_lattice_create with options: PERC_LATTICE_NO_END_CONTACTS drops the two end
@@ -281,6 +284,11 @@ typedef struct perc_server_config {
     int32_t host_only;   /* 1: no GPU work, every admitted request completes at the next
                             tick with status PERC_OK and zero outputs (scheduler tests) */
     perc_options opt;    /* item length (depth), block, grid of the step launches */
+    int32_t max_queue;   /* requests that may wait at once (0: 2^20); a submit beyond it
+                            is refused with PERC_EBUSY (load shedding) */
+    int32_t lookahead;   /* admission: 0 = strict FIFO (a request that does not fit waits,
+                            and so do the ones behind it); k > 0 = the first k requests
+                            behind a waiting head may be admitted past it when they fit */
 } perc_server_config;
 
 typedef struct perc_result {
@@ -288,7 +296,9 @@ typedef struct perc_result {
     int32_t W, L;
     double p;
     uint64_t seed, cfg;
-    int32_t status;      /* PERC_OK, or PERC_ECAP if the step cap was reached */
+    int32_t status;      /* PERC_OK; PERC_ECAP if the step cap was reached; PERC_ECANCELED
+                            (perc_server_cancel); PERC_EBUSY (refused by perc_server_run's
+                            submit: queue full) */
     uint8_t perc;        /* percolates */
     int32_t steps;       /* as perc_inspect */
     float hit;           /* first-hit probability at the stop (0 if not percolating) */
@@ -298,6 +308,8 @@ typedef struct perc_result {
 typedef struct perc_server_stats {
     int64_t queued, in_flight, completed, ticks;
     int64_t pool_bytes, pool_used_bytes;
+    int64_t rejected;    /* submits refused with PERC_EBUSY */
+    int64_t cancelled;   /* requests retired with PERC_ECANCELED */
 } perc_server_stats;
 
 /* Create a server on the current device, working on `stream` (hipStream_t or NULL); the
@@ -307,15 +319,23 @@ perc_server* perc_server_create(const perc_server_config* cfg, void* stream);
 void perc_server_destroy(perc_server* srv);
 
 /* Queue one request; t_arrive_ns < 0 stamps the current steady-clock time. PERC_EINVAL
- * for W outside [0, max_w], L outside [1, 2^22], p outside [0, 1], or a request whose
- * resident state would exceed the pool. */
+ * for W outside [0, max_w], L outside [1, 65535] or p outside [0, 1]; PERC_EBUSY (not
+ * queued) when max_queue requests already wait, or when the request's resident state
+ * exceeds the whole pool (it could never be admitted). */
 int perc_server_submit(perc_server* srv, int32_t W, int32_t L, double p, uint64_t seed, uint64_t cfg, uint64_t tag,
                        int64_t t_arrive_ns);
 
-/* One tick: admit queued requests (FIFO; a request that does not fit waits, and so do
- * the ones behind it), sample and initialise them, advance every resident inspection by
- * tick_steps steps, retire the finished ones. Returns the number retired (>= 0) or an
- * error. Synchronous. */
+/* Cancel every request with this tag: a waiting one leaves the queue at once, one in
+ * flight stops at the next tick (its slot and pool room are freed then). Each cancelled
+ * request is retired with status PERC_ECANCELED and zero outputs (poll returns it).
+ * Returns the number of requests cancelled (>= 0; 0 if none had the tag, or all had
+ * already finished). */
+int perc_server_cancel(perc_server* srv, uint64_t tag);
+
+/* One tick: admit queued requests (in queue order, as lookahead allows, while a slot and
+ * pool room are free), sample and initialise them, advance every resident inspection by
+ * tick_steps steps, retire the finished and the cancelled ones. Returns the number
+ * retired (>= 0) or an error. Synchronous. */
 int perc_server_tick(perc_server* srv);
 
 /* Move up to max finished results (retirement order) into out; returns the count. */
@@ -325,7 +345,8 @@ int perc_server_stats_read(const perc_server* srv, perc_server_stats* out);
 /* Serve a whole request stream natively: request i arrives t_arrive_ns[i] after the
  * start (non-decreasing); the loop submits arrivals as their time comes, ticks while
  * anything is queued or in flight, sleeps otherwise, and writes the n results (in
- * retirement order, t_arrive_ns on the same clock as t_done_ns) to out. */
+ * retirement order, t_arrive_ns on the same clock as t_done_ns) to out. A request the
+ * queue refuses (PERC_EBUSY at submit) gets a result with that status at once. */
 typedef struct perc_request {
     int64_t t_arrive_ns;
     int32_t W, L;

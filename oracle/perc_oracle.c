@@ -107,7 +107,8 @@ void orc_lattice_free(orc_lattice *lat) {
  * the regular FCC lattice of the same sites (12 side contacts only), the reference
  * lattice the paper compares its threshold with (Sec. III). Surfaces are the same. */
 orc_lattice *orc_lattice_new_ex(int W, int L, int ends) {
-    if (W < 0 || L < 1 || W > 4096 || L > (1 << 20)) return NULL;
+    /* L < 2^16 and W <= 1024: the Philox stream tag W<<16 | L names one shape only */
+    if (W < 0 || L < 1 || W > 1024 || L > 65535) return NULL;
     orc_lattice *lat = (orc_lattice *)calloc(1, sizeof(orc_lattice));
     if (!lat) return NULL;
     lat->W = W; lat->L = L;

@@ -49,7 +49,7 @@ class perc_job(C.Structure):
 
 class perc_server_config(C.Structure):
     _fields_ = [("hbm_bytes", C.c_int64), ("max_slots", C.c_int32), ("tick_steps", C.c_int32), ("max_w", C.c_int32),
-                ("host_only", C.c_int32), ("opt", perc_options)]
+                ("host_only", C.c_int32), ("opt", perc_options), ("max_queue", C.c_int32), ("lookahead", C.c_int32)]
 
 
 class perc_result(C.Structure):
@@ -60,7 +60,8 @@ class perc_result(C.Structure):
 
 class perc_server_stats(C.Structure):
     _fields_ = [("queued", C.c_int64), ("in_flight", C.c_int64), ("completed", C.c_int64), ("ticks", C.c_int64),
-                ("pool_bytes", C.c_int64), ("pool_used_bytes", C.c_int64)]
+                ("pool_bytes", C.c_int64), ("pool_used_bytes", C.c_int64), ("rejected", C.c_int64),
+                ("cancelled", C.c_int64)]
 
 
 class perc_request(C.Structure):
@@ -110,6 +111,7 @@ def _load():
     lib.perc_server_create.argtypes = [C.POINTER(perc_server_config), vp]
     lib.perc_server_destroy.argtypes = [vp]
     lib.perc_server_submit.argtypes = [vp, i32, i32, dbl, C.c_uint64, C.c_uint64, C.c_uint64, i64]
+    lib.perc_server_cancel.argtypes = [vp, C.c_uint64]
     lib.perc_server_tick.argtypes = [vp]
     lib.perc_server_poll.argtypes = [vp, C.POINTER(perc_result), i32]
     lib.perc_server_stats_read.argtypes = [vp, C.POINTER(perc_server_stats)]
@@ -124,7 +126,7 @@ EXPORTED = ("perc_lattice_create", "perc_lattice_create_ex", "perc_lattice_destr
             "perc_last_error", "perc_sample", "perc_sample_fixed", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
             "perc_batch", "perc_state_after", "perc_first_passage", "perc_first_passage_batch", "perc_steps_hist", "perc_profile_enable", "perc_profile_read", "perc_autotune",
             "perc_server_create",
-            "perc_server_destroy", "perc_server_submit", "perc_server_tick", "perc_server_poll",
+            "perc_server_destroy", "perc_server_submit", "perc_server_cancel", "perc_server_tick", "perc_server_poll",
             "perc_server_stats_read", "perc_server_run")
 
 
@@ -428,9 +430,10 @@ class perc_server:
     together, a tick at a time; the state of every admitted request stays on the GPU."""
 
     def __init__(self, hbm_bytes: int = 0, max_slots: int = 0, tick_steps: int = 0, max_w: int = 0,
-                 host_only: bool = False, depth: int = 0, block: int = 0, grid: int = 0, stream=None):
+                 host_only: bool = False, depth: int = 0, block: int = 0, grid: int = 0, max_queue: int = 0,
+                 lookahead: int = 0, stream=None):
         cfg = perc_server_config(int(hbm_bytes), int(max_slots), int(tick_steps), int(max_w), 1 if host_only else 0,
-                                 _options("span", depth, block, grid, 0))
+                                 _options("span", depth, block, grid, 0), int(max_queue), int(lookahead))
         self._lib = _lib
         self._stream = stream  # the server works on this stream; keep it alive as long
         self.handle = _lib.perc_server_create(C.byref(cfg), None if host_only else _stream(stream))
@@ -446,6 +449,14 @@ class perc_server:
     def submit(self, W: int, L: int, p: float, seed: int, cfg: int = 0, tag: int = 0, t_arrive_ns: int = -1):
         _check(_lib.perc_server_submit(self.handle, int(W), int(L), float(p), int(seed), int(cfg), int(tag),
                                        int(t_arrive_ns)))
+
+    def cancel(self, tag: int) -> int:
+        """Cancel the requests with this tag (queued: at once; in flight: at the next
+        tick); returns how many were cancelled."""
+        rc = _lib.perc_server_cancel(self.handle, int(tag))
+        if rc < 0:
+            _check(rc)
+        return rc
 
     def tick(self) -> int:
         rc = _lib.perc_server_tick(self.handle)

@@ -1183,6 +1183,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         const uint32_t f = s.flags, f2 = s.flags2;
         s.flags = 0;
         s.flags2 = 0;
+        if (s.done) {  // cancelled by the host: leaves the work list without a decision
+            a.st[b] = s;
+            continue;
+        }
         int dec = -1;  // -1 continue, 0 no, 1 yes
         int32_t steps = 0;
         if (s.m < 0) {

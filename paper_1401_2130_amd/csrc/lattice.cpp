@@ -149,7 +149,8 @@ std::shared_ptr<const ColumnSet> column_set(int32_t W, std::string& err) {
 
 bool build_lattice(int32_t W, int32_t L, LatticeDesc& d, std::string& err) {
     if (W < 0 || W > 1024) { err = "W must be in [0, 1024]"; return false; }
-    if (L < 1 || L > (1 << 22)) { err = "L must be in [1, 4194304]"; return false; }
+    // L < 2^16 keeps the sampler's stream tag (W << 16) | L distinct for every shape
+    if (L < 1 || L > 65535) { err = "L must be in [1, 65535]"; return false; }
     d = LatticeDesc{};
     d.cs = column_set(W, err);
     if (!d.cs) return false;

@@ -641,7 +641,8 @@ int run_persist(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out,
     Job* d_jobs = ar.take<Job>(n);
     DevShape* d_shapes = ar.take<DevShape>(S.dev.size());
     a.queue = ar.take<unsigned long long>(3);
-    a.err = reinterpret_cast<uint32_t*>(a.queue + 1);
+    // the cap flag goes to the caller's word when it has one (a synchronous call reads it)
+    a.err = out.cap ? out.cap : reinterpret_cast<uint32_t*>(a.queue + 1);
     const bool prof = profiling();
     if (prof) a.work = a.queue + 2;
     HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
@@ -741,17 +742,20 @@ int pi_impl(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, per
     bo.perc = out->bits ? out->bits : ar.take<uint8_t>(n_cfg);
     bo.steps = out->steps ? out->steps : ar.take<int32_t>(n_cfg);
     bo.hit = out->hit;
-    unsigned long long* count = ar.take<unsigned long long>(1);
+    // [0]: percolating count, [1]: step-cap flag of the persistent form
+    unsigned long long* count = ar.take<unsigned long long>(2);
+    bo.cap = reinterpret_cast<uint32_t*>(count + 1);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(count), 4, 0u, s));
     std::vector<HostJob> jobs(n_cfg);
     for (int64_t i = 0; i < n_cfg; ++i) jobs[i] = HostJob{lat, nullptr, seed, (uint64_t)i, thr, -1};
     PERC_TRY(run_jobs(jobs, bo, opt, s));
-    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(count), 2, 0u, s));
     HIP_TRY(launch_count(bo.perc, n_cfg, count, s));
-    unsigned long long host_count = 0;
-    HIP_TRY(hipMemcpyAsync(&host_count, count, sizeof(host_count), hipMemcpyDeviceToHost, s));
+    unsigned long long host_count[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(host_count, count, sizeof(host_count), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    out->n_perc = (int64_t)host_count;
-    out->pi = (double)host_count / (double)n_cfg;
+    if (host_count[1]) return fail(PERC_ECAP, "a configuration reached the step cap");
+    out->n_perc = (int64_t)host_count[0];
+    out->pi = (double)host_count[0] / (double)n_cfg;
     return PERC_OK;
 }
 
@@ -892,7 +896,8 @@ struct ServerSlot {
     perc_result res{};
     int64_t state_off = 0, state_words = 0, bits_off = 0, bits_n = 0;
     int32_t shape = -1;
-    int64_t seq = 0;  // admission order
+    int64_t seq = 0;      // admission order
+    bool cancel = false;  // cancelled while in flight: retired at the next tick
 };
 
 }  // namespace
@@ -942,7 +947,7 @@ struct perc_server {
     std::deque<perc_result> queue;
     std::deque<perc_result> done;
     int32_t n_act = 0;
-    int64_t ticks = 0, completed = 0, admitted = 0;
+    int64_t ticks = 0, completed = 0, admitted = 0, rejected = 0, cancelled = 0;
     hipGraphExec_t exec = nullptr;
 };
 
@@ -971,6 +976,8 @@ int server_init(perc_server* v, const perc_server_config* cfg, hipStream_t s) {
     if (c.max_slots <= 0) c.max_slots = 1024;
     if (c.tick_steps <= 0) c.tick_steps = 16;
     if (c.max_w <= 0) c.max_w = 64;
+    if (c.max_queue <= 0) c.max_queue = 1 << 20;
+    if (c.lookahead < 0) return fail(PERC_EINVAL, "lookahead must be >= 0");
     if (c.max_slots > (1 << 20)) return fail(PERC_EINVAL, "max_slots must be <= 2^20");
     if (c.tick_steps > 4096) return fail(PERC_EINVAL, "tick_steps must be <= 4096");
     if (c.max_w > kServerMaxW) return fail(PERC_EINVAL, "max_w must be <= 128");
@@ -1119,30 +1126,44 @@ void server_unshape(perc_server* v, int32_t idx, int32_t W, int32_t L) {
 void server_retire(perc_server* v, int32_t b, int64_t now) {
     ServerSlot& sl = v->slots[b];
     sl.res.t_done_ns = now;
+    if (sl.cancel) {
+        sl.res.status = PERC_ECANCELED;
+        sl.res.perc = 0;
+        sl.res.steps = 0;
+        sl.res.hit = 0.0f;
+        v->cancelled += 1;
+    } else {
+        v->completed += 1;
+    }
     v->done.push_back(sl.res);
     v->state_alloc.release(sl.state_off, sl.state_words);
     v->bits_alloc.release(sl.bits_off, sl.bits_n);
     server_unshape(v, sl.shape, sl.res.W, sl.res.L);
     sl.busy = false;
+    sl.cancel = false;
     v->free_slots.push_back(b);
-    v->completed += 1;
 }
 
-// Admit queued requests in FIFO order while a slot and pool room are free.
+// Admit queued requests in queue order while a slot and pool room are free; a request
+// that does not fit is passed over only while at most `lookahead` have been (0: strict
+// FIFO, the first one that does not fit stops admission).
 int server_admit(perc_server* v, std::vector<int32_t>& new_ids) {
     const int64_t now = steady_ns();
-    while (!v->queue.empty() && !v->free_slots.empty()) {
-        const perc_result& r = v->queue.front();
+    int64_t passed = 0;
+    auto it = v->queue.begin();
+    while (it != v->queue.end() && !v->free_slots.empty()) {
+        const perc_result& r = *it;
         LatticeDesc d;
         std::string err;
         if (!build_lattice(r.W, r.L, d, err)) return fail(PERC_EINVAL, err);
         const int64_t sw = slot_words(d), bw = server_bits_words(d);
         const int64_t so = v->state_alloc.alloc(sw);
-        if (so < 0) break;
-        const int64_t bo = v->bits_alloc.alloc(bw);
+        const int64_t bo = so < 0 ? -1 : v->bits_alloc.alloc(bw);
+        if (so >= 0 && bo < 0) v->state_alloc.release(so, sw);
         if (bo < 0) {
-            v->state_alloc.release(so, sw);
-            break;
+            if (++passed > v->cfg.lookahead) break;
+            ++it;
+            continue;
         }
         int32_t idx = -1;
         PERC_TRY(server_shape(v, d, idx));
@@ -1158,7 +1179,8 @@ int server_admit(perc_server* v, std::vector<int32_t>& new_ids) {
         sl.bits_n = bw;
         sl.shape = idx;
         sl.seq = v->admitted++;
-        v->queue.pop_front();
+        sl.cancel = false;
+        it = v->queue.erase(it);
         v->h_slot_shape[b] = idx;
         v->h_slot_off[b] = so;
         v->h_slot_bits[b] = v->bits ? v->bits + bo : nullptr;
@@ -1177,7 +1199,8 @@ int server_tick(perc_server* v) {
         std::vector<std::pair<int64_t, int32_t>> fin;
         for (int32_t b = 0; b < (int32_t)v->slots.size(); ++b) {
             const ServerSlot& sl = v->slots[b];
-            if (sl.busy && std::find(new_ids.begin(), new_ids.end(), b) == new_ids.end()) fin.emplace_back(sl.seq, b);
+            if (sl.busy && (sl.cancel || std::find(new_ids.begin(), new_ids.end(), b) == new_ids.end()))
+                fin.emplace_back(sl.seq, b);
         }
         std::sort(fin.begin(), fin.end());
         const int64_t now = steady_ns();
@@ -1273,6 +1296,13 @@ int server_tick(perc_server* v) {
         sl.res.status = v->h_st[b].done == 2 ? PERC_ECAP : PERC_OK;
         server_retire(v, b, now);
     }
+    // slots cancelled in flight: the planner of this tick dropped them from the work list
+    int32_t ncan = 0;
+    for (int32_t b = 0; b < M; ++b)
+        if (v->slots[b].busy && v->slots[b].cancel) {
+            server_retire(v, b, now);
+            ++ncan;
+        }
     v->n_act = v->h_hdr[0];
     if (nfin > 0 || cap) {
         v->h_hdr[2] = 0;
@@ -1280,7 +1310,7 @@ int server_tick(perc_server* v) {
         HIP_TRY(hipMemcpyAsync(a.hdr + 2, v->h_hdr + 2, 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
-    return nfin;
+    return nfin + ncan;
 }
 
 int server_submit(perc_server* v, int32_t W, int32_t L, double p, uint64_t seed, uint64_t cfg, uint64_t tag,
@@ -1290,8 +1320,14 @@ int server_submit(perc_server* v, int32_t W, int32_t L, double p, uint64_t seed,
     LatticeDesc d;
     std::string err;
     if (!build_lattice(W, L, d, err)) return fail(PERC_EINVAL, err);
-    if (slot_words(d) > v->state_cap || server_bits_words(d) > v->bits_cap)
-        return fail(PERC_EINVAL, "the request's resident state exceeds the server pool");
+    if (slot_words(d) > v->state_cap || server_bits_words(d) > v->bits_cap) {
+        v->rejected += 1;
+        return fail(PERC_EBUSY, "the request's resident state exceeds the server pool");
+    }
+    if ((int64_t)v->queue.size() >= v->cfg.max_queue) {
+        v->rejected += 1;
+        return fail(PERC_EBUSY, "the request queue is full");
+    }
     perc_result r{};
     r.tag = tag;
     r.W = W;
@@ -1302,6 +1338,38 @@ int server_submit(perc_server* v, int32_t W, int32_t L, double p, uint64_t seed,
     r.t_arrive_ns = t_arrive >= 0 ? t_arrive : steady_ns();
     v->queue.push_back(r);
     return PERC_OK;
+}
+
+int server_cancel(perc_server* v, uint64_t tag) {
+    int n = 0;
+    const int64_t now = steady_ns();
+    for (auto it = v->queue.begin(); it != v->queue.end();) {
+        if (it->tag != tag) {
+            ++it;
+            continue;
+        }
+        perc_result r = *it;
+        r.status = PERC_ECANCELED;
+        r.t_admit_ns = now;
+        r.t_done_ns = now;
+        v->done.push_back(r);
+        v->cancelled += 1;
+        it = v->queue.erase(it);
+        ++n;
+    }
+    for (int32_t b = 0; b < (int32_t)v->slots.size(); ++b) {
+        ServerSlot& sl = v->slots[b];
+        if (!sl.busy || sl.cancel || sl.res.tag != tag) continue;
+        sl.cancel = true;
+        ++n;
+        if (v->host_only) continue;
+        // between ticks no device work is in flight and the slot is undecided; marking it
+        // done makes the next planner drop it from the work list without a decision
+        static const int32_t kCancelled = 5;
+        HIP_TRY(hipMemcpyAsync(&v->a.st[b].done, &kCancelled, sizeof(int32_t), hipMemcpyHostToDevice, v->s));
+    }
+    if (n && !v->host_only) HIP_TRY(hipStreamSynchronize(v->s));
+    return n;
 }
 
 // Work buffers of the single-configuration entry points: the codes of occ_bits and its
@@ -1543,22 +1611,26 @@ int perc_batch(const perc_job* jobs, int64_t n_jobs, uint8_t* perc, int32_t* ste
     PERC_TRY(convert_jobs(jobs, n_jobs, n_groups, hj));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Arena ar;
-    PERC_TRY(ar.reserve(Arena::align(sizeof(int32_t) * n_jobs) + Arena::align(8 * (size_t)std::max(n_groups, 1)), s));
+    PERC_TRY(ar.reserve(Arena::align(sizeof(int32_t) * n_jobs) + Arena::align(8 * (size_t)(n_groups + 1)), s));
     BatchOut out;
     out.perc = perc;
     int32_t* own_steps = ar.take<int32_t>(n_jobs);
     out.steps = steps ? steps : own_steps;
     out.hit = hit;
-    unsigned long long* d_groups = ar.take<unsigned long long>(std::max(n_groups, 1));
+    // the group counts, then the step-cap flag of the persistent form (read when the call
+    // is synchronous)
+    unsigned long long* d_groups = ar.take<unsigned long long>(n_groups + 1);
     if (n_groups > 0) {
-        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_groups), 2 * (int64_t)n_groups, 0u, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_groups), 2 * (int64_t)(n_groups + 1), 0u, s));
         out.group_count = d_groups;
+        out.cap = reinterpret_cast<uint32_t*>(d_groups + n_groups);
     }
     PERC_TRY(run_jobs(hj, out, opt, s));
     if (n_groups > 0) {
-        std::vector<unsigned long long> h(n_groups);
-        HIP_TRY(hipMemcpyAsync(h.data(), d_groups, 8 * (size_t)n_groups, hipMemcpyDeviceToHost, s));
+        std::vector<unsigned long long> h(n_groups + 1);
+        HIP_TRY(hipMemcpyAsync(h.data(), d_groups, 8 * (size_t)(n_groups + 1), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (h[n_groups]) return fail(PERC_ECAP, "a configuration reached the step cap");
         for (int32_t g = 0; g < n_groups; ++g) group_count[g] = (int64_t)h[g];
     }
     return PERC_OK;
@@ -1643,6 +1715,11 @@ int perc_server_submit(perc_server* srv, int32_t W, int32_t L, double p, uint64_
     return server_submit(srv, W, L, p, seed, cfg, tag, t_arrive_ns);
 }
 
+int perc_server_cancel(perc_server* srv, uint64_t tag) {
+    if (!srv) return fail(PERC_EINVAL, "server is NULL");
+    return server_cancel(srv, tag);
+}
+
 int perc_server_tick(perc_server* srv) {
     if (!srv) return fail(PERC_EINVAL, "server is NULL");
     return server_tick(srv);
@@ -1666,6 +1743,8 @@ int perc_server_stats_read(const perc_server* srv, perc_server_stats* out) {
     out->ticks = srv->ticks;
     out->pool_bytes = srv->pool_bytes;
     out->pool_used_bytes = srv->state_alloc.used() * 9 + srv->bits_alloc.used() * 4;
+    out->rejected = srv->rejected;
+    out->cancelled = srv->cancelled;
     return PERC_OK;
 }
 
@@ -1679,11 +1758,32 @@ int perc_server_run(perc_server* srv, const perc_request* reqs, int64_t n, perc_
         const int64_t now = steady_ns();
         while (next < n && t0 + reqs[next].t_arrive_ns <= now) {
             const perc_request& q = reqs[next];
-            PERC_TRY(server_submit(srv, q.W, q.L, q.p, q.seed, q.cfg, q.tag, t0 + q.t_arrive_ns));
+            const int rc = server_submit(srv, q.W, q.L, q.p, q.seed, q.cfg, q.tag, t0 + q.t_arrive_ns);
+            if (rc == PERC_EBUSY) {  // shed: the result says so at once
+                perc_result r{};
+                r.tag = q.tag;
+                r.W = q.W;
+                r.L = q.L;
+                r.p = q.p;
+                r.seed = q.seed;
+                r.cfg = q.cfg;
+                r.status = PERC_EBUSY;
+                r.t_arrive_ns = t0 + q.t_arrive_ns;
+                r.t_admit_ns = r.t_done_ns = steady_ns();
+                out[got++] = r;
+            } else if (rc != PERC_OK) {
+                return rc;
+            }
             ++next;
+        }
+        if (got >= n) break;
+        while (!srv->done.empty() && got < n) {
+            out[got++] = srv->done.front();
+            srv->done.pop_front();
         }
         const bool idle = srv->queue.empty() && srv->free_slots.size() == srv->slots.size();
         if (idle) {
+            if (next >= n) break;  // every request was refused or retired
             if (next < n) {
                 std::this_thread::sleep_until(std::chrono::steady_clock::time_point(
                     std::chrono::nanoseconds(t0 + reqs[next].t_arrive_ns)));

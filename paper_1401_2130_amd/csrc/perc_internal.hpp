@@ -195,7 +195,8 @@ struct CfgState {
     int32_t done;     // 0 = active, 1 = decided, 2 = cap reached (error), 3 = decided with a
                       // detector hit after the first step of a two-step launch (the far-end
                       // words of that step are in SpanArgs::far1), 4 = the same after the
-                      // first launch of a pair (that state is in the buffer not named by par)
+                      // first launch of a pair (that state is in the buffer not named by par),
+                      // 5 = cancelled by the host (the planner drops it undecided)
     uint32_t flags;   // OR of the flags of the last launch (its first step); cleared by the planner
     uint32_t flags2;  // second-step flags of a two-step launch; cleared by the planner
     int32_t par;      // state buffer holding the newest state: 0 = ya, 1 = yb
@@ -216,6 +217,8 @@ struct BatchOut {
     float* hit = nullptr;                       // first-passage probability at the stop
     unsigned long long* group_count = nullptr;  // percolating count per job group
     const int32_t* group = nullptr;             // group of each slot (span form), or null
+    uint32_t* cap = nullptr;                    // persistent form: set to 1 when a configuration
+                                                // reached the step cap (nullable)
 };
 
 // A configuration to inspect: its shape, and either caller bits or a Philox draw.

@@ -46,7 +46,7 @@ def check_hit(hit_gpu, hit_ref, perc_ref, steps_ref):
     assert np.all(hit_gpu[perc_ref == 0] == 0.0)
 
 
-# (form, cells per work item); the library rounds up to a multiple of 16
+# (form, cells per work item); the library rounds up to a multiple of 8
 FORMS = [("plain", 8), ("span", 8), ("span", 5), ("span", 24), ("persist", 8), ("persist", 16), ("persist", 64),
          ("span2", 8), ("span2", 24), ("span2", 64)]
 

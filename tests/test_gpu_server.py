@@ -134,3 +134,40 @@ def test_serving_recipe_sample(perc):
         assert (r["perc"], r["steps"]) == (int(pb[0]), int(sb[0])), (tag, W, L, p, r)
         checked += 1
     assert checked >= 10
+
+
+def test_cancel_in_flight_and_queued(perc):
+    """Requests cancelled while queued or in flight retire with PERC_ECANCELED; the
+    planner drops the in-flight ones from the work list, their slots and pool room are
+    reused, and every other request still equals its inspection alone and the oracle."""
+    stream = torch.cuda.Stream()
+    srv = perc.perc_server(hbm_bytes=64 << 20, max_slots=4, tick_steps=4, max_w=8, lookahead=4, stream=stream)
+    # long inspections (percolating fibers of ~100 tubes along the axis) so that the
+    # cancelled ones are still in flight after the first tick
+    reqs = [(6, 300, 0.6, 21, i, i) for i in range(6)] + [(3, 40, 0.35, 22, i, 100 + i) for i in range(4)]
+    for (W, L, p, seed, cfg, tag) in reqs:
+        srv.submit(W, L, p, seed, cfg=cfg, tag=tag)
+    assert srv.tick() == 0
+    assert srv.stats()["in_flight"] == 4
+    assert srv.cancel(1) == 1 and srv.cancel(2) == 1  # in flight
+    assert srv.cancel(5) == 1                          # still queued
+    results = {}
+    for r in srv.poll():
+        results[r["tag"]] = r
+    # a request that arrives after the cancellations takes a freed slot
+    late = (6, 300, 0.6, 21, 40, 40)
+    srv.submit(*late[:4], cfg=late[4], tag=late[5])
+    for _ in range(2000):
+        srv.tick()
+        for r in srv.poll():
+            assert r["tag"] not in results
+            results[r["tag"]] = r
+        if len(results) == len(reqs) + 1:
+            break
+    assert sorted(results) == sorted([t for *_, t in reqs] + [40])
+    for t in (1, 2, 5):
+        assert results[t]["status"] == perc.PERC_ECANCELED
+    st = srv.stats()
+    assert st["cancelled"] == 3 and st["pool_used_bytes"] == 0 and st["in_flight"] == 0
+    kept = [q for q in reqs + [late] if q[5] not in (1, 2, 5)]
+    check_against_alone_and_oracle(perc, kept, results)

@@ -99,3 +99,18 @@ def test_invalid_arguments():
     assert lib.perc_inspect(lat.handle, None, 0, None, None, None) == perc.PERC_OK
     assert lib.perc_pi(lat.handle, 0.3, 0, 1, C.byref(out), None) == perc.PERC_OK
     assert out.n_perc == 0 and out.pi == 0.0
+
+
+def test_length_bound_keeps_stream_tags_distinct():
+    """L <= 65535 and W <= 1024 in both the product and the oracle, so the sampler's
+    stream tag W << 16 | L names one shape only (with L = 65536 allowed, (W=0, L=65537)
+    would share its stream with (W=1, L=1))."""
+    assert perc.Lattice(0, 65535).n == (65535 + 2) // 3
+    for W, L in [(0, 65536), (1, 1 << 20), (1025, 4)]:
+        with pytest.raises(perc.PercError) as e:
+            perc.Lattice(W, L)
+        assert e.value.code == perc.PERC_EINVAL
+        with pytest.raises(ValueError):
+            oracle.Lattice(W, L)
+    tags = {(W << 16) | L for W in (0, 1, 2, 1024) for L in (1, 2, 65535)}
+    assert len(tags) == 12

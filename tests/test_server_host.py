@@ -86,10 +86,89 @@ def test_invalid_requests():
         with pytest.raises(perc.PercError) as e:
             srv.submit(*args, seed=1)
         assert e.value.code == perc.PERC_EINVAL
-    with pytest.raises(perc.PercError):  # resident state larger than the whole pool
+    with pytest.raises(perc.PercError) as e:  # resident state larger than the whole pool
         srv.submit(16, 4000, 0.3, seed=1)
+    assert e.value.code == perc.PERC_EBUSY
+    assert srv.stats()["rejected"] == 1 and srv.stats()["queued"] == 0
     with pytest.raises(perc.PercError):
         perc.perc_server(max_slots=4, host_only=True)  # host-only needs an explicit pool size
+    with pytest.raises(perc.PercError):
+        perc.perc_server(hbm_bytes=1 << 22, lookahead=-1, host_only=True)
+
+
+def test_bounded_queue_sheds_load():
+    srv = perc.perc_server(hbm_bytes=1 << 26, max_slots=2, max_queue=3, host_only=True)
+    for i in range(3):
+        srv.submit(3, 12, 0.25, seed=1, cfg=i, tag=i)
+    with pytest.raises(perc.PercError) as e:
+        srv.submit(3, 12, 0.25, seed=1, cfg=3, tag=3)
+    assert e.value.code == perc.PERC_EBUSY
+    st = srv.stats()
+    assert st["queued"] == 3 and st["rejected"] == 1
+    srv.tick()  # two admitted: room in the queue again
+    srv.submit(3, 12, 0.25, seed=1, cfg=3, tag=3)
+    got = []
+    for _ in range(6):
+        srv.tick()
+        got += srv.poll()
+    assert sorted(r["tag"] for r in got) == [0, 1, 2, 3]
+    assert all(r["status"] == perc.PERC_OK for r in got)
+
+
+def test_run_loop_reports_shed_requests():
+    # all requests arrive at once; a queue of 4 and 2 slots refuse the rest
+    reqs = [(0.0, 3, 12, 0.25, 5, i, i) for i in range(20)]
+    srv = perc.perc_server(hbm_bytes=1 << 26, max_slots=2, max_queue=4, host_only=True)
+    res = srv.run(reqs)
+    assert sorted(r["tag"] for r in res) == list(range(20))
+    busy = [r for r in res if r["status"] == perc.PERC_EBUSY]
+    ok = [r for r in res if r["status"] == perc.PERC_OK]
+    assert len(busy) + len(ok) == 20 and len(ok) >= 4 and len(busy) >= 1
+    assert srv.stats()["rejected"] == len(busy)
+    assert all(r["t_done_ns"] >= r["t_arrive_ns"] for r in res)
+
+
+def test_cancel_queued_and_in_flight():
+    srv = perc.perc_server(hbm_bytes=1 << 26, max_slots=2, host_only=True)
+    for i in range(5):
+        srv.submit(3, 12, 0.25, seed=1, cfg=i, tag=10 + i)
+    assert srv.cancel(14) == 1  # still queued: retired at once
+    first = srv.poll()
+    assert [(r["tag"], r["status"]) for r in first] == [(14, perc.PERC_ECANCELED)]
+    assert srv.stats()["queued"] == 4
+    srv.tick()  # 10 and 11 admitted
+    assert srv.stats()["in_flight"] == 2
+    assert srv.cancel(11) == 1  # in flight: stops at the next tick
+    assert srv.cancel(11) == 0  # already cancelled
+    assert srv.cancel(999) == 0
+    got = []
+    for _ in range(6):
+        srv.tick()
+        got += srv.poll()
+    status = {r["tag"]: r["status"] for r in got}
+    assert status == {10: perc.PERC_OK, 11: perc.PERC_ECANCELED, 12: perc.PERC_OK, 13: perc.PERC_OK}
+    st = srv.stats()
+    assert st["cancelled"] == 2 and st["completed"] == 3 and st["pool_used_bytes"] == 0
+    assert all(r["perc"] == 0 and r["steps"] == 0 for r in got if r["status"] == perc.PERC_ECANCELED)
+
+
+def test_lookahead_admits_past_a_waiting_head():
+    """With lookahead 1 a small request behind a big one that does not fit yet is
+    admitted past it; with 0 (strict FIFO) it waits."""
+    big, _ = footprint(16, 300)
+    small, _ = footprint(2, 10)
+    unit = 9 * 16 + 8
+    hbm = ((big + small) // (9 * 16) + 3) * unit
+    for look, expect in ((0, [0, 1, 2]), (1, [0, 2, 1])):
+        srv = perc.perc_server(hbm_bytes=hbm, max_slots=16, lookahead=look, host_only=True)
+        srv.submit(16, 300, 0.3, seed=1, tag=0)
+        srv.submit(16, 300, 0.3, seed=1, tag=1)  # does not fit beside tag 0
+        srv.submit(2, 10, 0.3, seed=1, tag=2)    # fits beside tag 0
+        order = []
+        for _ in range(10):
+            srv.tick()
+            order += [r["tag"] for r in srv.poll()]
+        assert order == expect, look
 
 
 def test_run_loop_arrivals():
