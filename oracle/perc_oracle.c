@@ -235,7 +235,8 @@ uint64_t orc_threshold(double p) {
 /* Occupancy of configurations cfg0 .. cfg0+n_cfg-1, canonical bit layout:
  * bit s of configuration c is word c*words + s/32, bit s%32 (LSB first).
  * Counter of site s: (s/4, cfg low word, cfg high word, W<<16 | L); key = seed words;
- * site s takes output word s%4. */
+ * site s takes output word s%4. Every output word is written by one thread (OpenMP
+ * over the words of all configurations), each site with its own Philox call. */
 int orc_sample(const orc_lattice *lat, double p, uint64_t seed, int64_t cfg0, int64_t n_cfg,
                uint32_t *bits) {
     if (!(p >= 0.0 && p <= 1.0) || n_cfg < 0) return ORC_EINVAL;
@@ -243,16 +244,23 @@ int orc_sample(const orc_lattice *lat, double p, uint64_t seed, int64_t cfg0, in
     uint64_t t = orc_threshold(p);
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t tag = ((uint32_t)lat->W << 16) | (uint32_t)lat->L;
-    for (int64_t c = 0; c < n_cfg; ++c) {
+    int64_t total = n_cfg * words;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t i = 0; i < total; ++i) {
+        int64_t c = i / words, w = i - c * words;
         uint64_t cfg = (uint64_t)(cfg0 + c);
-        uint32_t *b = bits + c * words;
-        memset(b, 0, sizeof(uint32_t) * (size_t)words);
-        for (int64_t s = 0; s < n; ++s) {
+        uint32_t word = 0;
+        for (int b = 0; b < 32; ++b) {
+            int64_t s = w * 32 + b;
+            if (s >= n) break;
             uint32_t ctr[4] = {(uint32_t)(s >> 2), (uint32_t)cfg, (uint32_t)(cfg >> 32), tag};
             uint32_t out[4];
             orc_philox4x32_10(ctr, key, out);
-            if ((uint64_t)out[s & 3] < t) b[s >> 5] |= 1u << (s & 31);
+            if ((uint64_t)out[s & 3] < t) word |= 1u << b;
         }
+        bits[i] = word;
     }
     return ORC_OK;
 }
