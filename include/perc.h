@@ -152,6 +152,22 @@ int perc_inspect(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cf
 int perc_inspect_ex(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc,
                     int32_t* steps, float* hit, const perc_options* opt, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture elsewhere in the
+ * program, tight serving loops, harnesses that forbid allocation): perc_inspect_ex in
+ * the span form with every work buffer (state, codes, slot tables, the planner's work
+ * list, the shape tables) carved from one fixed 256 MiB array per device that the
+ * library holds from its first use on that device until the process ends. The call
+ * makes no device, pinned-host or pool allocation and builds no graph; it runs in
+ * waves of as many configurations as the array holds and returns when the work is
+ * complete (synchronous; not capturable). occ_bits, perc, steps (may be NULL), hit
+ * (may be NULL): device, as perc_inspect_ex; results equal perc_inspect_ex's bit for
+ * bit. PERC_EINVAL when one configuration of the fiber needs more than the array (at
+ * 9 bytes per state word: e.g. W=64 fits up to L of about 7,000 layers). Every call on
+ * a device shares its array: calls that overlap on one device (other threads, other
+ * streams) race and must be serialised by the caller. */
+int perc_inspect_noalloc(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc,
+                         int32_t* steps, float* hit, void* stream);
+
 /* ---- percolation probability Pi(p) (Sec. III) ------------------------------------ */
 
 typedef struct perc_pi_out {

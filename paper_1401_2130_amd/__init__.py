@@ -97,6 +97,7 @@ def _load():
     lib.perc_sample_fixed.argtypes = [vp, dbl, C.c_uint64, i64, i64, vp, vp]
     lib.perc_inspect.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.perc_inspect_ex.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(perc_options), vp]
+    lib.perc_inspect_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     lib.perc_pi.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), vp]
     lib.perc_pi_ex.argtypes = [vp, dbl, i64, C.c_uint64, C.POINTER(perc_pi_out), C.POINTER(perc_options), vp]
     lib.perc_state_after.argtypes = [vp, vp, i32, vp, vp, vp]
@@ -123,7 +124,8 @@ _lib = _load()
 
 EXPORTED = ("perc_lattice_create", "perc_lattice_create_ex", "perc_lattice_destroy", "perc_lattice_sites", "perc_lattice_words",
             "perc_lattice_columns", "perc_lattice_state_bytes", "perc_site_coord", "perc_site_neighbors",
-            "perc_last_error", "perc_sample", "perc_sample_fixed", "perc_inspect", "perc_inspect_ex", "perc_pi", "perc_pi_ex",
+            "perc_last_error", "perc_sample", "perc_sample_fixed", "perc_inspect", "perc_inspect_ex", "perc_inspect_noalloc",
+            "perc_pi", "perc_pi_ex",
             "perc_batch", "perc_state_after", "perc_first_passage", "perc_first_passage_batch", "perc_steps_hist", "perc_profile_enable", "perc_profile_read", "perc_autotune",
             "perc_server_create",
             "perc_server_destroy", "perc_server_submit", "perc_server_cancel", "perc_server_tick", "perc_server_poll",
@@ -283,6 +285,18 @@ def perc_inspect_ex(lat: Lattice, occ: torch.Tensor, n_cfg: Optional[int] = None
                                 _dptr(perc, torch.uint8, n_cfg), _dptr(steps, torch.int32, n_cfg),
                                 _dptr(hit_t, torch.float32, n_cfg), C.byref(opt), _stream(stream)))
     return perc, steps, hit_t
+
+
+def perc_inspect_noalloc(lat: Lattice, occ: torch.Tensor, perc: torch.Tensor, steps=None, hit=None,
+                         n_cfg: Optional[int] = None, stream=None):
+    """perc_inspect_ex in the span form with the library's fixed work array: the caller
+    passes every output buffer; the call allocates nothing (synchronous)."""
+    if n_cfg is None:
+        n_cfg = occ.numel() // lat.words
+    _check(_lib.perc_inspect_noalloc(lat.handle, _dptr(occ, torch.int32, n_cfg * lat.words), int(n_cfg),
+                                     _dptr(perc, torch.uint8, n_cfg), _dptr(steps, torch.int32, n_cfg),
+                                     _dptr(hit, torch.float32, n_cfg), _stream(stream)))
+    return perc, steps, hit
 
 
 def perc_pi(lat: Lattice, p: float, n_cfg: int, seed: int, bits=None, steps=None, hit=None, stream=None):

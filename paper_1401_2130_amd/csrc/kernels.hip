@@ -31,6 +31,8 @@
 // address 0.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "perc_internal.hpp"
 
 namespace perc {
@@ -1591,6 +1593,24 @@ __global__ void __launch_bounds__(256) k_count(const uint8_t* __restrict__ perc,
     if (threadIdx.x == 0 && red) atomicAdd(count, red);
 }
 
+// Slot tables of a batch of n configurations of one shape whose occupancy words lie back
+// to back from `bits` and whose state slots lie `stride` words apart.
+__global__ void __launch_bounds__(256) k_slot_table(int32_t* __restrict__ slot_shape, int64_t* __restrict__ slot_off,
+                                                    const uint32_t** __restrict__ slot_bits, int32_t n, int64_t stride,
+                                                    const uint32_t* bits, int64_t words) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n; b += gridDim.x * blockDim.x) {
+        slot_shape[b] = 0;
+        slot_off[b] = (int64_t)b * stride;
+        slot_bits[b] = bits + (int64_t)b * words;
+    }
+}
+
+// Work memory of the entry point that allocates nothing (perc_inspect_noalloc): one
+// array per device, part of the code object, kept until the process ends. Host code
+// never passes the array's name to a kernel: it takes the device address once per
+// device (scratch_region) and carves that.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 constexpr size_t kDynLds = 160 * 1024;  // dynamic LDS limit set once per device
 
 template <typename K>
@@ -1612,6 +1632,35 @@ hipError_t prepare_kernels(int device) {
     if (e == hipSuccess) e = allow_lds(k_chunk_step);
     if (e == hipSuccess) e = allow_lds(k_persist);
     return e;
+}
+
+hipError_t scratch_region(void** ptr, size_t* bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kScratchBytes;
+    return hipSuccess;
+}
+
+hipError_t launch_slot_table(int32_t* slot_shape, int64_t* slot_off, const uint32_t** slot_bits, int32_t n,
+                             int64_t stride, const uint32_t* bits, int64_t words, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slot_table, dim3((n + 255) / 256), dim3(256), 0, s, slot_shape, slot_off, slot_bits, n, stride,
+                       bits, words);
+    return hipGetLastError();
 }
 
 int32_t span_step_resident(int32_t block, int32_t lds) {

@@ -1454,6 +1454,148 @@ int one_setup(const perc_lattice* lat, const uint32_t* occ_bits, hipStream_t s, 
     return PERC_OK;
 }
 
+// ---------------------------------------------------------------------------------
+// The inspection in the span form with every work buffer carved from the library's
+// fixed per-device array (perc_inspect_noalloc): no device, pinned or pool allocation,
+// no graph; the host polls the planner's header with plain copies.
+// ---------------------------------------------------------------------------------
+struct Carver {
+    char* base;
+    size_t size, used = 0;
+    template <typename T>
+    T* take(size_t count) {
+        T* p = reinterpret_cast<T*>(base + used);
+        used += Arena::align(sizeof(T) * std::max<size_t>(count, 1));
+        return p;
+    }
+    bool fits() const { return used <= size; }
+};
+
+int noalloc_impl(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc, int32_t* steps,
+                 float* hit, hipStream_t s) {
+    PERC_TRY(validate_lat(lat));
+    if (n_cfg < 0) return fail(PERC_EINVAL, "n_cfg < 0");
+    if (n_cfg == 0) return PERC_OK;
+    if (!occ_bits || !perc) return fail(PERC_EINVAL, "occ_bits and perc must be device pointers");
+    if (stream_capturing(s)) return fail(PERC_EINVAL, "the inspection synchronises; not capturable");
+    const LatticeDesc& d = lat->d;
+    const ColumnSet& cs = *d.cs;
+    ShapeNeed nd;
+    nd.span_max = d.span_max;
+    nd.tile_max = d.tile_max;
+    nd.C = d.C;
+    nd.items = (int64_t)d.U * d.ntile;
+    const int32_t block = block_for(nd);
+    PERC_TRY(check_walk(nd, block));
+    void* region = nullptr;
+    size_t region_bytes = 0;
+    HIP_TRY(scratch_region(&region, &region_bytes));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    PERC_TRY(prepare(dev));
+    // tables of the shape, then the slots of one wave
+    Carver cv{reinterpret_cast<char*>(region), region_bytes};
+    DevShape* d_shape = cv.take<DevShape>(1);
+    uint32_t* d_nboff = cv.take<uint32_t>(cs.contact.size());
+    int32_t* d_tile = cv.take<int32_t>(cs.tile.size());
+    int32_t* d_rank = cv.take<int32_t>(cs.rank.size());
+    int32_t* d_sig = cv.take<int32_t>(cs.sig.size());
+    int32_t* d_hdr = cv.take<int32_t>(16);
+    const size_t fixed = cv.used;
+    const int64_t sw = slot_words(d);
+    // bytes of one wave of nb slots, in the order the wave carves them below
+    auto wave_bytes = [&](int64_t nb) {
+        auto al = [](size_t b) { return Arena::align(std::max<size_t>(b, 1)); };
+        const size_t n = (size_t)nb;
+        return al(sizeof(float) * sw * n) * 2 + al((size_t)sw * n) + al(sizeof(CfgState) * n) +
+               al(sizeof(int32_t) * n) * 3 + al(sizeof(int64_t) * (n + 1)) * 2 + al(sizeof(void*) * n) +
+               (steps ? 0 : al(sizeof(int32_t) * n));
+    };
+    if (fixed + wave_bytes(1) > region_bytes)
+        return fail(PERC_EINVAL, "one configuration of this fiber needs " + std::to_string(fixed + wave_bytes(1)) +
+                                     " bytes of work memory, more than the fixed " + std::to_string(region_bytes));
+    // configurations per wave: as many as the array holds (bisection on the exact carve)
+    int64_t lo = 1, hi = std::min<int64_t>(n_cfg, 1 << 16);
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (fixed + wave_bytes(mid) <= region_bytes) lo = mid; else hi = mid - 1;
+    }
+    const int64_t per_wave = lo;
+    DevShape sh;
+    sh.nboff = d_nboff;
+    sh.tile = d_tile;
+    sh.rank = d_rank;
+    sh.sig = d_sig;
+    sh.nboff2 = nullptr;
+    sh.tile2 = nullptr;
+    sh.C = d.C; sh.CP = d.CP; sh.U = d.U; sh.L = d.L;
+    sh.ntile = d.ntile; sh.span_max = d.span_max; sh.tile_max = d.tile_max; sh.W = d.W;
+    sh.ends = d.ends;
+    sh.span2_max = 0;
+    sh.N = d.N; sh.words = d.words;
+    HIP_TRY(hipMemcpyAsync(d_shape, &sh, sizeof(DevShape), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_nboff, cs.contact.data(), sizeof(uint32_t) * cs.contact.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_tile, cs.tile.data(), sizeof(int32_t) * cs.tile.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_rank, cs.rank.data(), sizeof(int32_t) * cs.rank.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_sig, cs.sig.data(), sizeof(int32_t) * cs.sig.size(), hipMemcpyHostToDevice, s));
+    const int lds = (int)lds_total(d.span_max);
+    const int32_t resident = span_step_resident(block, lds);
+    for (int64_t w0 = 0; w0 < n_cfg; w0 += per_wave) {
+        const int32_t nb = (int32_t)std::min<int64_t>(per_wave, n_cfg - w0);
+        Carver wv{reinterpret_cast<char*>(region) + fixed, region_bytes - fixed};
+        SpanArgs a{};
+        a.shapes = d_shape;
+        a.ya = wv.take<float>(sw * nb);
+        a.yb = wv.take<float>(sw * nb);
+        a.code = wv.take<uint8_t>(sw * nb);
+        a.st = wv.take<CfgState>(nb);
+        a.active = wv.take<int32_t>(nb);
+        a.active2 = wv.take<int32_t>(nb);
+        int32_t* slot_shape = wv.take<int32_t>(nb);
+        a.chunk_off = wv.take<int64_t>(nb + 1);
+        int64_t* slot_off = wv.take<int64_t>(nb + 1);
+        const uint32_t** slot_bits = wv.take<const uint32_t*>(nb);
+        int32_t* own_steps = steps ? nullptr : wv.take<int32_t>(nb);
+        if (!wv.fits()) return fail(PERC_EINVAL, "work memory carve exceeds the fixed array");
+        a.slot_shape = slot_shape;
+        a.slot_off = slot_off;
+        a.slot_bits = slot_bits;
+        a.hdr = d_hdr;
+        a.work = reinterpret_cast<unsigned long long*>(d_hdr + 8);
+        a.out.perc = perc + w0;
+        a.out.steps = steps ? steps + w0 : own_steps;
+        a.out.hit = hit ? hit + w0 : nullptr;
+        a.n_slot = nb;
+        a.depth = 64;
+        a.block = block;
+        a.grid = kSpanGrid;
+        a.lds = lds;
+        a.pair = kSpanPairs ? 1 : 0;
+        a.resident = resident;
+        HIP_TRY(launch_slot_table(slot_shape, slot_off, slot_bits, nb, sw, occ_bits + w0 * d.words, d.words, s));
+        HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_hdr), 16, 0u, s));
+        HIP_TRY(launch_span_init(a, s));
+        int32_t h[16];
+        int reps = 1;
+        for (;;) {
+            HIP_TRY(hipMemcpyAsync(h, d_hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (h[0] == 0) break;
+            for (int i = 0; i < 8 * reps; ++i) {
+                HIP_TRY(launch_span_step(a, s));
+                if (a.pair) HIP_TRY(launch_span_step(second_of(a), s));
+                HIP_TRY(launch_span_plan(a, s));
+            }
+            reps = std::min(reps * 2, 8);
+        }
+        if (h[2]) return fail(PERC_ECAP, "a configuration reached the step cap");
+        HIP_TRY(launch_span_finish(a, s));
+    }
+    // the next call may overwrite the array: the work of this one ends first
+    HIP_TRY(hipStreamSynchronize(s));
+    return PERC_OK;
+}
+
 }  // namespace
 
 // =================================================================================
@@ -1587,6 +1729,11 @@ int perc_inspect(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cf
 int perc_inspect_ex(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc, int32_t* steps,
                     float* hit, const perc_options* opt, void* stream) {
     return inspect_impl(lat, occ_bits, n_cfg, perc, steps, hit, opt, stream);
+}
+
+int perc_inspect_noalloc(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc,
+                         int32_t* steps, float* hit, void* stream) {
+    return noalloc_impl(lat, occ_bits, n_cfg, perc, steps, hit, reinterpret_cast<hipStream_t>(stream));
 }
 
 int perc_pi(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, perc_pi_out* out, void* stream) {

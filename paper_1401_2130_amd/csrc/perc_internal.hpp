@@ -339,6 +339,14 @@ hipError_t launch_count(const uint8_t* perc, int64_t n, unsigned long long* coun
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 int persist_resident_per_cu(int block, int lds_bytes);
+
+// The fixed work array of perc_inspect_noalloc on the current device: its device address
+// (taken with hipGetSymbolAddress on the first call per device) and size.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+hipError_t scratch_region(void** ptr, size_t* bytes);
+// slot_shape[b] = 0, slot_off[b] = b * stride, slot_bits[b] = bits + b * words, b < n.
+hipError_t launch_slot_table(int32_t* slot_shape, int64_t* slot_off, const uint32_t** slot_bits, int32_t n,
+                             int64_t stride, const uint32_t* bits, int64_t words, hipStream_t s);
 hipError_t prepare_kernels(int device);
 
 }  // namespace perc
