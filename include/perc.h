@@ -64,11 +64,16 @@ enum {
                               the whole inspection (sampling included) in one launch;
                               it reports PERC_ECAP from the synchronous calls only
                               (perc_pi, perc_pi_ex, perc_batch with groups) */
-    PERC_FORM_SPAN2 = 4    /* the span form advancing two steps per launch: the first step
+    PERC_FORM_SPAN2 = 4,   /* the span form advancing two steps per launch: the first step
                               of a tile's halo range is kept in LDS and the second is
                               computed from it, one pass over the state per two steps.
                               PERC_EINVAL for fibers whose outer range (the halo of the
                               halo range) exceeds two columns per thread or LDS */
+    PERC_FORM_PERSIST2 = 5 /* the persistent form advancing two steps per pass: one
+                              workgroup holds the whole cross-section (one thread per
+                              column, no halo), keeps the first step in LDS and writes the
+                              second; PERC_EINVAL for fibers of more than 1024 columns
+                              (W > 17). Reports PERC_ECAP as the persistent form */
 };
 
 typedef struct perc_options {
@@ -273,9 +278,11 @@ int perc_profile_read(perc_profile* out);
 
 /* ---- autotuning of the execution settings -------------------------------------- */
 /* Time candidate settings (span form with 32/64/128 cells per work item and one or two
- * block sizes, persistent form with 32/64/128) on the sample `jobs` (as perc_batch; group
- * must be -1) and return the fastest in *best (wall time of the whole sample, ms, in
- * *best_ms; either may be NULL). If every job has the same (W, L), the choice is also
+ * block sizes, persistent form with 64/128/256, the two-step forms where the shapes allow
+ * them) on the sample `jobs` (as perc_batch; group must be -1; a sample spread over the
+ * batch's p values and shapes represents it best) and return the fastest in *best (wall
+ * time of the whole sample, ms, in *best_ms; either may be NULL). If every job has the
+ * same (W, L), the choice is also
  * remembered for PERC_FORM_AUTO calls on that shape with a batch of about n_target
  * configurations (n_target <= 0: the sample size). Synchronous; the outputs of the
  * timing runs are discarded. */

@@ -23,8 +23,9 @@ LIB_PATH = os.path.join(_PKG, "_build", "libperc.so")
 
 PERC_OK, PERC_EINVAL, PERC_ENOMEM, PERC_EHIP, PERC_EBUSY, PERC_ECANCELED, PERC_ECAP = 0, -1, -2, -3, -4, -5, -6
 PERC_LATTICE_NO_END_CONTACTS = 1
-FORM_AUTO, FORM_PLAIN, FORM_SPAN, FORM_PERSIST, FORM_SPAN2 = 0, 1, 2, 3, 4
-_FORMS = {"auto": FORM_AUTO, "plain": FORM_PLAIN, "span": FORM_SPAN, "persist": FORM_PERSIST, "span2": FORM_SPAN2}
+FORM_AUTO, FORM_PLAIN, FORM_SPAN, FORM_PERSIST, FORM_SPAN2, FORM_PERSIST2 = 0, 1, 2, 3, 4, 5
+_FORMS = {"auto": FORM_AUTO, "plain": FORM_PLAIN, "span": FORM_SPAN, "persist": FORM_PERSIST, "span2": FORM_SPAN2,
+          "persist2": FORM_PERSIST2}
 
 
 class PercError(RuntimeError):

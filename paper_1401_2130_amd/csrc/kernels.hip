@@ -202,12 +202,15 @@ __device__ __forceinline__ uint32_t code_of(const uint32_t* __restrict__ code8, 
 // loads are never predicated: the group index is clamped into the configuration and
 // the words are masked when written to the ring.
 // ------------------------------------------------------------------------------
-struct Stage {
-    int col[kLoadCols];         // global column of each staged column of this thread (clamped)
-    uint32_t* slot[kLoadCols];  // its LDS column (row 0)
-    bool ok[kLoadCols];         // inside the halo range
-    int nj;                     // staged column slots the workgroup needs (uniform)
+// NJ: staged column slots per thread (span <= NJ * blockDim).
+template <int NJ>
+struct StageN {
+    int col[NJ];         // global column of each staged column of this thread (clamped)
+    uint32_t* slot[NJ];  // its LDS column (row 0)
+    bool ok[NJ];         // inside the halo range
+    int nj;              // staged column slots the workgroup needs (uniform)
 };
+using Stage = StageN<kLoadCols>;
 
 __device__ __forceinline__ Stage stage_columns(const TileV& tv) {
     Stage st;
@@ -248,17 +251,18 @@ __device__ __forceinline__ void put_quad(uint32_t* slot, int g, int vmax, uint4 
 }
 
 // Raw state quads of group g (clamped into [0, vmax / 4]) for the staged columns.
-__device__ __forceinline__ void load_quads(const DevShape& sh, const Stage& st, const float* __restrict__ y, int g,
-                                           int vmax, uint4 (&out)[kLoadCols]) {
+template <int NJ>
+__device__ __forceinline__ void load_quads(const DevShape& sh, const StageN<NJ>& st, const float* __restrict__ y, int g,
+                                           int vmax, uint4 (&out)[NJ]) {
     const uint4* q = reinterpret_cast<const uint4*>(y) + (uint32_t)min(max(g, 0), vmax >> 2) * sh.CP;
 #pragma unroll
-    for (int j = 0; j < kLoadCols; ++j) out[j] = j < st.nj ? q[st.col[j]] : make_uint4(0u, 0u, 0u, 0u);
+    for (int j = 0; j < NJ; ++j) out[j] = j < st.nj ? q[st.col[j]] : make_uint4(0u, 0u, 0u, 0u);
 }
 
-template <int S0>
-__device__ __forceinline__ void put_quads(const Stage& st, int g, int vmax, const uint4 (&q)[kLoadCols]) {
+template <int S0, int NJ>
+__device__ __forceinline__ void put_quads(const StageN<NJ>& st, int g, int vmax, const uint4 (&q)[NJ]) {
 #pragma unroll
-    for (int j = 0; j < kLoadCols; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         if (j >= st.nj) break;
         if (st.ok[j]) put_quad<S0>(st.slot[j], g, vmax, q[j]);
     }
@@ -427,23 +431,25 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
 // single steps; first-step words of a tube computed by several items are identical.
 // ------------------------------------------------------------------------------
 
-// Halo-range columns of this thread that compute the first step (up to kLoadCols).
+// Halo-range columns of this thread that compute the first step (up to NJ).
+template <int NJ>
 struct Prod {
-    const uint32_t* nb[kLoadCols][kSide];  // R0 word of each side contact (slot 0)
-    const uint32_t* me[kLoadCols];         // own column in R0 (row 0)
-    uint32_t* out[kLoadCols];              // own column in R1 (row 0)
-    int c[kLoadCols];
-    int top[kLoadCols];
-    bool ok[kLoadCols];  // a halo-range column (else a copy of the first one, not stored)
-    int n;               // column slots in use (uniform)
+    const uint32_t* nb[NJ][kSide];  // R0 word of each side contact (slot 0)
+    const uint32_t* me[NJ];         // own column in R0 (row 0)
+    uint32_t* out[NJ];              // own column in R1 (row 0)
+    int c[NJ];
+    int top[NJ];
+    bool ok[NJ];  // a halo-range column (else a copy of the first one, not stored)
+    int n;        // column slots in use (uniform)
 };
 
-__device__ __forceinline__ Stage stage_range(int hs, int he, uint32_t* base) {
-    Stage st;
+template <int NJ>
+__device__ __forceinline__ StageN<NJ> stage_range(int hs, int he, uint32_t* base) {
+    StageN<NJ> st;
     const int span = he - hs;
     st.nj = (span + (int)blockDim.x - 1) / (int)blockDim.x;
 #pragma unroll
-    for (int j = 0; j < kLoadCols; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const int lc = (int)threadIdx.x + j * (int)blockDim.x;
         st.ok[j] = lc < span;
         st.col[j] = st.ok[j] ? hs + lc : hs;
@@ -452,14 +458,15 @@ __device__ __forceinline__ Stage stage_range(int hs, int he, uint32_t* base) {
     return st;
 }
 
-__device__ __forceinline__ Prod prod_columns(const DevShape& sh, int k, const TileV& tv, int os,
-                                             const uint32_t* r0, uint32_t* r1) {
-    Prod p;
+template <int NJ>
+__device__ __forceinline__ Prod<NJ> prod_columns(const DevShape& sh, int k, const TileV& tv, int os,
+                                                 const uint32_t* r0, uint32_t* r1) {
+    Prod<NJ> p;
     const int span = tv.he - tv.hs;
     p.n = (span + (int)blockDim.x - 1) / (int)blockDim.x;
     const uint32_t* tab = sh.nboff2 + (size_t)k * kSide * sh.span_max;
 #pragma unroll
-    for (int j = 0; j < kLoadCols; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const int lc = (int)threadIdx.x + j * (int)blockDim.x;
         p.ok[j] = lc < span;
         const int l = p.ok[j] ? lc : 0;
@@ -484,12 +491,13 @@ __device__ __forceinline__ Own own_column_in(const DevShape& sh, const TileV& tv
     return w;
 }
 
+template <int NJ>
 struct Step2State {
-    uint4 next[kLoadCols];        // staged outer quads of the group after the current one
-    uint32_t cq1[2][kLoadCols];   // halo-range code words, by group parity
-    uint32_t cq2[2];              // tile code words, by group parity
-    uint32_t r2[4];               // second-step words of the group before
-    uint32_t first0[kLoadCols];   // first-step words of the group's first cell (stored late)
+    uint4 next[NJ];        // staged outer quads of the group after the current one
+    uint32_t cq1[2][NJ];   // halo-range code words, by group parity
+    uint32_t cq2[2];       // tile code words, by group parity
+    uint32_t r2[4];        // second-step words of the group before
+    uint32_t first0[NJ];   // first-step words of the group's first cell (stored late)
     uint32_t grew1 = 0, far1 = 0, ent1 = 0;
     uint32_t grew2 = 0, far2 = 0, ent2a = 0, ent2b = 0;
 };
@@ -497,12 +505,12 @@ struct Step2State {
 // First step of cell u (ring slot K) for every halo-range column of this thread, written
 // to the same slot of R1 (with the mirror row of slots 0 and 7). Words outside [0, vmax1]
 // are set to zero: those cells hold no mass after the first step.
-template <int K>
-__device__ __forceinline__ void first_cell(const DevShape& sh, const Prod& p, const float4* ct, int u, int vmax1,
-                                           int front, float* __restrict__ far1, Step2State& ss) {
+template <int K, int NJ>
+__device__ __forceinline__ void first_cell(const DevShape& sh, const Prod<NJ>& p, const float4* ct, int u, int vmax1,
+                                           int front, float* __restrict__ far1, Step2State<NJ>& ss) {
     constexpr int k = K & 3, par = K >> 2;
 #pragma unroll
-    for (int j = 0; j < kLoadCols; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         if (j >= p.n) break;
         const uint32_t cd = (ss.cq1[par][j] >> (4 * K)) & 0xfu;
         const uint32_t own = p.me[j][(K + 1) * kBlkCols];
@@ -529,10 +537,10 @@ __device__ __forceinline__ void first_cell(const DevShape& sh, const Prod& p, co
 }
 
 // The first-step words of the first cell of a group (ring slot K), with the mirror row.
-template <int K>
-__device__ __forceinline__ void store_first0(const Prod& p, const Step2State& ss) {
+template <int K, int NJ>
+__device__ __forceinline__ void store_first0(const Prod<NJ>& p, const Step2State<NJ>& ss) {
 #pragma unroll
-    for (int j = 0; j < kLoadCols; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         if (j >= p.n) break;
         if (!p.ok[j]) continue;
         p.out[j][(K + 1) * kBlkCols] = ss.first0[j];
@@ -542,9 +550,9 @@ __device__ __forceinline__ void store_first0(const Prod& p, const Step2State& ss
 
 // Second step of cell u (ring slot K of R1) for this thread's tile column; at the last
 // cell of the group its quad goes to HBM.
-template <int K>
+template <int K, int NJ>
 __device__ __forceinline__ void second_cell(const DevShape& sh, const Own& w, const float4* ct, int u, int front,
-                                            int top_min, float* __restrict__ yout, Step2State& ss) {
+                                            int top_min, float* __restrict__ yout, Step2State<NJ>& ss) {
     constexpr int k = K & 3, par = K >> 2;
     const uint32_t cd = (ss.cq2[par] >> (4 * K)) & 0xfu;
     const uint32_t own = w.me[(K + 1) * kBlkCols];
@@ -568,9 +576,10 @@ __device__ __forceinline__ void second_cell(const DevShape& sh, const Own& w, co
     }
 }
 
+template <int NJ>
 struct Walk2 {
-    const Stage* st;
-    const Prod* p;
+    const StageN<NJ>* st;
+    const Prod<NJ>* p;
     const Own* w;
     const float4* ct;
     const float* yin;
@@ -591,8 +600,8 @@ __device__ __forceinline__ int clamp_q(int g, int last_q) { return min(max(g, 0)
 // only R1 word of G-2 the first second-step cell reads; before the second-step cells
 // that read group G. The first three first-step cells write rows that no second-step
 // cell between the first two barriers reads.
-template <int P>
-__device__ __forceinline__ void half2(const DevShape& sh, const Walk2& k2, int G, bool second, Step2State& ss) {
+template <int P, int NJ>
+__device__ __forceinline__ void half2(const DevShape& sh, const Walk2<NJ>& k2, int G, bool second, Step2State<NJ>& ss) {
     constexpr int K0 = 4 * P, Q0 = 4 * (P ^ 1);
     const int u = 4 * G;
     first_cell<K0>(sh, *k2.p, k2.ct, u, k2.vmax1, k2.front, k2.far1, ss);
@@ -601,7 +610,7 @@ __device__ __forceinline__ void half2(const DevShape& sh, const Walk2& k2, int G
     put_quads<Q0>(*k2.st, G + 1, k2.vmax0, ss.next);
     load_quads(sh, *k2.st, k2.yin, G + 2, k2.vmax0, ss.next);
 #pragma unroll
-    for (int j = 0; j < kLoadCols; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         if (j >= k2.p->n) break;
         ss.cq1[P ^ 1][j] = k2.code4[code_word_g(sh, clamp_q(G + 1, k2.last_q), k2.p->c[j])];
     }
@@ -622,7 +631,9 @@ __device__ __forceinline__ void half2(const DevShape& sh, const Walk2& k2, int G
 // Two steps of the tile's tubes in cells [ub, ue) (cut at min(U, front+3); ub a multiple
 // of 8): reads yin, writes the second step's words to yout and the first step's words of
 // the far-end tubes to far1 (indexed by column; nullable). Returns the first step's flags
-// and stores the second step's in *fl2.
+// and stores the second step's in *fl2. NJ: column slots per thread of the halo and
+// outer ranges (1 when the workgroup has a thread per column of the whole tile).
+template <int NJ>
 __device__ __forceinline__ uint32_t walk_step2(const DevShape& sh, int k, const TileV& tv, const float4* ct,
                                                const float* __restrict__ yin, float* __restrict__ yout,
                                                const uint8_t* __restrict__ code, float* __restrict__ far1, int ub,
@@ -633,10 +644,10 @@ __device__ __forceinline__ uint32_t walk_step2(const DevShape& sh, int k, const 
     uint32_t* r0 = reinterpret_cast<uint32_t*>(lds);
     uint32_t* r1 = r0 + r1_off;
     const int os = uniform_i32(sh.tile2 + 2 * k), oe = uniform_i32(sh.tile2 + 2 * k + 1);
-    const Stage st = stage_range(os, oe, r0);
-    const Prod p = prod_columns(sh, k, tv, os, r0, r1);
+    const StageN<NJ> st = stage_range<NJ>(os, oe, r0);
+    const Prod<NJ> p = prod_columns<NJ>(sh, k, tv, os, r0, r1);
     const Own w = own_column_in(sh, tv, r1);
-    Walk2 k2;
+    Walk2<NJ> k2;
     k2.st = &st;
     k2.p = &p;
     k2.w = &w;
@@ -656,15 +667,15 @@ __device__ __forceinline__ uint32_t walk_step2(const DevShape& sh, int k, const 
         r0[ring_word((int)threadIdx.x, 0)] = 0u;
         r1[ring_word((int)threadIdx.x, 0)] = 0u;
     }
-    Step2State ss;
-    uint4 q[kLoadCols];
+    Step2State<NJ> ss;
+    uint4 q[NJ];
     load_quads(sh, st, yin, g0 - 2, k2.vmax0, q);
     put_quads<0>(st, g0 - 2, k2.vmax0, q);
     load_quads(sh, st, yin, g0 - 1, k2.vmax0, q);
     put_quads<4>(st, g0 - 1, k2.vmax0, q);
     load_quads(sh, st, yin, g0, k2.vmax0, ss.next);
 #pragma unroll
-    for (int j = 0; j < kLoadCols; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         if (j >= p.n) break;
         ss.cq1[1][j] = k2.code4[code_word_g(sh, clamp_q(g0 - 1, k2.last_q), p.c[j])];
     }
@@ -1075,6 +1086,20 @@ __global__ void __launch_bounds__(256) k_sample_slots(const DevShape* shapes, co
     }
 }
 
+// Occupancy of the listed jobs, one workgroup per job, into the buffer each job's bits
+// pointer names (the persistent form draws every configuration before it starts).
+__global__ void __launch_bounds__(256) k_sample_jobs(const DevShape* shapes, const Job* jobs, const int64_t* idx,
+                                                     int64_t n) {
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const Job job = jobs[idx[i]];
+        const DevShape sh = shapes[job.shape];
+        uint32_t* dst = const_cast<uint32_t*>(job.bits);
+        const uint32_t k0 = (uint32_t)job.seed, k1 = (uint32_t)(job.seed >> 32);
+        for (int64_t w = threadIdx.x; w < sh.words; w += blockDim.x)
+            dst[w] = sample_word(w, sh.N, job.cfg, job.thr, k0, k1, shape_tag(sh));
+    }
+}
+
 // Item layout of the initialisation (all cells of every slot) and the slot states.
 // Slots to initialise: the listed ones (a.ids), else all.
 __device__ __forceinline__ int init_count(const SpanArgs& a) { return a.ids ? a.n_ids : a.n_slot; }
@@ -1339,7 +1364,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_step2(SpanArgs a) {
         const float* yin = (s.par ? a.yb : a.ya) + off;
         float* yout = (s.par ? a.ya : a.yb) + off;
         uint32_t fl2 = 0;
-        const uint32_t fl = walk_step2(sh, k, load_tile(sh, k), tl.ct, yin, yout, a.code + off,
+        const uint32_t fl = walk_step2<kLoadCols>(sh, k, load_tile(sh, k), tl.ct, yin, yout, a.code + off,
                                        a.far1 + (int64_t)b * a.far1_stride, r * E, r * E + E, s.front, a.r1_off, &fl2);
         flags_to(&a.st[b].flags, fl | (threadIdx.x < 64 ? (F_STEPPED | F_FUSED) : 0u));
         flags_to(&a.st[b].flags2, fl2);
@@ -1398,13 +1423,20 @@ __global__ void __launch_bounds__(256) k_span_finish(SpanArgs a) {
     }
 }
 
-__global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
+// The persistent form: each workgroup pulls configurations from a device queue and runs
+// the whole inspection of each (codes and start state, every step, the outputs) on its
+// own state buffers; Philox occupancy is drawn for all configurations beforehand
+// (k_sample_jobs, at the full occupancy of a sampling kernel). TWO: two steps per pass of the whole-cross-section tile (the
+// first step kept in LDS, walk_step2); the decisions are those of single steps.
+template <bool TWO>
+__device__ __forceinline__ void persist_body(const PersistArgs& a) {
     const Tail tl = lds_tail(a.lds);
     fill_codes(tl.ct);
     const int E = a.depth;
     float* ya = a.ya + blockIdx.x * a.state_stride;
     float* yb = a.yb + blockIdx.x * a.state_stride;
     uint8_t* code = a.code + blockIdx.x * a.state_stride;
+    float* far1 = TWO ? a.far1 + blockIdx.x * a.far1_stride : nullptr;
     unsigned long long work = 0;  // tube slots advanced by this workgroup's steps
     for (;;) {
         __syncthreads();
@@ -1421,17 +1453,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
         }
         const Job job = uniform_load(a.jobs + j);
         const DevShape sh = uniform_load(a.shapes + job.shape);
-        const uint32_t* bits;
-        if (job.bits) {
-            bits = job.bits;
-        } else {
-            uint32_t* sb = a.bits_scratch + blockIdx.x * a.bits_stride;
-            const uint32_t k0 = (uint32_t)job.seed, k1 = (uint32_t)(job.seed >> 32);
-            for (int64_t w = threadIdx.x; w < sh.words; w += blockDim.x)
-                sb[w] = sample_word(w, sh.N, job.cfg, job.thr, k0, k1, shape_tag(sh));
-            __syncthreads();
-            bits = sb;
-        }
+        const uint32_t* bits = job.bits;  // the caller's, or drawn by k_sample_jobs beforehand
         // initialisation: codes of every cell, start state in ya
         const int n0 = count_start(sh, bits, tl.misc + 1);
         const float x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
@@ -1444,29 +1466,67 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
         if (f) atomicOr(&tl.misc[0], f);
         __syncthreads();
         f = tl.misc[0];
-        int32_t perc = -1, steps = 0, mm = 0, front = 0;
+        int32_t perc = -1, steps = 0, mm = 0, front = 0, par = 0;
+        bool hit_first = false;  // decided on the first step of a two-step pass
         if (!(f & F_NONEMPTY)) { perc = 0; steps = 0; }
         else if (f & F_FAR) { perc = 1; steps = 1; }
         while (perc < 0) {
-            const float* yin = (mm & 1) ? yb : ya;
-            float* yout = (mm & 1) ? ya : yb;
-            const int ulim = min(sh.U, front + 2);
-            work += (unsigned long long)ulim * (unsigned long long)sh.C;
-            uint32_t fl = 0;
-            for (int ub = 0; ub < ulim; ub += E)
-                for (int k = 0; k < sh.ntile; ++k)
-                    fl |= walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, code, ub, ub + E, front, front);
-            __syncthreads();
-            if (threadIdx.x == 0) tl.misc[0] = 0;
-            __syncthreads();
-            if (fl) atomicOr(&tl.misc[0], fl);
-            __syncthreads();
-            f = tl.misc[0];
-            mm += 1;
-            if (f & F_FRONT) front += 1;
-            if (f & F_FAR) { perc = 1; steps = mm + 1; }
-            else if (!(f & F_GREW)) { perc = 0; steps = mm; }
-            else if (mm > sh.N) { perc = 0; steps = mm; if (threadIdx.x == 0) atomicOr(a.err, 1u); }
+            const float* yin = par ? yb : ya;
+            float* yout = par ? ya : yb;
+            par ^= 1;
+            if (!TWO) {
+                const int ulim = min(sh.U, front + 2);
+                work += (unsigned long long)ulim * (unsigned long long)sh.C;
+                uint32_t fl = 0;
+                for (int ub = 0; ub < ulim; ub += E)
+                    for (int k = 0; k < sh.ntile; ++k)
+                        fl |= walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, code, ub, ub + E, front, front);
+                __syncthreads();
+                if (threadIdx.x == 0) tl.misc[0] = 0;
+                __syncthreads();
+                if (fl) atomicOr(&tl.misc[0], fl);
+                __syncthreads();
+                f = tl.misc[0];
+                mm += 1;
+                if (f & F_FRONT) front += 1;
+                if (f & F_FAR) { perc = 1; steps = mm + 1; }
+                else if (!(f & F_GREW)) { perc = 0; steps = mm; }
+                else if (mm > sh.N) { perc = 0; steps = mm; if (threadIdx.x == 0) atomicOr(a.err, 1u); }
+            } else {
+                const int ulim = min(sh.U, front + 3);
+                uint32_t fl = 0, fl2 = 0;
+                for (int ub = 0; ub < ulim; ub += E)
+                    for (int k = 0; k < sh.ntile; ++k) {
+                        uint32_t g2 = 0;
+                        fl |= walk_step2<1>(sh, k, load_tile(sh, k), tl.ct, yin, yout, code, far1, ub, ub + E, front,
+                                         a.r1_off, &g2);
+                        fl2 |= g2;
+                    }
+                __syncthreads();
+                if (threadIdx.x == 0) { tl.misc[0] = 0; tl.misc[6] = 0; }
+                __syncthreads();
+                if (fl) atomicOr(&tl.misc[0], fl);
+                if (fl2) atomicOr(&tl.misc[6], fl2);
+                __syncthreads();
+                f = tl.misc[0];
+                const uint32_t f2 = tl.misc[6];
+                // the first step
+                mm += 1;
+                work += (unsigned long long)min(sh.U, front + 2) * (unsigned long long)sh.C;
+                if (f & F_FRONT) front += 1;
+                if (f & F_FAR) { perc = 1; steps = mm + 1; hit_first = true; }
+                else if (!(f & F_GREW)) { perc = 0; steps = mm; }
+                else if (mm > sh.N) { perc = 0; steps = mm; if (threadIdx.x == 0) atomicOr(a.err, 1u); }
+                else {
+                    // the second step; its front flags are relative to the front before the first
+                    mm += 1;
+                    work += (unsigned long long)min(sh.U, front + 2) * (unsigned long long)sh.C;
+                    if ((f & F_FRONT) ? (f2 & F_FRONT2) : (f2 & F_FRONT)) front += 1;
+                    if (f2 & F_FAR) { perc = 1; steps = mm + 1; }
+                    else if (!(f2 & F_GREW)) { perc = 0; steps = mm; }
+                    else if (mm > sh.N) { perc = 0; steps = mm; if (threadIdx.x == 0) atomicOr(a.err, 1u); }
+                }
+            }
         }
         if (threadIdx.x == 0) {
             a.out.perc[j] = (uint8_t)perc;
@@ -1476,14 +1536,27 @@ __global__ void __launch_bounds__(kMaxBlock) k_persist(PersistArgs a) {
         if (a.out.hit) {
             float h = 0.0f;
             if (perc == 1) {
-                far_sum(sh, ((steps - 1) & 1) ? yb : ya, front, tl.part, tl.misc + 4,
-                        reinterpret_cast<float*>(tl.misc + 5));
+                // the detector mass at the stop: the far-end sum of the state after steps-1
+                // steps (the newest one, or the first step of the last pass)
+                if (TWO && hit_first)
+                    far_sum_cols(sh, far1, front, tl.part, tl.misc + 4, reinterpret_cast<float*>(tl.misc + 5));
+                else
+                    far_sum(sh, par ? yb : ya, front, tl.part, tl.misc + 4, reinterpret_cast<float*>(tl.misc + 5));
                 h = __uint_as_float(tl.misc[5]);
             }
             if (threadIdx.x == 0) a.out.hit[j] = h;
         }
     }
 }
+
+// Register budget: six waves per SIMD (80 VGPRs). The initialisation phase alone would
+// take 96 VGPRs (two workgroups per CU at the usual 448 threads); capped, a few words of
+// its set-up spill (outside the step walk) and a third workgroup fits on every CU.
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(6))) k_persist(PersistArgs a) {
+    persist_body<false>(a);
+}
+
+__global__ void __launch_bounds__(kMaxBlock) k_persist2(PersistArgs a) { persist_body<true>(a); }
 
 // Test hook support: far-end sum added to the detector mass, reach of the detector.
 __global__ void __launch_bounds__(256) k_far_acc(DevShape sh, const float* y, float* det_mass,
@@ -1631,6 +1704,7 @@ hipError_t prepare_kernels(int device) {
     if (e == hipSuccess) e = allow_lds(k_span_step2);
     if (e == hipSuccess) e = allow_lds(k_chunk_step);
     if (e == hipSuccess) e = allow_lds(k_persist);
+    if (e == hipSuccess) e = allow_lds(k_persist2);
     return e;
 }
 
@@ -1677,6 +1751,12 @@ int persist_resident_per_cu(int block, int lds_bytes) {
     return n;
 }
 
+int persist2_resident_per_cu(int block, int lds_bytes) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persist2, block, lds_bytes) != hipSuccess) return 1;
+    return n;
+}
+
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
@@ -1710,6 +1790,13 @@ hipError_t launch_sample_slots(const DevShape* shapes, const Job* jobs, int32_t 
     if (n_slot <= 0) return hipSuccess;
     const int grid = std::min(n_slot, 65536);
     hipLaunchKernelGGL(k_sample_slots, dim3(grid), dim3(256), 0, s, shapes, jobs, n_slot, slot_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_jobs(const DevShape* shapes, const Job* jobs, const int64_t* idx, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(n, 65536);
+    hipLaunchKernelGGL(k_sample_jobs, dim3(grid), dim3(256), 0, s, shapes, jobs, idx, n);
     return hipGetLastError();
 }
 
@@ -1768,7 +1855,10 @@ hipError_t launch_multi_step(const DevShape& sh, const float* yin, float* yout, 
 }
 
 hipError_t launch_persist(const PersistArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_persist, dim3(a.grid), dim3(a.block), a.lds, s, a);
+    if (a.two)
+        hipLaunchKernelGGL(k_persist2, dim3(a.grid), dim3(a.block), a.lds, s, a);
+    else
+        hipLaunchKernelGGL(k_persist, dim3(a.grid), dim3(a.block), a.lds, s, a);
     return hipGetLastError();
 }
 

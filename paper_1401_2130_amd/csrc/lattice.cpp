@@ -115,6 +115,15 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
         d.tile2[(size_t)k * 2 + 1] = oe;
         d.span2_max = std::max(d.span2_max, oe - os);
     }
+    if (C <= kWholeCols) {
+        d.contact_whole.assign((size_t)kSide * C, 0u);
+        for (int c = 0; c < C; ++c)
+            for (int i = 0; i < kSide; ++i) {
+                const int32_t v = d.nb[(size_t)i * C + c];
+                const int32_t col = v >> 2, dcp1 = v & 3;
+                d.contact_whole[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col + 1) : 0u;
+            }
+    }
     if (d.span_max <= kMaxSpan2 && d.span2_max <= kMaxSpan2) {
         const size_t sm = (size_t)d.span_max;
         d.contact2.assign((size_t)nt * kSide * sm, 0u);

@@ -103,27 +103,38 @@ int column_device(const ColumnSet& cs, int dev, ColumnDevice& out) {
         PERC_TRY(upload(&n.nboff2, cs.contact2));
         PERC_TRY(upload(&n.tile2, cs.tile2));
     }
+    if (!cs.contact_whole.empty()) {
+        PERC_TRY(upload(&n.nboff_whole, cs.contact_whole));
+        PERC_TRY(upload(&n.tile_whole, std::vector<int32_t>{0, cs.C, 0, cs.C, 0, cs.C}));
+    }
     g_coldev.emplace(std::make_pair(dev, cs.W), n);
     out = n;
     return PERC_OK;
 }
 
-int shape_of(const LatticeDesc& d, DevShape& sh) {
+// The kernels' view of a shape; with `whole`, the one-tile tiling of the whole
+// cross-section (fibers of at most kWholeCols columns), whose tile is also its own
+// outer range for the two-step walk.
+int shape_of(const LatticeDesc& d, DevShape& sh, bool whole = false) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     PERC_TRY(prepare(dev));
     ColumnDevice cd;
     PERC_TRY(column_device(*d.cs, dev, cd));
-    sh.nboff = cd.nboff;
-    sh.tile = cd.tile;
+    if (whole && !cd.nboff_whole) return fail(PERC_EINVAL, "the fiber has more columns than one tile holds");
+    sh.nboff = whole ? cd.nboff_whole : cd.nboff;
+    sh.tile = whole ? cd.tile_whole : cd.tile;
     sh.rank = cd.rank;
     sh.sig = cd.sig;
-    sh.nboff2 = cd.nboff2;
-    sh.tile2 = cd.tile2;
+    sh.nboff2 = whole ? cd.nboff_whole : cd.nboff2;
+    sh.tile2 = whole ? cd.tile_whole + 4 : cd.tile2;
     sh.C = d.C; sh.CP = d.CP; sh.U = d.U; sh.L = d.L;
-    sh.ntile = d.ntile; sh.span_max = d.span_max; sh.tile_max = d.tile_max; sh.W = d.W;
+    sh.ntile = whole ? 1 : d.ntile;
+    sh.span_max = whole ? d.C : d.span_max;
+    sh.tile_max = whole ? d.C : d.tile_max;
+    sh.W = d.W;
     sh.ends = d.ends;
-    sh.span2_max = d.cs->span2_max;
+    sh.span2_max = whole ? d.C : d.cs->span2_max;
     sh.N = d.N; sh.words = d.words;
     return PERC_OK;
 }
@@ -141,6 +152,11 @@ struct Arena {
         if (base) (void)hipFreeAsync(base, s);
     }
     static size_t align(size_t v) { return (v + 255) & ~(size_t)255; }
+    // bytes take<T>(count) uses (a piece is never empty)
+    template <typename T>
+    static size_t need(size_t count) {
+        return align(sizeof(T) * std::max<size_t>(count, 1));
+    }
     int reserve(size_t bytes, hipStream_t stream) {
         s = stream;
         size = std::max<size_t>(bytes, 256);
@@ -157,6 +173,10 @@ struct Arena {
         T* p = reinterpret_cast<T*>(base + used);
         used += align(sizeof(T) * std::max<size_t>(count, 1));
         return p;
+    }
+    // every piece taken lies inside the reservation (checked before any launch)
+    int check() const {
+        return used <= size ? PERC_OK : fail(PERC_EINVAL, "internal: work memory carved beyond its reservation");
     }
 };
 
@@ -287,6 +307,9 @@ int32_t block_for(const ShapeNeed& nd) {
 // every CU work.
 int32_t cells_for(const ShapeNeed& nd, int32_t form) {
     if (form == FORM_PLAIN) return (int32_t)(std::max<int64_t>(1, std::min<int64_t>(4, nd.items / 8192)) * 8);
+    // a persistent workgroup walks its configuration alone: long walks (batched W=16
+    // L=256 sweep: 32 cells 443 ms, 64 cells 418 ms, 128 cells 408 ms of kernel time)
+    if (form == FORM_PERSIST || form == FORM_PERSIST2) return 128;
     return 64;
 }
 
@@ -324,7 +347,7 @@ int resolve(const ShapeNeed& nd, int64_t state_words, int64_t n_jobs, const perc
         tu.grid = opt->grid;
         tu.graph_steps = opt->graph_steps;
     }
-    if (tu.form < FORM_AUTO || tu.form > FORM_SPAN2) return fail(PERC_EINVAL, "unknown execution form");
+    if (tu.form < FORM_AUTO || tu.form > FORM_PERSIST2) return fail(PERC_EINVAL, "unknown execution form");
     if (tu.form == FORM_AUTO && key) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune.find(*key);
@@ -343,10 +366,19 @@ int resolve(const ShapeNeed& nd, int64_t state_words, int64_t n_jobs, const perc
     if (tu.depth == 0) tu.depth = cells_for(nd, tu.form);
     if (tu.depth < 1 || tu.depth > (1 << 20)) return fail(PERC_EINVAL, "depth (cells per work item) must be 1..2^20");
     tu.depth = (tu.depth + 7) & ~7;  // items are whole pairs of cell groups
+    if (tu.form == FORM_PERSIST2) {
+        // one thread per column of the whole cross-section
+        if (nd.C > kWholeCols)
+            return fail(PERC_EINVAL, "the two-step persistent form needs fibers of at most " +
+                                         std::to_string(kWholeCols) + " columns (W <= 17)");
+        const int32_t bw = std::max<int32_t>(64, ((nd.C + 63) / 64) * 64);
+        if (tu.block == 0) tu.block = bw;
+        if (tu.block < bw) return fail(PERC_EINVAL, "block must hold one thread per column (" + std::to_string(bw) + ")");
+    }
     if (tu.block == 0) tu.block = block_for(nd);
     if (tu.block < 64 || tu.block > 1024 || tu.block % 64)
         return fail(PERC_EINVAL, "block must be 64..1024, a multiple of 64");
-    PERC_TRY(tu.form == FORM_SPAN2 ? check_walk2(nd, tu.block) : check_walk(nd, tu.block));
+    if (tu.form != FORM_PERSIST2) PERC_TRY(tu.form == FORM_SPAN2 ? check_walk2(nd, tu.block) : check_walk(nd, tu.block));
     if (tu.graph_steps == 0) tu.graph_steps = 8;
     if (tu.graph_steps < 1 || tu.graph_steps > 256) return fail(PERC_EINVAL, "graph_steps must be 1..256");
     if (tu.grid < 0) return fail(PERC_EINVAL, "grid must be >= 0");
@@ -401,9 +433,9 @@ void collect_shapes(const std::vector<HostJob>& jobs, Shapes& S) {
     }
 }
 
-int device_shapes(Shapes& S) {
+int device_shapes(Shapes& S, bool whole = false) {
     S.dev.resize(S.lats.size());
-    for (size_t i = 0; i < S.lats.size(); ++i) PERC_TRY(shape_for(S.lats[i], S.dev[i]));
+    for (size_t i = 0; i < S.lats.size(); ++i) PERC_TRY(shape_of(S.lats[i]->d, S.dev[i], whole));
     return PERC_OK;
 }
 
@@ -476,11 +508,11 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
             h_group[b] = hj.group;
         }
         Arena ar;
-        const size_t bytes = Arena::align(sizeof(float) * off) * 2 + Arena::align((size_t)off) +
-                             Arena::align(sizeof(uint32_t) * boff) + Arena::align(sizeof(CfgState) * nb) +
-                             Arena::align(sizeof(int32_t) * nb) * 4 + Arena::align(sizeof(int64_t) * (nb + 1)) * 2 +
-                             Arena::align(sizeof(void*) * nb) + Arena::align(sizeof(Job) * nb) + Arena::align(64) +
-                             (fused ? Arena::align(sizeof(float) * (size_t)nb * S.need.CP) : 0);
+        // every piece as take<>() carves it below (an empty piece still takes 256 bytes)
+        const size_t bytes = Arena::need<float>(off) * 2 + Arena::need<uint8_t>(off) + Arena::need<uint32_t>(boff) +
+                             Arena::need<CfgState>(nb) + Arena::need<int32_t>(nb) * 4 + Arena::need<int64_t>(nb + 1) * 2 +
+                             Arena::need<void*>(nb) + Arena::need<Job>(nb) + Arena::need<int32_t>(16) +
+                             (fused ? Arena::need<float>((size_t)nb * S.need.CP) : 0);
         PERC_TRY(ar.reserve(bytes, s));
         SpanArgs a{};
         a.shapes = d_shapes;
@@ -507,6 +539,7 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
             a.far1 = ar.take<float>((size_t)nb * S.need.CP);
             a.r1_off = (int32_t)lds_ring2_words(S.need.span2_max);
         }
+        PERC_TRY(ar.check());
         std::vector<const uint32_t*> h_bits(nb);
         for (int32_t b = 0; b < nb; ++b) h_bits[b] = h_jobs[b].bits ? h_jobs[b].bits : scratch_bits + h_boff[b];
         HIP_TRY(hipMemcpyAsync(d_shape, h_shape.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
@@ -606,62 +639,84 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
 }
 
 // Persistent form: every job in one launch; scratch per resident workgroup.
-int run_persist(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, const Tuning& tu, hipStream_t s) {
-    const int64_t n = (int64_t)jobs.size();
-    if (n == 0) return PERC_OK;
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    int cus = 0;
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int lds = (int)lds_total(S.need.span_max);
-    int grid = tu.grid;
-    if (grid == 0) grid = cus * std::max(1, persist_resident_per_cu(tu.block, lds));
+// Persistent form: the jobs in chunks whose drawn occupancy fits kPersistBitsBudget; per
+// chunk one sampling launch for the Philox jobs, then one persistent launch over all the
+// chunk's jobs with scratch per resident workgroup.
+constexpr int64_t kPersistBitsBudget = 8ll << 30;
+
+int run_persist_chunk(const std::vector<HostJob>& jobs, int64_t j0, int64_t j1, const Shapes& S, BatchOut out,
+                      const Tuning& tu, int grid, int lds, hipStream_t s) {
+    const int64_t n = j1 - j0;
+    const bool two = tu.form == FORM_PERSIST2;
     grid = (int)std::min<int64_t>(grid, n);
     const int64_t sw = (S.max_state + 63) & ~(int64_t)63;
-    const int64_t bw = (S.max_words + 63) & ~(int64_t)63;
-    bool any_sample = false;
     std::vector<Job> h_jobs(n);
+    std::vector<int64_t> h_idx;
+    int64_t bits_total = 0;
     for (int64_t j = 0; j < n; ++j) {
-        const HostJob& hj = jobs[j];
-        h_jobs[j] = Job{hj.bits, hj.seed, hj.cfg, hj.thr, S.of_job[j], hj.group};
-        any_sample |= hj.bits == nullptr;
+        const HostJob& hj = jobs[j0 + j];
+        h_jobs[j] = Job{hj.bits, hj.seed, hj.cfg, hj.thr, S.of_job[j0 + j], hj.group};
+        if (!hj.bits) {
+            h_idx.push_back(j);
+            bits_total += bits_words(hj.lat->d);
+        }
     }
+    const int64_t n_draw = (int64_t)h_idx.size();
     Arena ar;
-    const size_t bytes = Arena::align(sizeof(float) * grid * sw) * 2 + Arena::align((size_t)grid * sw) +
-                         (any_sample ? Arena::align(sizeof(uint32_t) * grid * bw) : 0) + Arena::align(sizeof(Job) * n) +
-                         Arena::align(sizeof(DevShape) * S.dev.size()) + Arena::align(64);
+    const size_t bytes = Arena::need<float>((size_t)grid * sw) * 2 + Arena::need<uint8_t>((size_t)grid * sw) +
+                         Arena::need<uint32_t>(bits_total) + Arena::need<int64_t>(n_draw) + Arena::need<Job>(n) +
+                         Arena::need<DevShape>(S.dev.size()) + Arena::need<unsigned long long>(3) +
+                         (two ? Arena::need<float>((size_t)grid * S.need.CP) : 0);
     PERC_TRY(ar.reserve(bytes, s));
     PersistArgs a{};
     a.ya = ar.take<float>(grid * sw);
     a.yb = ar.take<float>(grid * sw);
     a.code = ar.take<uint8_t>(grid * sw);
     a.state_stride = sw;
-    a.bits_scratch = any_sample ? ar.take<uint32_t>(grid * bw) : nullptr;
-    a.bits_stride = bw;
+    uint32_t* drawn = ar.take<uint32_t>(bits_total);
+    int64_t* d_idx = ar.take<int64_t>(n_draw);
     Job* d_jobs = ar.take<Job>(n);
     DevShape* d_shapes = ar.take<DevShape>(S.dev.size());
+    int64_t boff = 0;
+    for (int64_t k = 0; k < n_draw; ++k) {
+        Job& jb = h_jobs[h_idx[k]];
+        jb.bits = drawn + boff;
+        boff += bits_words(jobs[j0 + h_idx[k]].lat->d);
+    }
+    if (two) {
+        a.two = 1;
+        a.far1_stride = S.need.CP;
+        a.far1 = ar.take<float>((size_t)grid * S.need.CP);
+        a.r1_off = (int32_t)lds_ring2_words(S.need.C);
+    }
     a.queue = ar.take<unsigned long long>(3);
+    PERC_TRY(ar.check());
     // the cap flag goes to the caller's word when it has one (a synchronous call reads it)
     a.err = out.cap ? out.cap : reinterpret_cast<uint32_t*>(a.queue + 1);
     const bool prof = profiling();
     if (prof) a.work = a.queue + 2;
     HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_shapes, S.dev.data(), sizeof(DevShape) * S.dev.size(), hipMemcpyHostToDevice, s));
+    if (n_draw) HIP_TRY(hipMemcpyAsync(d_idx, h_idx.data(), sizeof(int64_t) * n_draw, hipMemcpyHostToDevice, s));
     a.shapes = d_shapes;
     a.jobs = d_jobs;
     a.n_jobs = n;
     a.out = out;
+    a.out.perc = out.perc + j0;
+    a.out.steps = out.steps + j0;
+    a.out.hit = out.hit ? out.hit + j0 : nullptr;
     a.depth = tu.depth;
     a.block = tu.block;
     a.grid = grid;
     a.lds = lds;
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(a.queue), 6, 0u, s));
+    HIP_TRY(launch_sample_jobs(d_shapes, d_jobs, d_idx, n_draw, s));
     if (!prof) {
         HIP_TRY(launch_persist(a, s));
         return PERC_OK;
     }
-    // profiled: the launch between HIP events on its stream, and the tube slots its
-    // steps advanced (synchronous)
+    // profiled: the persistent launch between HIP events on its stream, and the tube
+    // slots its steps advanced (synchronous)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -683,6 +738,33 @@ int run_persist(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out,
     return PERC_OK;
 }
 
+int run_persist(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, const Tuning& tu, hipStream_t s) {
+    const int64_t n = (int64_t)jobs.size();
+    if (n == 0) return PERC_OK;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const bool two = tu.form == FORM_PERSIST2;
+    // two steps per pass: the whole cross-section is the tile and its own outer range
+    const int lds = (int)(two ? lds_total2(S.need.C, S.need.C) : lds_total(S.need.span_max));
+    int grid = tu.grid;
+    if (grid == 0)
+        grid = cus * std::max(1, two ? persist2_resident_per_cu(tu.block, lds) : persist_resident_per_cu(tu.block, lds));
+    for (int64_t j0 = 0; j0 < n;) {
+        int64_t j1 = j0, words = 0;
+        while (j1 < n) {
+            const int64_t w = jobs[j1].bits ? 0 : bits_words(jobs[j1].lat->d);
+            if (j1 > j0 && (words + w) * 4 > kPersistBitsBudget) break;
+            words += w;
+            ++j1;
+        }
+        PERC_TRY(run_persist_chunk(jobs, j0, j1, S, out, tu, grid, lds, s));
+        j0 = j1;
+    }
+    return PERC_OK;
+}
+
 int validate_lat(const perc_lattice* lat) {
     if (!lat) return fail(PERC_EINVAL, "lattice is NULL");
     return PERC_OK;
@@ -697,8 +779,8 @@ int run_jobs(const std::vector<HostJob>& jobs, BatchOut out, const perc_options*
     if (one) key = TuneKey{S.lats[0]->d.W, S.lats[0]->d.L, size_bucket((int64_t)jobs.size())};
     Tuning tu;
     PERC_TRY(resolve(S.need, S.max_state, (int64_t)jobs.size(), opt, tu, one ? &key : nullptr));
-    PERC_TRY(device_shapes(S));
-    if (tu.form == FORM_PERSIST) return run_persist(jobs, S, out, tu, s);
+    PERC_TRY(device_shapes(S, tu.form == FORM_PERSIST2));
+    if (tu.form == FORM_PERSIST || tu.form == FORM_PERSIST2) return run_persist(jobs, S, out, tu, s);
     return run_span(jobs, S, out, tu, s);
 }
 
@@ -744,6 +826,7 @@ int pi_impl(const perc_lattice* lat, double p, int64_t n_cfg, uint64_t seed, per
     bo.hit = out->hit;
     // [0]: percolating count, [1]: step-cap flag of the persistent form
     unsigned long long* count = ar.take<unsigned long long>(2);
+    PERC_TRY(ar.check());
     bo.cap = reinterpret_cast<uint32_t*>(count + 1);
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(count), 4, 0u, s));
     std::vector<HostJob> jobs(n_cfg);
@@ -785,8 +868,10 @@ int autotune(const std::vector<HostJob>& hj, int64_t n_target, perc_options* bes
     for (int32_t depth : {32, 64, 128}) {
         cands.push_back(perc_options{FORM_SPAN, depth, b0, 0, 16});
         if (b0 + 64 <= 1024) cands.push_back(perc_options{FORM_SPAN, depth, b0 + 64, 0, 16});
-        cands.push_back(perc_options{FORM_PERSIST, depth, b0, 0, 0});
     }
+    for (int32_t depth : {64, 128, 256}) cands.push_back(perc_options{FORM_PERSIST, depth, b0, 0, 0});
+    if (S.need.C <= kWholeCols)
+        for (int32_t depth : {64, 128}) cands.push_back(perc_options{FORM_PERSIST2, depth, 0, 0, 0});
     if (two_step_fits(S.need, b0))
         for (int32_t depth : {64, 128}) cands.push_back(perc_options{FORM_SPAN2, depth, b0, 0, 16});
     const int64_t n = (int64_t)hj.size();
@@ -795,6 +880,7 @@ int autotune(const std::vector<HostJob>& hj, int64_t n_target, perc_options* bes
     BatchOut out;
     out.perc = ar.take<uint8_t>(n);
     out.steps = ar.take<int32_t>(n);
+    PERC_TRY(ar.check());
     double best_t = -1.0;
     perc_options best_o{};
     bool warm = false;
@@ -1418,6 +1504,7 @@ int one_setup(const perc_lattice* lat, const uint32_t* occ_bits, hipStream_t s, 
     int64_t* slot_off = ar.take<int64_t>(n + 1);
     const uint32_t** slot_bits = ar.take<const uint32_t*>(n);
     int64_t* chunk_off = ar.take<int64_t>(n + 1);
+    PERC_TRY(ar.check());
     std::vector<int64_t> h_off(n);
     std::vector<const uint32_t*> h_bits(n);
     for (int64_t i = 0; i < n; ++i) {
@@ -1767,6 +1854,7 @@ int perc_batch(const perc_job* jobs, int64_t n_jobs, uint8_t* perc, int32_t* ste
     // the group counts, then the step-cap flag of the persistent form (read when the call
     // is synchronous)
     unsigned long long* d_groups = ar.take<unsigned long long>(n_groups + 1);
+    PERC_TRY(ar.check());
     if (n_groups > 0) {
         HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(d_groups), 2 * (int64_t)(n_groups + 1), 0u, s));
         out.group_count = d_groups;

@@ -70,8 +70,14 @@ struct ColumnSet {
     // halo-range column lc of tile k, as in `contact`; empty when span_max or span2_max
     // exceeds kMaxSpan2 (the two-step form is not offered for such widths)
     std::vector<uint32_t> contact2;
+    // One tile holding the whole cross-section (no halo), for fibers of at most
+    // kWholeCols columns (one thread per column): the contact table of that tile,
+    // [kSide][C], LDS words relative to column 0. It also serves as the two-step table
+    // (outer range = halo range = all columns). Empty for wider fibers.
+    std::vector<uint32_t> contact_whole;
 };
 constexpr int32_t kMaxSpan2 = 2048;
+constexpr int32_t kWholeCols = 1024;
 
 // The column set of hex radius W, built on first use and kept for the process (one per
 // distinct W; thread safe). Null with a message for a bad W.
@@ -148,6 +154,8 @@ struct ColumnDevice {
     int32_t* sig = nullptr;
     uint32_t* nboff2 = nullptr;
     int32_t* tile2 = nullptr;
+    uint32_t* nboff_whole = nullptr;  // the whole-cross-section tile (null: none)
+    int32_t* tile_whole = nullptr;    // {0, C, 0, C, 0, C}: tile, then its outer range
 };
 
 // Dynamic LDS of the walking kernels: the ring from address 0, 1 + span columns (pad
@@ -178,6 +186,8 @@ enum Form : int32_t {
                        // launch per step over a device-built work list, graph-replayed
     FORM_PERSIST = 3,  // one workgroup per configuration, whole inspection in one launch
     FORM_SPAN2 = 4,    // the span form with two steps per launch (one pass over HBM)
+    FORM_PERSIST2 = 5, // the persistent form with two steps per pass over the whole
+                       // cross-section (fibers of at most kWholeCols columns)
 };
 
 struct Tuning {
@@ -243,6 +253,9 @@ hipError_t launch_sample(const DevShape& sh, uint32_t* bits, int64_t n_cfg, uint
 hipError_t launch_sample_fixed(const DevShape& sh, uint32_t* bits, int64_t n_cfg, uint64_t cfg0, int64_t K,
                                uint64_t seed, hipStream_t s);
 
+// Philox occupancy of jobs idx[0..n): each into the buffer its bits pointer names.
+hipError_t launch_sample_jobs(const DevShape* shapes, const Job* jobs, const int64_t* idx, int64_t n, hipStream_t s);
+
 // Philox occupancy of the slots whose job has no caller bits (jobs indexed by slot).
 hipError_t launch_sample_slots(const DevShape* shapes, const Job* jobs, int32_t n_slot, uint32_t* const* slot_bits,
                                hipStream_t s);
@@ -298,10 +311,8 @@ hipError_t launch_span_finish(const SpanArgs& a, hipStream_t s);     // first-hi
 // Persistent form: one workgroup per job, scratch per resident workgroup.
 struct PersistArgs {
     const DevShape* shapes;
-    const Job* jobs;           // [n_jobs]
+    const Job* jobs;           // [n_jobs], every one with its occupancy bits
     int64_t n_jobs;
-    uint32_t* bits_scratch;    // [grid][bits_stride]
-    int64_t bits_stride;
     float* ya;                 // [grid][state_stride]
     float* yb;
     uint8_t* code;
@@ -314,8 +325,15 @@ struct PersistArgs {
     int32_t block;
     int32_t grid;
     int32_t lds;
+    // two steps per pass (every shape the whole-cross-section tile): first-step far-end
+    // words per workgroup, and the LDS word offset of the inner ring
+    int32_t two;
+    int32_t r1_off;
+    float* far1;               // [grid][far1_stride]
+    int64_t far1_stride;
 };
 hipError_t launch_persist(const PersistArgs& a, hipStream_t s);
+int persist2_resident_per_cu(int block, int lds_bytes);
 
 // Test hook: one step of one configuration over all cells; detector accumulation;
 // export of x = |y| deg (canonical order) and the reach bits, detector last.

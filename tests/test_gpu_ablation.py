@@ -12,7 +12,7 @@ from paper_1401_2130_amd import workloads
 pytestmark = pytest.mark.gpu
 
 U24 = 2.0 ** -24
-FORMS = [("plain", 8), ("span", 8), ("span", 24), ("persist", 16), ("span2", 16)]
+FORMS = [("plain", 8), ("span", 8), ("span", 24), ("persist", 16), ("span2", 16), ("persist2", 16)]
 SHAPES = [(0, 2), (0, 10), (1, 4), (2, 13), (3, 9), (4, 17), (7, 44), (16, 40)]
 
 

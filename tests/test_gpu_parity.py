@@ -48,7 +48,7 @@ def check_hit(hit_gpu, hit_ref, perc_ref, steps_ref):
 
 # (form, cells per work item); the library rounds up to a multiple of 8
 FORMS = [("plain", 8), ("span", 8), ("span", 5), ("span", 24), ("persist", 8), ("persist", 16), ("persist", 64),
-         ("span2", 8), ("span2", 24), ("span2", 64)]
+         ("span2", 8), ("span2", 24), ("span2", 64), ("persist2", 8), ("persist2", 64)]
 
 
 # --------------------------------------------------------------------------------
@@ -176,7 +176,7 @@ def test_edge_cases(perc):
                     for c in cases])
     pm, sm, hm = ref.inspect_markov(occ)
     assert list(pm) == [0, 1, 0, 1, 0]
-    for form in ("plain", "span", "persist"):
+    for form in ("plain", "span", "persist", "persist2"):
         pg, sg, hg = perc.perc_inspect_ex(lat, dev(occ), hit=True, form=form)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(pg.cpu().numpy(), pm)
@@ -307,7 +307,7 @@ def test_pi_batched_workload_sampled(perc):
 # uneven batches: several lattice shapes in one launch
 # --------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("form,depth", [("span", 8), ("span", 16), ("persist", 8), ("plain", 8)])
+@pytest.mark.parametrize("form,depth", [("span", 8), ("span", 16), ("persist", 8), ("plain", 8), ("persist2", 16)])
 def test_batch_of_mixed_shapes(perc, form, depth):
     shapes = [(2, 9), (5, 22), (3, 40), (8, 17), (0, 12), (11, 33)]
     lats = {s: perc.Lattice(*s) for s in shapes}
@@ -451,3 +451,21 @@ def test_largest_serving_fiber(perc, form):
         pb, sb = ref.inspect_bfs(host_words(occ))
         np.testing.assert_array_equal(pg.cpu().numpy(), pb)
         np.testing.assert_array_equal(sg.cpu().numpy(), sb)
+
+
+def test_two_step_persistent_form_limits(perc):
+    """PERC_FORM_PERSIST2 holds the whole cross-section in one workgroup: W = 17 (919
+    columns) runs and equals the one-step persistent form bitwise; W = 18 (1027 columns)
+    is refused with PERC_EINVAL before any work."""
+    lat = perc.Lattice(17, 60)
+    occ = perc.perc_sample(lat, 0.2, 13, 64)
+    a = perc.perc_inspect_ex(lat, occ, hit=True, form="persist")
+    b = perc.perc_inspect_ex(lat, occ, hit=True, form="persist2")
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert np.array_equal(x.cpu().numpy().view(np.uint8), y.cpu().numpy().view(np.uint8))
+    wide = perc.Lattice(18, 30)
+    occw = perc.perc_sample(wide, 0.2, 13, 4)
+    with pytest.raises(perc.PercError) as e:
+        perc.perc_inspect_ex(wide, occw, form="persist2")
+    assert e.value.code == perc.PERC_EINVAL

@@ -78,7 +78,7 @@ def test_large_workload(perc, golden):
         check_group(g, b.cpu().numpy(), s.cpu().numpy())
 
 
-@pytest.mark.parametrize("form", ["persist", "span"])
+@pytest.mark.parametrize("form", ["persist2", "persist", "span"])
 def test_batched_workload(perc, golden, form):
     """W=16 L=256, 21 p x 4096 (seed 3) in one perc_batch call with one group per p:
     all 86,016 configurations, and the Pi(p) counts."""
