@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the percolation inspection on one MI355X.
 
-Workload: fibers of hex radius W=32 and L=1024 layers (1,081,686 tubes), tubes metallic
-with p in {0.14, 0.1533, 0.17}, 256 configurations at each p from Philox seed 2. One
-step is the whole hot path over that batch: occupancy sampling on the device, degree
+Headline workload: fibers of hex radius W=32 and L=1024 layers (1,081,686 tubes), tubes
+metallic with p in {0.14, 0.1533, 0.17}, 256 configurations at each p from Philox seed 2.
+One step is the whole hot path over that batch: occupancy sampling on the device, degree
 codes and start state, the forward iteration to the stop of every configuration, the
 first-hit probabilities and the Pi counts.
 
 Printed (one JSON line on stdout): configurations inspected per second (value),
 site-updates per second (N x steps per configuration, the same count for every form),
-the plain per-configuration form on a sample for comparison, the roofline of the step
-kernel (HIP events on its stream inside the timed region, 8.375 algorithmic bytes per
-tube slot advanced one step) and the CPU oracle timed on the host cores.
+the roofline of the step kernel (HIP events on its stream inside the timed region, 8.375
+algorithmic bytes per tube slot advanced one step) beside the streaming-copy ceiling,
+the other workloads (the small plain one, the batched and uneven sweeps, the serving
+stream) each with its own kernel roofline and its Pi counts checked against the oracle's
+stored results, and the CPU oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -30,6 +32,8 @@ METRIC = "configs inspected/s and site-updates/s (batched vs plain) + % HBM roof
 BYTES_PER_TUBE_STEP = 8.375  # x read + write (4 + 4 B), occupancy bit, reach bit read + write
 HBM_PEAK_GBS = 8000.0
 STEP_KERNEL = "k_span_step"
+STEP_KERNELS = {"span": "k_span_step", "plain": "k_span_step", "span2": "k_span_step2", "persist": "k_persist",
+                "persist2": "k_persist2"}
 
 
 def log(*a):
@@ -91,6 +95,82 @@ def cpu_baseline(wl, budget_s: float):
     }
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_workloads.json")
+
+
+def golden_workloads():
+    """The oracle's stored results of the benchmark workloads (tests/golden, written by a
+    script that calls only the CPU oracle), or None when the file is absent."""
+    if not os.path.exists(GOLDEN):
+        return None
+    with open(GOLDEN) as fh:
+        return json.load(fh)["workloads"]
+
+
+def parity(groups, counts) -> dict:
+    """Pi counts of a leg against the oracle's, group by group."""
+    want = [g["n_perc"] for g in groups]
+    got = [int(c) for c in counts]
+    return {"groups": len(want), "equal": got == want,
+            "mismatches": [i for i, (a, b) in enumerate(zip(got, want)) if a != b][:10]}
+
+
+def kernel_roofline(prof, kernel: str) -> dict:
+    """The step kernel's algorithmic bandwidth over its HIP-event time."""
+    ms, tubes = prof["step_ms"], prof["tube_steps"]
+    gbs = tubes * BYTES_PER_TUBE_STEP / (ms / 1e3) / 1e9 if ms > 0 else None
+    return {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS if gbs else None, "launches": prof["step_launches"], "kernel_ms": ms,
+            "tube_steps": tubes, "bytes_per_tube_step": BYTES_PER_TUBE_STEP}
+
+
+def cpu_other_workloads(workloads, budget_s: float) -> dict:
+    """The CPU oracle (explicit CSR FP64 Markov iteration, host Philox sampling, one
+    configuration per OpenMP thread) on bounded samples of the other workloads: all of
+    the small plain workload, and the first configurations of the batched and uneven
+    sweeps at every p (uneven: the two smallest and the two largest shapes), each for
+    about budget_s seconds."""
+    import numpy as np
+    import oracle
+    cores = oracle.num_threads()
+    out = {}
+
+    def run(name, items, per):
+        """items: (W, L, p, seed); per: configurations per item and pass"""
+        lats, done, t, upd, cfg0 = {}, 0, 0.0, 0, {}
+        while True:
+            for (W, L, p, seed) in items:
+                if (W, L) not in lats:
+                    lats[(W, L)] = oracle.Lattice(W, L)
+                ref = lats[(W, L)]
+                c0 = cfg0.get((W, L, p), 0)
+                t0 = time.perf_counter()
+                pm, sm, _ = ref.inspect_markov(ref.sample(p, seed, per, cfg0=c0), nthreads=cores)
+                t += time.perf_counter() - t0
+                cfg0[(W, L, p)] = c0 + per
+                done += per
+                upd += int(np.sum(sm.astype(np.int64))) * ref.n
+            if t >= budget_s or name == "small":
+                break
+        out[name] = {"value": done / t, "unit": "configs/s", "cores": cores, "kind": "oracle",
+                     "site_updates_per_s": upd / t, "configs": done, "seconds": t}
+
+    sm_ = workloads.SMALL
+    run("small", [(sm_.shapes[0][0], sm_.shapes[0][1], sm_.ps[0], sm_.seed)], sm_.n_cfg)
+    out["small"]["sample"] = "all 1000 configurations of W=4 L=16 p=0.1533 (seed 1)"
+    b = workloads.BATCH
+    run("batched", [(b.shapes[0][0], b.shapes[0][1], p, b.seed) for p in b.ps], cores)
+    out["batched"]["sample"] = (f"configurations 0..{out['batched']['configs'] // len(b.ps) - 1} at each of the 21 p "
+                                f"of W=16 L=256 (seed 3)")
+    u = workloads.UNEVEN
+    shapes = sorted(u.shapes, key=lambda s: s[0] * s[0] * s[1])
+    pick = shapes[:2] + shapes[-2:]
+    run("uneven", [(W, L, p, u.seed) for (W, L) in pick for p in u.ps], cores)
+    out["uneven"]["sample"] = (f"configurations from 0 at both p of shapes {pick} of the aspect-ratio sweep "
+                               f"(seed 4), {out['uneven']['configs']} in all")
+    return out
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -110,8 +190,10 @@ def batched_leg(perc, workloads, stream):
     wl = workloads.BATCH
     (W, L), seed, n = wl.shapes[0], wl.seed, wl.n_cfg
     lat = perc.Lattice(W, L)
-    p_mid = wl.ps[len(wl.ps) // 2]
-    sample = [(lat, p_mid, seed, c) for c in range(512)]
+    # the tuning sample spans the sweep and fills the device several times over (one
+    # workgroup per configuration in the persistent forms): 256 configurations at each
+    # of the 21 p
+    sample = [(lat, p, seed, c) for p in wl.ps for c in range(256)]
     tuned = perc.perc_autotune(sample, n_target=n * len(wl.ps), stream=stream)
     jobs = [(lat, p, seed, c, g) for g, p in enumerate(wl.ps) for c in range(n)]
     opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
@@ -132,15 +214,14 @@ def batched_leg(perc, workloads, stream):
     out = {"workload": f"W={W} L={L} ({lat.n} tubes), p = 0.100..0.200 step 0.005 x {n}, Philox seed {seed}",
            "configs": len(jobs), "configs_per_s": len(jobs) / wall, "wall_s": wall,
            "site_updates_per_s": float(steps.sum()) * lat.n / wall, "autotune": tuned,
-           "kernel_roofline": {"achieved_gbs": prof["tube_steps"] * BYTES_PER_TUBE_STEP / (prof["step_ms"] / 1e3) / 1e9
-                               if prof["step_ms"] > 0 else None,
-                               "frac": prof["tube_steps"] * BYTES_PER_TUBE_STEP / (prof["step_ms"] / 1e3) / 1e9
-                               / HBM_PEAK_GBS if prof["step_ms"] > 0 else None,
-                               "launches": prof["step_launches"], "kernel_ms": prof["step_ms"],
-                               "tube_steps": prof["tube_steps"],
-                               "note": "tube slots of the steps x 8.375 B over the step-kernel time "
-                                       "(the persistent form's one launch also samples and initialises)"},
+           "kernel_roofline": kernel_roofline(prof, STEP_KERNELS[tuned["form"]]),
            "pi": {f"{p:.3f}": float(v) for p, v in zip(wl.ps, pis)}}
+    if tuned["form"] in ("persist", "persist2"):
+        out["kernel_roofline"]["note"] = ("the persistent launch also initialises every configuration and sums its "
+                                          "first-hit probability: its rate is a lower bound")
+    gw = golden_workloads()
+    if gw:
+        out["oracle_parity"] = parity(gw["batched"]["groups"], counts)
     try:
         pc, T, cov = fss.fit_fermi_dirac(wl.ps, pis, n)
         out["eq5_fit"] = {"pc": pc, "T": T, "pc_err": float(np.sqrt(cov[0, 0]))}
@@ -155,19 +236,75 @@ def uneven_leg(perc, workloads, stream):
     from paper_1401_2130_amd import fss
     wl = workloads.UNEVEN
     lats = [perc.Lattice(*sh) for sh in wl.shapes]
-    tuned = perc.perc_autotune([(lat, wl.ps[0], wl.seed, c) for lat in lats for c in range(8)], stream=stream)
+    # the tuning sample spans the sweep: 16 configurations of every shape at both p
+    tuned = perc.perc_autotune([(lat, p, wl.seed, c) for lat in lats for p in wl.ps for c in range(16)],
+                               stream=stream)
     opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
     torch_sync()
     t0 = time.perf_counter()
     counts = fss.pi_table(wl.shapes, wl.ps, wl.n_cfg, wl.seed, stream=stream, **opts)
     torch_sync()
     wall = time.perf_counter() - t0
+    perc.perc_profile_enable(True)
+    fss.pi_table(wl.shapes, wl.ps, wl.n_cfg, wl.seed, stream=stream, **opts)
+    torch_sync()
+    prof = perc.perc_profile_read()
+    perc.perc_profile_enable(False)
     n_jobs = len(wl.shapes) * len(wl.ps) * wl.n_cfg
     ana = fss.uneven_analysis(counts, wl.n_cfg)
-    return {"workload": "W in {8,12,16,24,32} x L/W in {1,2,4,8,16,32,64}, p in {0.1533, 0.16} x 1024, Philox seed 4",
-            "configs": n_jobs, "configs_per_s": n_jobs / wall, "wall_s": wall, "autotune": tuned,
-            "pc_inf": ana.get("pc_inf"), "eq8": ana.get("eq8"),
-            "shapes_with_pc": sum(1 for r in ana["shapes"] if r["pc"] is not None)}
+    out = {"workload": "W in {8,12,16,24,32} x L/W in {1,2,4,8,16,32,64}, p in {0.1533, 0.16} x 1024, Philox seed 4",
+           "configs": n_jobs, "configs_per_s": n_jobs / wall, "wall_s": wall, "autotune": tuned,
+           "kernel_roofline": kernel_roofline(prof, STEP_KERNELS[tuned["form"]]),
+           "pc_inf": ana.get("pc_inf"), "eq8": ana.get("eq8"),
+           "shapes_with_pc": sum(1 for r in ana["shapes"] if r["pc"] is not None)}
+    gw = golden_workloads()
+    if gw:
+        keys = [(g["W"], g["L"], g["p"]) for g in gw["uneven"]["groups"]]
+        out["oracle_parity"] = parity(gw["uneven"]["groups"], [counts[k] for k in keys])
+    return out
+
+
+def small_leg(perc, workloads, stream):
+    """The small plain workload: W=4 L=16 p=0.1533, 1000 configurations one at a time in
+    the plain form (the paper's one-configuration loop, the host checking the stop flags
+    after every step), then all at once in the span form; Pi against the oracle."""
+    import numpy as np
+    wl = workloads.SMALL
+    (W, L), p, seed, n = wl.shapes[0], wl.ps[0], wl.seed, wl.n_cfg
+    lat = perc.Lattice(W, L)
+    occ = perc.perc_sample(lat, p, seed, n, stream=stream)
+    bits = torch_empty(n, "uint8")
+    steps = torch_empty(n, "int32")
+    perc.perc_inspect_ex(lat, occ[:8], 8, perc=bits[:8], steps=steps[:8], form="plain", stream=stream)  # warm-up
+    torch_sync()
+    t0 = time.perf_counter()
+    for i in range(n):
+        perc.perc_inspect_ex(lat, occ[i:i + 1], 1, perc=bits[i:i + 1], steps=steps[i:i + 1], form="plain",
+                             stream=stream)
+    torch_sync()
+    wall = time.perf_counter() - t0
+    st = steps.cpu().numpy().astype(np.int64)
+    n_perc = int(bits.sum().item())
+    torch_sync()
+    t1 = time.perf_counter()
+    n_span, _ = perc.perc_pi_ex(lat, p, n, seed, form="span", stream=stream)
+    torch_sync()
+    wall_span = time.perf_counter() - t1
+    out = {"workload": f"W={W} L={L} ({lat.n} tubes), p = {p} x {n}, Philox seed {seed}",
+           "plain": {"configs_per_s": n / wall, "wall_s": wall, "site_updates_per_s": float(st.sum()) * lat.n / wall,
+                     "ms_per_config": wall / n * 1e3},
+           "span_one_batch": {"configs_per_s": n / wall_span, "wall_s": wall_span},
+           "pi": n_perc / n, "n_perc_plain": n_perc, "n_perc_span": n_span}
+    gw = golden_workloads()
+    if gw:
+        out["oracle_parity"] = parity(gw["small"]["groups"], [n_perc])
+        out["oracle_parity"]["span_equal"] = n_span == gw["small"]["groups"][0]["n_perc"]
+    return out
+
+
+def torch_empty(n, dtype):
+    import torch
+    return torch.empty(n, dtype=getattr(torch, dtype), device="cuda")
 
 
 def hist_summary(h) -> dict:
@@ -316,7 +453,31 @@ def torch_sync():
     torch.cuda.synchronize()
 
 
-def serving_leg(perc, workloads, n: int, rate_hz: float, stream, grid: int = 0, tick: int = 16):
+def serving_kernel_roofline(perc, workloads, n: int, stream, grid: int = 0, tick: int = 16) -> dict:
+    """The first n requests of the serving recipe all arriving at once, served with the
+    step profiler on (steps launched directly between HIP events): the step kernel's
+    roofline over the server's ticks, and every served result against the oracle's
+    stored ones."""
+    base = workloads.serving_requests(n)
+    reqs = [(0.0, W, L, p, i, 0, i) for (_, W, L, p, i) in base]
+    srv = perc.perc_server(hbm_bytes=96 << 30, max_slots=2048, tick_steps=tick, max_w=workloads.SERVING.w_range[1],
+                           grid=grid, stream=stream)
+    perc.perc_profile_enable(True)
+    res = {r["tag"]: r for r in srv.run(reqs)}
+    prof = perc.perc_profile_read()
+    perc.perc_profile_enable(False)
+    del srv
+    out = {"requests": n, "kernel_roofline": kernel_roofline(prof, STEP_KERNEL)}
+    gw = golden_workloads()
+    if gw:
+        rows = [r for r in gw["serving"]["rows"] if r[0] < n]
+        bad = [r[0] for r in rows if (res[r[0]]["perc"], res[r[0]]["steps"]) != (r[4], r[5])]
+        out["oracle_parity"] = {"requests_checked": len(rows), "rule": gw["serving"]["rule"], "equal": not bad,
+                                "mismatches": bad[:10]}
+    return out
+
+
+def serving_leg(perc, workloads, n: int, rate_hz: float, stream, grid: int = 0, tick: int = 16, lookahead: int = 0):
     """Serve the first n requests of the serving recipe (W, L, p per request; Philox seed
     = request id, configuration 0) with arrivals rescaled to rate_hz; latency = completion
     minus scheduled arrival on the host steady clock."""
@@ -325,7 +486,7 @@ def serving_leg(perc, workloads, n: int, rate_hz: float, stream, grid: int = 0, 
     scale = workloads.SERVING.rate_hz / rate_hz
     reqs = [(t * scale, W, L, p, i, 0, i) for (t, W, L, p, i) in base]
     srv = perc.perc_server(hbm_bytes=96 << 30, max_slots=2048, tick_steps=tick, max_w=workloads.SERVING.w_range[1],
-                           grid=grid, stream=stream)
+                           grid=grid, lookahead=lookahead, stream=stream)
     t0 = time.perf_counter()
     res = srv.run(reqs)
     wall = time.perf_counter() - t0
@@ -338,7 +499,7 @@ def serving_leg(perc, workloads, n: int, rate_hz: float, stream, grid: int = 0, 
             "completed_per_s": n / wall, "site_updates_per_s": upd / wall,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "max_ms": float(lat.max()), "percolating": float(np.mean([r["perc"] for r in res])),
-            "ticks": st["ticks"], "tick_steps": tick, "max_slots": 2048, "grid": grid,
+            "ticks": st["ticks"], "tick_steps": tick, "max_slots": 2048, "grid": grid, "lookahead": lookahead,
             "overloaded": bool(wall > 1.5 * span + 1.0)}
 
 
@@ -347,18 +508,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", default="span", choices=["span", "span2", "persist", "auto"])
+    ap.add_argument("--form", default="span", choices=["span", "span2", "persist", "persist2", "auto"])
     ap.add_argument("--depth", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0, help="workgroups per step launch (0: the library's choice)")
     ap.add_argument("--graph-steps", type=int, default=0)
-    ap.add_argument("--plain-sample", type=int, default=4, help="configurations per p for the plain form")
+    ap.add_argument("--plain-sample", type=int, default=64, help="configurations per p for the plain form")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-other-seconds", type=float, default=5.0,
+                    help="CPU oracle seconds on each of the batched and uneven samples (0: skip those)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device to device (counter calibration runs)")
     ap.add_argument("--copy-bandwidth-mib", type=int, default=1024,
-                    help="measure device-to-device copy bandwidth on this many MiB (0: skip)")
+                    help="measure the streaming-copy ceiling on this many MiB (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="serving leg: first requests of the Poisson stream at its own rate (0: skip)")
     ap.add_argument("--serve-low-rate", type=float, default=150.0,
@@ -366,6 +529,10 @@ def main():
     ap.add_argument("--serve-low-requests", type=int, default=450)
     ap.add_argument("--serve-grid", type=int, default=0, help="server step-launch workgroups (0: library default)")
     ap.add_argument("--serve-tick", type=int, default=16, help="steps per server tick")
+    ap.add_argument("--serve-lookahead", type=int, default=0,
+                    help="offered-load run: requests admitted past a waiting head (0: strict FIFO)")
+    ap.add_argument("--serve-profile", type=int, default=1, help="profiled all-at-once serving run (kernel roofline)")
+    ap.add_argument("--small", type=int, default=1, help="small plain workload leg (W=4 L=16 x 1000, one at a time)")
     ap.add_argument("--batched", type=int, default=1, help="batched Pi(p) leg (W=16 L=256, 21 p x 4096)")
     ap.add_argument("--first-passage", type=int, default=1024,
                     help="moves of the backward all-sources leg on the headline fiber (0: skip)")
@@ -453,24 +620,23 @@ def main():
             torch.cuda.synchronize()
             t_plain += time.perf_counter() - t0
             upd_plain += int(st.cpu().numpy().astype(np.int64).sum()) * lat.n
-    log(f"plain form: {3 * k} configurations in {t_plain:.2f} s")
+    log(f"plain form: {len(wl.ps) * k} configurations in {t_plain:.2f} s")
 
-    # achievable HBM bandwidth on this device: a plain device-to-device copy, timed with
-    # events on the same stream (bytes read + written per second)
+    # the practical HBM ceiling on this device: the library's streaming copy (the step
+    # kernel's grid and access pattern, no arithmetic), timed with events on its stream
     copy_gbs = None
     if args.copy_bandwidth_mib > 0:
         src = torch.ones(args.copy_bandwidth_mib * 2 ** 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        with torch.cuda.stream(stream):
-            dst.copy_(src)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(5):
-                dst.copy_(src)
-            e1.record(stream)
+        perc.perc_stream_copy(src, dst, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            perc.perc_stream_copy(src, dst, stream=stream)
+        e1.record(stream)
         e1.synchronize()
-        copy_gbs = 2 * src.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+        copy_gbs = 2 * src.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log(f"streaming copy: {copy_gbs:.0f} GB/s (read + write)")
         del src, dst
 
     launches = max(prof["step_launches"], 1)
@@ -494,27 +660,29 @@ def main():
         "config": {"workload": "W=32 L=1024 fiber (1,081,686 tubes), p in {0.14, 0.1533, 0.17} x 256 "
                                "configurations, Philox seed 2",
                    "form": args.form, "depth": args.depth, "block": args.block},
+        # the work-independent count (N x steps per configuration): the kernels process
+        # only the cells up to front + 1 of each step, so this is a rate of work done, not a
+        # bandwidth; the roofline below prices the cells the step kernel does process
         "site_updates_per_s": site_updates / (elapsed / args.steps),
-        # the work-independent count (N x steps per configuration) priced at the same
-        # 8.375 B: the kernel touches only the cells up to front + 1 of each step, so this
-        # exceeds the bytes it moves; the roofline below uses the cells it does process
-        "site_update_bytes": {"gbs": site_updates / (elapsed / args.steps) * BYTES_PER_TUBE_STEP / 1e9,
-                              "frac": site_updates / (elapsed / args.steps) * BYTES_PER_TUBE_STEP / 1e9 / HBM_PEAK_GBS},
         "graph_replay": {"configs_per_s": n_total * args.steps / elapsed_graph,
                          "ms_per_step": elapsed_graph / args.steps * 1e3,
                          "note": "same steps from captured HIP graphs, no per-launch events"},
         "pi": {str(p): c / n for p, c in zip(wl.ps, counts)},
-        "plain": ({"configs_per_s": 3 * k / t_plain, "site_updates_per_s": upd_plain / t_plain,
+        "plain": ({"configs_per_s": len(wl.ps) * k / t_plain, "site_updates_per_s": upd_plain / t_plain,
                    "sample": f"configurations 0..{k - 1} at each p, one at a time"} if k > 0 else None),
-        "batched_over_plain": (value / (3 * k / t_plain)) if k > 0 else None,
+        "batched_over_plain": (value / (len(wl.ps) * k / t_plain)) if k > 0 else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "copy_gbs": copy_gbs, "frac_of_copy": (achieved / copy_gbs) if copy_gbs else None,
+                     "copy_gbs": copy_gbs, "copy_kernel": "k_stream_copy (perc_stream_copy, 1 GiB)",
+                     "frac_of_copy": (achieved / copy_gbs) if copy_gbs else None,
                      "kernel": STEP_KERNEL, "launches": prof["step_launches"],
                      "avg_launch_us": prof["step_ms"] / launches * 1e3,
                      "tube_steps_per_launch": prof["tube_steps"] / launches,
                      "bytes_per_tube_step": BYTES_PER_TUBE_STEP},
     }
+    gw = golden_workloads()
+    if gw:
+        result["oracle_parity"] = parity(gw["large"]["groups"], counts)
     # the m* (shortest spanning path) distribution of the timed workload, on the device
     result["backbone"] = {"bins": "m* = tubes on the shortest spanning path", "per_p": {}}
     for (b, s, _), p in zip(bufs, wl.ps):
@@ -526,6 +694,10 @@ def main():
         result["first_passage"] = first_passage_leg(perc, workloads, stream, args.first_passage)
         log(f"first passage: {result['first_passage']['ms']:.1f} ms, "
             f"{result['first_passage']['achieved_gbs']:.0f} GB/s")
+    if args.small:
+        log("small plain leg ...")
+        result["small"] = small_leg(perc, workloads, stream)
+        log(f"small: plain {result['small']['plain']['configs_per_s']:.0f} configs/s")
     if args.batched:
         log("batched Pi(p) leg ...")
         result["batched"] = batched_leg(perc, workloads, stream)
@@ -550,11 +722,15 @@ def main():
     if args.serve_requests > 0:
         log(f"serving: {args.serve_requests} requests at {workloads.SERVING.rate_hz:.0f}/s ...")
         result["serving"] = {"offered": serving_leg(perc, workloads, args.serve_requests, workloads.SERVING.rate_hz,
-                                                    stream, args.serve_grid, args.serve_tick)}
+                                                    stream, args.serve_grid, args.serve_tick, args.serve_lookahead)}
         if args.serve_low_requests > 0:
             log(f"serving: {args.serve_low_requests} requests at {args.serve_low_rate:.0f}/s ...")
             result["serving"]["sustainable"] = serving_leg(perc, workloads, args.serve_low_requests,
                                                            args.serve_low_rate, stream, args.serve_grid, args.serve_tick)
+        if args.serve_profile:
+            log("serving: profiled all-at-once run ...")
+            result["serving"]["profiled"] = serving_kernel_roofline(perc, workloads, args.serve_requests, stream,
+                                                                    args.serve_grid, args.serve_tick)
         result["serving"]["workload"] = ("Poisson arrivals (seed 5), W uniform 8..64, L uniform 64..4096, "
                                          "p uniform 0.12..0.19, Philox seed = request id, configuration 0")
         log(f"serving p50/p99: {result['serving']['offered']['p50_ms']:.1f} / "
@@ -562,6 +738,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        if args.cpu_other_seconds > 0:
+            log("cpu baseline (oracle) on the other workloads ...")
+            result["cpu_baseline"]["other_workloads"] = cpu_other_workloads(workloads, args.cpu_other_seconds)
     print(json.dumps(result), flush=True)
 
 

@@ -266,15 +266,24 @@ typedef struct perc_profile {
     int64_t tube_steps;    /* tube slots those launches advanced by one step */
 } perc_profile;
 
-/* Process-wide switch; resets the counters. While on, the span form launches its steps
- * directly (HIP reports no elapsed time for events recorded as graph nodes) with an
- * event pair around each step launch, or around each pair of step launches that run
- * back to back between two plans (counted as two launches), on the caller's stream; the
- * persistent form times
- * its one launch (sampling, initialisation and finishing included, so its rate is a
- * lower bound) and counts the tube slots of its steps, and runs synchronously. */
+/* Process-wide switch; resets the counters. While on, the span form and the server's
+ * ticks launch their steps directly (HIP reports no elapsed time for events recorded as
+ * graph nodes) with an event pair around each step launch, or around each pair of step
+ * launches that run back to back between two plans (counted as two launches), on the
+ * caller's (server's) stream, and count the tube slots the planner schedules; the
+ * persistent form times its one persistent launch (initialisation and finishing
+ * included, so its rate is a lower bound; sampling is a launch of its own) and counts
+ * the tube slots of its steps, and runs synchronously. */
 int perc_profile_enable(int32_t on);
 int perc_profile_read(perc_profile* out);
+
+/* ---- measurement: the HBM ceiling ------------------------------------------------- */
+/* Copy `bytes` (a multiple of 16; src and dst device, 16-byte aligned, not overlapping)
+ * with the step kernels' memory access pattern and none of their arithmetic: `grid`
+ * workgroups of 512 threads (0: the span step's 4096), each copying one contiguous chunk
+ * with 16-byte loads and non-temporal 16-byte stores. Timing it gives the practical
+ * read+write bandwidth the step kernels' HBM traffic is compared with. Async. */
+int perc_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, void* stream);
 
 /* ---- autotuning of the execution settings -------------------------------------- */
 /* Time candidate settings (span form with 32/64/128 cells per work item and one or two

@@ -1678,6 +1678,20 @@ __global__ void __launch_bounds__(256) k_slot_table(int32_t* __restrict__ slot_s
     }
 }
 
+// Streaming copy, the HBM ceiling the step kernels are compared with: each workgroup
+// copies one contiguous chunk with 16-byte loads and non-temporal 16-byte stores (the
+// step kernel's access pattern without the stencil).
+__global__ void __launch_bounds__(512) k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n,
+                                                     int64_t per) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const int64_t b = (int64_t)blockIdx.x * per, e = min(b + per, n);
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+        const uint4 v = src[i];
+        const v4u w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<v4u*>(dst) + i);
+    }
+}
+
 // Work memory of the entry point that allocates nothing (perc_inspect_noalloc): one
 // array per device, part of the code object, kept until the process ends. Host code
 // never passes the array's name to a kernel: it takes the device address once per
@@ -1727,6 +1741,14 @@ hipError_t scratch_region(void** ptr, size_t* bytes) {
     *ptr = addr[dev];
     *bytes = kScratchBytes;
     return hipSuccess;
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, int grid, hipStream_t s) {
+    if (n16 <= 0) return hipSuccess;
+    const int64_t per = (n16 + grid - 1) / grid;
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(512), 0, s, reinterpret_cast<const uint4*>(src),
+                       reinterpret_cast<uint4*>(dst), n16, per);
+    return hipGetLastError();
 }
 
 hipError_t launch_slot_table(int32_t* slot_shape, int64_t* slot_off, const uint32_t** slot_bits, int32_t n,

@@ -1298,6 +1298,11 @@ int server_tick(perc_server* v) {
     }
     hipStream_t s = v->s;
     SpanArgs& a = v->a;
+    // with the step profiler on, the tick launches its steps directly between HIP events
+    // and the planner counts the tube slots it schedules (device word hdr[8..9])
+    const bool prof = profiling();
+    a.work = prof ? reinterpret_cast<unsigned long long*>(a.hdr + 8) : nullptr;
+    StepTimer timer(prof);
     const int32_t k = (int32_t)new_ids.size();
     if (k > 0) {
         for (int32_t i = 0; i < k; ++i) {
@@ -1331,7 +1336,13 @@ int server_tick(perc_server* v) {
         HIP_TRY(launch_span_plan(a, s));
         v->n_act += k;
     }
-    if (v->n_act > 0 || k > 0) {
+    if (prof && (v->n_act > 0 || k > 0)) {
+        for (int i = 0; i < v->cfg.tick_steps; i += a.pair ? 2 : 1) {
+            HIP_TRY(timer.step(a, s));
+            HIP_TRY(launch_span_plan(a, s));
+        }
+        HIP_TRY(launch_span_finish(a, s));
+    } else if (v->n_act > 0 || k > 0) {
         if (!v->exec && s) {
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1373,6 +1384,20 @@ int server_tick(perc_server* v) {
     const int64_t now = steady_ns();
     const int32_t nfin = v->h_hdr[3];
     const bool cap = v->h_hdr[2] != 0;
+    if (prof) {
+        HIP_TRY(timer.collect());
+        unsigned long long tubes = 0;
+        std::memcpy(&tubes, v->h_hdr + 8, sizeof(tubes));
+        if (tubes) {
+            {
+                std::lock_guard<std::mutex> g(g_prof.mu);
+                g_prof.tube_steps += (int64_t)tubes;
+            }
+            static const unsigned long long kZero = 0;
+            HIP_TRY(hipMemcpyAsync(a.hdr + 8, &kZero, sizeof(kZero), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+    }
     for (int32_t i = 0; i < nfin; ++i) {
         const int32_t b = v->h_fin[i];
         ServerSlot& sl = v->slots[b];
@@ -2035,6 +2060,16 @@ int perc_server_run(perc_server* srv, const perc_request* reqs, int64_t n, perc_
     return PERC_OK;
 }
 
+
+int perc_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, void* stream) {
+    if (bytes < 0 || bytes % 16) return fail(PERC_EINVAL, "bytes must be a non-negative multiple of 16");
+    if (bytes > 0 && (!src || !dst)) return fail(PERC_EINVAL, "NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+        return fail(PERC_EINVAL, "src and dst must be 16-byte aligned");
+    if (grid < 0) return fail(PERC_EINVAL, "grid must be >= 0");
+    HIP_TRY(launch_stream_copy(src, dst, bytes / 16, grid ? grid : kSpanGrid, reinterpret_cast<hipStream_t>(stream)));
+    return PERC_OK;
+}
 
 int perc_autotune(const perc_job* jobs, int64_t n_jobs, int64_t n_target, perc_options* best, double* best_ms,
                   void* stream) {

@@ -358,6 +358,9 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 int persist_resident_per_cu(int block, int lds_bytes);
 
+// Streaming copy of n16 16-byte words (perc_stream_copy).
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t n16, int grid, hipStream_t s);
+
 // The fixed work array of perc_inspect_noalloc on the current device: its device address
 // (taken with hipGetSymbolAddress on the first call per device) and size.
 constexpr size_t kScratchBytes = (size_t)256 << 20;
