@@ -182,7 +182,16 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def batched_leg(perc, workloads, stream):
+def leg_settings(perc, sample, n_target, stream, forced):
+    """The autotuner's choice on `sample`, or the forced (form, depth) of a profiling run
+    (a profiler's overhead would change the timings the tuner compares)."""
+    if forced:
+        form, depth = forced
+        return {"form": form, "depth": depth, "block": 0, "graph_steps": 0, "ms": None, "forced": True}
+    return perc.perc_autotune(sample, n_target=n_target, stream=stream)
+
+
+def batched_leg(perc, workloads, stream, forced=None):
     """Batched Monte Carlo: every configuration of the Pi(p) sweep in one batch (one
     output group per p), settings picked by the autotuner on a sample, then the Eq. 5 fit."""
     import numpy as np
@@ -194,7 +203,7 @@ def batched_leg(perc, workloads, stream):
     # workgroup per configuration in the persistent forms): 256 configurations at each
     # of the 21 p
     sample = [(lat, p, seed, c) for p in wl.ps for c in range(256)]
-    tuned = perc.perc_autotune(sample, n_target=n * len(wl.ps), stream=stream)
+    tuned = leg_settings(perc, sample, n * len(wl.ps), stream, forced)
     jobs = [(lat, p, seed, c, g) for g, p in enumerate(wl.ps) for c in range(n)]
     opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
     perc.perc_batch(jobs[:1024], n_groups=len(wl.ps), stream=stream, **opts)  # warm-up
@@ -230,15 +239,15 @@ def batched_leg(perc, workloads, stream):
     return out
 
 
-def uneven_leg(perc, workloads, stream):
+def uneven_leg(perc, workloads, stream, forced=None):
     """Uneven batch: 35 shapes x 2 p x 1024 configurations mixed in one batch; effective
     thresholds per shape and the Eq. 7 / Eq. 8 fits."""
     from paper_1401_2130_amd import fss
     wl = workloads.UNEVEN
     lats = [perc.Lattice(*sh) for sh in wl.shapes]
     # the tuning sample spans the sweep: 16 configurations of every shape at both p
-    tuned = perc.perc_autotune([(lat, p, wl.seed, c) for lat in lats for p in wl.ps for c in range(16)],
-                               stream=stream)
+    tuned = leg_settings(perc, [(lat, p, wl.seed, c) for lat in lats for p in wl.ps for c in range(16)], 0, stream,
+                         forced)
     opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
     torch_sync()
     t0 = time.perf_counter()
@@ -519,7 +528,7 @@ def main():
                     help="CPU oracle seconds on each of the batched and uneven samples (0: skip those)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="first copy this many MiB device to device (counter calibration runs)")
+                    help="first stream this many MiB with k_stream_copy (counter calibration runs)")
     ap.add_argument("--copy-bandwidth-mib", type=int, default=1024,
                     help="measure the streaming-copy ceiling on this many MiB (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -533,6 +542,11 @@ def main():
                     help="offered-load run: requests admitted past a waiting head (0: strict FIFO)")
     ap.add_argument("--serve-profile", type=int, default=1, help="profiled all-at-once serving run (kernel roofline)")
     ap.add_argument("--small", type=int, default=1, help="small plain workload leg (W=4 L=16 x 1000, one at a time)")
+    ap.add_argument("--only", default="", choices=["", "small", "batched", "uneven", "serving"],
+                    help="run this leg alone and print its JSON (profiling runs); not the benchmark line")
+    ap.add_argument("--leg-form", default="", choices=["", "span", "span2", "persist", "persist2"],
+                    help="batched and uneven legs: this form instead of the autotuner's choice (profiling runs)")
+    ap.add_argument("--leg-depth", type=int, default=0, help="cells per work item with --leg-form")
     ap.add_argument("--batched", type=int, default=1, help="batched Pi(p) leg (W=16 L=256, 21 p x 4096)")
     ap.add_argument("--first-passage", type=int, default=1024,
                     help="moves of the backward all-sources leg on the headline fiber (0: skip)")
@@ -554,9 +568,32 @@ def main():
     import paper_1401_2130_amd as perc
     from paper_1401_2130_amd import workloads
 
+    torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        # a copy of known size in the same process, for scaling the traffic counters
+        src = torch.ones(args.copy_calibration_mib * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        perc.perc_stream_copy(src, dst)
+        torch.cuda.synchronize()
+        log(f"streamed {args.copy_calibration_mib} MiB for counter calibration (k_stream_copy)")
+        del src, dst
+    forced = (args.leg_form, args.leg_depth) if args.leg_form else None
+    if args.only:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            if args.only == "small":
+                res = small_leg(perc, workloads, stream)
+            elif args.only == "batched":
+                res = batched_leg(perc, workloads, stream, forced)
+            elif args.only == "uneven":
+                res = uneven_leg(perc, workloads, stream, forced)
+            else:
+                res = serving_kernel_roofline(perc, workloads, args.serve_requests, stream, args.serve_grid,
+                                              args.serve_tick)
+        print(json.dumps({args.only: res}), flush=True)
+        return
     wl = workloads.LARGE
     (W, L), seed, n = wl.shapes[0], wl.seed, wl.n_cfg
-    torch.cuda.set_device(0)
     lat = perc.Lattice(W, L)
     stream = torch.cuda.Stream()
     bufs = [(torch.empty(n, dtype=torch.uint8, device="cuda"), torch.empty(n, dtype=torch.int32, device="cuda"),
@@ -569,15 +606,6 @@ def main():
             n_perc, _ = perc.perc_pi_ex(lat, p, n, seed, bits=b, steps=s, hit=h, stream=stream, **opts)
             counts.append(n_perc)
         return counts
-
-    if args.copy_calibration_mib:
-        src = torch.ones(args.copy_calibration_mib * 2 ** 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copied {args.copy_calibration_mib} MiB for counter calibration")
-        del src, dst
 
     with torch.cuda.stream(stream):
         for i in range(args.warmup):
@@ -700,11 +728,11 @@ def main():
         log(f"small: plain {result['small']['plain']['configs_per_s']:.0f} configs/s")
     if args.batched:
         log("batched Pi(p) leg ...")
-        result["batched"] = batched_leg(perc, workloads, stream)
+        result["batched"] = batched_leg(perc, workloads, stream, forced)
         log(f"batched: {result['batched']['configs_per_s']:.0f} configs/s, fit {result['batched'].get('eq5_fit')}")
     if args.uneven:
         log("uneven aspect-ratio leg ...")
-        result["uneven"] = uneven_leg(perc, workloads, stream)
+        result["uneven"] = uneven_leg(perc, workloads, stream, forced)
         log(f"uneven: {result['uneven']['configs_per_s']:.0f} configs/s, pc_inf {result['uneven']['pc_inf']}")
     if args.ablation:
         log("ablation leg (regular FCC) ...")

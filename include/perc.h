@@ -30,6 +30,12 @@
  *    ordinary memory. `stream` is a hipStream_t (NULL = the default stream). Calls
  *    marked async enqueue work on `stream` and return; the caller keeps every buffer
  *    alive until the stream is synchronised.
+ *  - Work memory: pieces under 64 MiB are taken stream-ordered from the device's
+ *    memory pool; larger work memory comes from one buffer per device that the library
+ *    keeps between calls (it grows in 1 GiB steps to the largest need seen, at most
+ *    about 48 GiB for the batched forms) and lends to one call at a time, stream-ordered
+ *    behind the previous borrower's work; a call that finds it lent to another thread
+ *    allocates its own. perc_trim releases it.
  *  - Errors: a negative PERC_E* code; perc_last_error() gives a message (per thread,
  *    valid until the next call on that thread). No call aborts the process.
  */
@@ -145,8 +151,8 @@ int perc_sample_fixed(const perc_lattice* lat, double p, uint64_t seed, int64_t 
 
 /* Decide percolation of n_cfg >= 0 configurations given as canonical occupancy bits
  * (device, n_cfg * words uint32). perc (device, n_cfg bytes) receives 0/1 and steps
- * (device, n_cfg int32, may be NULL) the step counts. Async. Work memory is taken
- * stream-ordered from the device pool and returned before the call's work completes. */
+ * (device, n_cfg int32, may be NULL) the step counts. Async (work memory as the
+ * conventions above state). */
 int perc_inspect(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cfg, uint8_t* perc,
                  int32_t* steps, void* stream);
 
@@ -284,6 +290,12 @@ int perc_profile_read(perc_profile* out);
  * with 16-byte loads and non-temporal 16-byte stores. Timing it gives the practical
  * read+write bandwidth the step kernels' HBM traffic is compared with. Async. */
 int perc_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, void* stream);
+
+/* ---- work memory ----------------------------------------------------------------- */
+/* Release the work buffer the library keeps on the current device (waiting for the work
+ * of its last borrower first). PERC_EBUSY if a call is using it; the next call that
+ * needs large work memory allocates it again. */
+int perc_trim(void);
 
 /* ---- autotuning of the execution settings -------------------------------------- */
 /* Time candidate settings (span form with 32/64/128 cells per work item and one or two

@@ -110,6 +110,7 @@ def _load():
     lib.perc_profile_read.argtypes = [C.POINTER(perc_profile)]
     lib.perc_autotune.argtypes = [C.POINTER(perc_job), i64, i64, C.POINTER(perc_options), C.POINTER(dbl), vp]
     lib.perc_stream_copy.argtypes = [vp, vp, i64, i32, vp]
+    lib.perc_trim.argtypes = []
     lib.perc_server_create.restype = vp
     lib.perc_server_create.argtypes = [C.POINTER(perc_server_config), vp]
     lib.perc_server_destroy.argtypes = [vp]
@@ -129,7 +130,7 @@ EXPORTED = ("perc_lattice_create", "perc_lattice_create_ex", "perc_lattice_destr
             "perc_last_error", "perc_sample", "perc_sample_fixed", "perc_inspect", "perc_inspect_ex", "perc_inspect_noalloc",
             "perc_pi", "perc_pi_ex",
             "perc_batch", "perc_state_after", "perc_first_passage", "perc_first_passage_batch", "perc_steps_hist", "perc_profile_enable", "perc_profile_read", "perc_autotune",
-            "perc_stream_copy",
+            "perc_stream_copy", "perc_trim",
             "perc_server_create",
             "perc_server_destroy", "perc_server_submit", "perc_server_cancel", "perc_server_tick", "perc_server_poll",
             "perc_server_stats_read", "perc_server_run")
@@ -379,6 +380,11 @@ def perc_stream_copy(src: torch.Tensor, dst: torch.Tensor, grid: int = 0, stream
     if dst.numel() * dst.element_size() < nbytes:
         raise ValueError("dst is smaller than src")
     _check(_lib.perc_stream_copy(_dptr(src), _dptr(dst), int(nbytes), int(grid), _stream(stream)))
+
+
+def perc_trim() -> None:
+    """Release the work buffer the library keeps between calls on the current device."""
+    _check(_lib.perc_trim())
 
 
 def perc_profile_enable(on: bool) -> None:
