@@ -3,9 +3,10 @@
 
 Headline workload: fibers of hex radius W=32 and L=1024 layers (1,081,686 tubes), tubes
 metallic with p in {0.14, 0.1533, 0.17}, 256 configurations at each p from Philox seed 2.
-One step is the whole hot path over that batch: occupancy sampling on the device, degree
-codes and start state, the forward iteration to the stop of every configuration, the
-first-hit probabilities and the Pi counts.
+One step is the whole hot path over that batch, one perc_batch call of its 768 jobs with
+one Pi group per p: occupancy sampling on the device, degree codes and start state, the
+forward iteration to the stop of every configuration, the first-hit probabilities and the
+Pi counts.
 
 Printed (one JSON line on stdout): configurations inspected per second (value),
 site-updates per second (N x steps per configuration, the same count for every form),
@@ -55,7 +56,8 @@ def traffic_from_profiles(tube_steps_per_launch: float):
         d = json.load(fh)
     if d.get("kernels_sha") != kernel_source_sha():
         return None
-    return d.get("hbm_bytes_per_launch")
+    # the measured bytes per tube slot, at this run's tube slots per launch
+    return d["hbm_bytes_per_tube_step"] * tube_steps_per_launch
 
 
 def cpu_baseline(wl, budget_s: float):
@@ -596,15 +598,19 @@ def main():
     (W, L), seed, n = wl.shapes[0], wl.seed, wl.n_cfg
     lat = perc.Lattice(W, L)
     stream = torch.cuda.Stream()
-    bufs = [(torch.empty(n, dtype=torch.uint8, device="cuda"), torch.empty(n, dtype=torch.int32, device="cuda"),
-             torch.empty(n, dtype=torch.float32, device="cuda")) for _ in wl.ps]
+    n_total = n * len(wl.ps)
+    bits_all = torch.empty(n_total, dtype=torch.uint8, device="cuda")
+    steps_all_t = torch.empty(n_total, dtype=torch.int32, device="cuda")
+    hit_all = torch.empty(n_total, dtype=torch.float32, device="cuda")
+    bufs = [(bits_all[k * n:(k + 1) * n], steps_all_t[k * n:(k + 1) * n], hit_all[k * n:(k + 1) * n])
+            for k in range(len(wl.ps))]
+    # one batch of every (p, configuration) job, one Pi group per p
+    jobs = [(lat, p, seed, c, k) for k, p in enumerate(wl.ps) for c in range(n)]
     opts = dict(form=args.form, depth=args.depth, block=args.block, graph_steps=args.graph_steps, grid=args.grid)
 
     def step():
-        counts = []
-        for (b, s, h), p in zip(bufs, wl.ps):
-            n_perc, _ = perc.perc_pi_ex(lat, p, n, seed, bits=b, steps=s, hit=h, stream=stream, **opts)
-            counts.append(n_perc)
+        _, _, _, counts = perc.perc_batch(jobs, n_groups=len(wl.ps), perc=bits_all, steps=steps_all_t, hit=hit_all,
+                                          stream=stream, **opts)
         return counts
 
     with torch.cuda.stream(stream):
@@ -631,7 +637,6 @@ def main():
         elapsed_graph = time.perf_counter() - t0
         log(f"graph-replayed steps: {elapsed_graph / args.steps * 1e3:.1f} ms/step")
 
-    n_total = n * len(wl.ps)
     steps_all = np.concatenate([s.cpu().numpy().astype(np.int64) for _, s, _ in bufs])
     site_updates = int(steps_all.sum()) * lat.n
     value = n_total * args.steps / elapsed
@@ -687,6 +692,7 @@ def main():
         "data": "synthetic: occupancy drawn on the device from Philox4x32-10, seed 2",
         "config": {"workload": "W=32 L=1024 fiber (1,081,686 tubes), p in {0.14, 0.1533, 0.17} x 256 "
                                "configurations, Philox seed 2",
+                   "call": "perc_batch: 768 jobs, one Pi group per p",
                    "form": args.form, "depth": args.depth, "block": args.block},
         # the work-independent count (N x steps per configuration): the kernels process
         # only the cells up to front + 1 of each step, so this is a rate of work done, not a

@@ -66,7 +66,7 @@ def test_small_workload(perc, golden, form):
 
 def test_large_workload(perc, golden):
     """W=32 L=1024 at p in {0.14, 0.1533, 0.17} x 256 (seed 2), the headline workload,
-    through perc_pi_ex in the span form the benchmark times: all 768 configurations."""
+    through perc_pi_ex in the span form, one call per p: all 768 configurations."""
     groups = golden["large"]["groups"]
     assert len(groups) == 3
     lat = perc.Lattice(groups[0]["W"], groups[0]["L"])
@@ -76,6 +76,21 @@ def test_large_workload(perc, golden):
         n_perc, _ = perc.perc_pi_ex(lat, g["p"], g["n"], g["seed"], bits=b, steps=s, form="span")
         assert n_perc == g["n_perc"]
         check_group(g, b.cpu().numpy(), s.cpu().numpy())
+
+
+def test_large_workload_one_batch(perc, golden):
+    """The same 768 configurations as one perc_batch call with one Pi group per p, the
+    call the benchmark times."""
+    groups = golden["large"]["groups"]
+    lat = perc.Lattice(groups[0]["W"], groups[0]["L"])
+    n = groups[0]["n"]
+    jobs = [(lat, g["p"], g["seed"], c, k) for k, g in enumerate(groups) for c in range(n)]
+    pg, sg, _, counts = perc.perc_batch(jobs, n_groups=len(groups), hit=True, form="span")
+    torch.cuda.synchronize()
+    bits, steps = pg.cpu().numpy(), sg.cpu().numpy()
+    assert counts == [g["n_perc"] for g in groups]
+    for k, g in enumerate(groups):
+        check_group(g, bits[k * n:(k + 1) * n], steps[k * n:(k + 1) * n])
 
 
 @pytest.mark.parametrize("form", ["persist2", "persist", "span"])
