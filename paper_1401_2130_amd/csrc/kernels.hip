@@ -334,16 +334,19 @@ struct StepState {
 template <int K>
 __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, const Own& w, const float4* ct,
                                           const float* __restrict__ yin, float* __restrict__ yout,
-                                          const uint32_t* __restrict__ code4, int u8, int front, int vmax,
+                                          const uint32_t* __restrict__ code4, int u8, int ue, int front, int vmax,
                                           int top_min, StepState& ss) {
     constexpr int k = K & 3, par = K >> 2;
     const int u = u8 + K, g = u >> 2;
     if (k & 1) __syncthreads();
     if (k == 1) {
         put_quads<(par ^ 1) * 4>(st, g + 1, vmax, ss.next);
-        load_quads(sh, st, yin, g + 2, vmax, ss.next);
-        // the code word of the next eight cells, once per eight cells
-        if (K == 1) ss.cq[1] = code4[(uint32_t)min((u8 >> 3) + 1, (sh.U - 1) >> 3) * sh.CP + w.c];
+        // group g + 2 only if a cell the walk computes reads it: the cells of the last
+        // group the walk enters, (ue - 1) / 4, read one group further (a uniform branch;
+        // a skipped load leaves words that no computed cell reads)
+        if (g + 2 <= ((ue - 1) >> 2) + 1) load_quads(sh, st, yin, g + 2, vmax, ss.next);
+        // the code word of the next eight cells, once per eight cells, if the walk gets there
+        if (K == 1 && u8 + 8 < ue) ss.cq[1] = code4[(uint32_t)min((u8 >> 3) + 1, (sh.U - 1) >> 3) * sh.CP + w.c];
     }
     const uint32_t cd = (ss.cq[0] >> (4 * K)) & 0xfu;
     if (K == 7) ss.cq[0] = ss.cq[1];
@@ -405,15 +408,15 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
     ss.cq[1] = 0xffffffffu;  // (g0 is even: the first word covers g0 and g0 + 1)
     __syncthreads();
     for (int u8 = ub; u8 < ue; u8 += kRingCells) {
-        step_cell<0>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
-        step_cell<1>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
-        step_cell<2>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
-        step_cell<3>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
+        step_cell<0>(sh, st, w, ct, yin, yout, code4, u8, ue, front_chk, vmax, top_min, ss);
+        step_cell<1>(sh, st, w, ct, yin, yout, code4, u8, ue, front_chk, vmax, top_min, ss);
+        step_cell<2>(sh, st, w, ct, yin, yout, code4, u8, ue, front_chk, vmax, top_min, ss);
+        step_cell<3>(sh, st, w, ct, yin, yout, code4, u8, ue, front_chk, vmax, top_min, ss);
         if (u8 + 4 >= ue) break;
-        step_cell<4>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
-        step_cell<5>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
-        step_cell<6>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
-        step_cell<7>(sh, st, w, ct, yin, yout, code4, u8, front_chk, vmax, top_min, ss);
+        step_cell<4>(sh, st, w, ct, yin, yout, code4, u8, ue, front_chk, vmax, top_min, ss);
+        step_cell<5>(sh, st, w, ct, yin, yout, code4, u8, ue, front_chk, vmax, top_min, ss);
+        step_cell<6>(sh, st, w, ct, yin, yout, code4, u8, ue, front_chk, vmax, top_min, ss);
+        step_cell<7>(sh, st, w, ct, yin, yout, code4, u8, ue, front_chk, vmax, top_min, ss);
     }
     return (ss.grew ? F_GREW : 0u) | (ss.far ? F_FAR : 0u) | (ss.entered ? F_FRONT : 0u) |
            (ss.entered2 ? F_FRONT2 : 0u);
