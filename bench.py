@@ -204,9 +204,9 @@ def batched_leg(perc, workloads, stream, forced=None):
     # the tuning sample spans the sweep and fills the device several times over (one
     # workgroup per configuration in the persistent forms): 256 configurations at each
     # of the 21 p
-    sample = [(lat, p, seed, c) for p in wl.ps for c in range(256)]
+    sample = np.concatenate([perc.philox_jobs(lat, p, seed, 256) for p in wl.ps])
     tuned = leg_settings(perc, sample, n * len(wl.ps), stream, forced)
-    jobs = [(lat, p, seed, c, g) for g, p in enumerate(wl.ps) for c in range(n)]
+    jobs = np.concatenate([perc.philox_jobs(lat, p, seed, n, group=g) for g, p in enumerate(wl.ps)])
     opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
     perc.perc_batch(jobs[:1024], n_groups=len(wl.ps), stream=stream, **opts)  # warm-up
     torch_sync()
@@ -248,8 +248,9 @@ def uneven_leg(perc, workloads, stream, forced=None):
     wl = workloads.UNEVEN
     lats = [perc.Lattice(*sh) for sh in wl.shapes]
     # the tuning sample spans the sweep: 16 configurations of every shape at both p
-    tuned = leg_settings(perc, [(lat, p, wl.seed, c) for lat in lats for p in wl.ps for c in range(16)], 0, stream,
-                         forced)
+    import numpy as np
+    sample = np.concatenate([perc.philox_jobs(lat, p, wl.seed, 16) for lat in lats for p in wl.ps])
+    tuned = leg_settings(perc, sample, 0, stream, forced)
     opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
     torch_sync()
     t0 = time.perf_counter()
@@ -605,7 +606,7 @@ def main():
     bufs = [(bits_all[k * n:(k + 1) * n], steps_all_t[k * n:(k + 1) * n], hit_all[k * n:(k + 1) * n])
             for k in range(len(wl.ps))]
     # one batch of every (p, configuration) job, one Pi group per p
-    jobs = [(lat, p, seed, c, k) for k, p in enumerate(wl.ps) for c in range(n)]
+    jobs = np.concatenate([perc.philox_jobs(lat, p, seed, n, group=k) for k, p in enumerate(wl.ps)])
     opts = dict(form=args.form, depth=args.depth, block=args.block, graph_steps=args.graph_steps, grid=args.grid)
 
     def step():

@@ -16,6 +16,7 @@ import ctypes as C
 import os
 from typing import Optional
 
+import numpy as np
 import torch  # loaded first so that libperc.so binds to the same HIP runtime
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -46,6 +47,13 @@ class perc_profile(C.Structure):
 class perc_job(C.Structure):
     _fields_ = [("lat", C.c_void_p), ("occ_bits", C.c_void_p), ("p", C.c_double), ("seed", C.c_uint64),
                 ("cfg", C.c_int64), ("group", C.c_int32)]
+
+
+# perc_job as a numpy record, for building large job arrays without a Python loop
+JOB_DTYPE = np.dtype({"names": ["lat", "occ_bits", "p", "seed", "cfg", "group"],
+                      "formats": [np.uint64, np.uint64, np.float64, np.uint64, np.int64, np.int32],
+                      "offsets": [getattr(perc_job, f).offset for f in ("lat", "occ_bits", "p", "seed", "cfg", "group")],
+                      "itemsize": C.sizeof(perc_job)})
 
 
 class perc_server_config(C.Structure):
@@ -318,9 +326,34 @@ def perc_pi_ex(lat: Lattice, p: float, n_cfg: int, seed: int, bits=None, steps=N
     return int(out.n_perc), float(out.pi)
 
 
+def philox_jobs(lat: "Lattice", p: float, seed: int, n_cfg: int, cfg0: int = 0, group: int = -1) -> np.ndarray:
+    """Jobs (lat, p, seed, cfg) for cfg = cfg0 .. cfg0+n_cfg-1 as a JOB_DTYPE array, the
+    fast form of the job list for perc_batch / perc_autotune (concatenate several with
+    numpy). The array holds the lattice's handle: keep the Lattice alive while it is used."""
+    a = np.zeros(n_cfg, dtype=JOB_DTYPE)
+    a["lat"] = lat.handle
+    a["p"] = float(p)
+    a["seed"] = int(seed) & (2**64 - 1)
+    a["cfg"] = np.arange(cfg0, cfg0 + n_cfg, dtype=np.int64)
+    a["group"] = group
+    return a
+
+
 def _job_array(jobs):
     """perc_job array of (lattice, occ[, group]) or (lattice, p, seed, cfg[, group]) tuples,
-    and the tensors it points into (kept alive by the caller)."""
+    or of a JOB_DTYPE numpy array (used in place), and what it points into (kept alive by
+    the caller)."""
+    if isinstance(jobs, np.ndarray):
+        if jobs.dtype.names != JOB_DTYPE.names:
+            raise TypeError("a numpy job array must have the fields of JOB_DTYPE")
+        if jobs.dtype != JOB_DTYPE or not jobs.flags.c_contiguous:
+            # numpy packs a structured dtype when it concatenates: copy the fields back
+            # into the struct layout (padding zero)
+            out = np.zeros(len(jobs), dtype=JOB_DTYPE)
+            for name in JOB_DTYPE.names:
+                out[name] = jobs[name]
+            jobs = out
+        return jobs.ctypes.data_as(C.POINTER(perc_job)), [jobs]
     n = len(jobs)
     arr = (perc_job * max(n, 1))()
     keep = []

@@ -190,12 +190,12 @@ def pi_table(shapes: Iterable[Tuple[int, int]], ps: Sequence[float], n_cfg: int,
     import paper_1401_2130_amd as perc
     shapes = list(shapes)
     lats = {s: perc.Lattice(*s, ends=ends) for s in shapes}
-    jobs, keys = [], []
+    blocks, keys = [], []
     for (W, L) in shapes:
         for p in ps:
-            g = len(keys)
+            blocks.append(perc.philox_jobs(lats[(W, L)], float(p), seed, n_cfg, group=len(keys)))
             keys.append((W, L, float(p)))
-            jobs += [(lats[(W, L)], float(p), seed, c, g) for c in range(n_cfg)]
+    jobs = np.concatenate(blocks) if blocks else np.zeros(0, dtype=perc.JOB_DTYPE)
     _, _, _, counts = perc.perc_batch(jobs, n_groups=len(keys), stream=stream, **opts)
     return {k: int(c) for k, c in zip(keys, counts)}
 

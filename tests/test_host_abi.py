@@ -114,3 +114,21 @@ def test_length_bound_keeps_stream_tags_distinct():
             oracle.Lattice(W, L)
     tags = {(W << 16) | L for W in (0, 1, 2, 1024) for L in (1, 2, 65535)}
     assert len(tags) == 12
+
+
+def test_numpy_job_array_matches_the_struct():
+    """philox_jobs builds, without a Python loop, the bytes of the perc_job array that
+    the tuple form marshals element by element."""
+    assert perc.JOB_DTYPE.itemsize == C.sizeof(perc.perc_job)
+    lat = perc.Lattice(3, 9)
+    a = perc.philox_jobs(lat, 0.3, 2**64 + 7, 5, cfg0=2, group=1)
+    arr_t, _ = perc._job_array([(lat, 0.3, 7, c, 1) for c in range(2, 7)])
+    arr_n, keep = perc._job_array(a)
+    n = 5 * C.sizeof(perc.perc_job)
+    assert C.string_at(arr_t, n) == C.string_at(arr_n, n) == a.tobytes()
+    # numpy packs the record when it concatenates; the binding restores the layout
+    both = np.concatenate([a, a])
+    arr_c, keep_c = perc._job_array(both)
+    assert C.string_at(arr_c, 2 * n) == a.tobytes() * 2
+    with pytest.raises(TypeError):
+        perc._job_array(np.zeros(3, dtype=np.int64))
