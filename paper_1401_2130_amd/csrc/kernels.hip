@@ -383,6 +383,10 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
 // written for cells of the last group at or beyond the cut are zero (their inputs are
 // beyond the front) or lie in the padding beyond U: no other item writes them and no
 // reader uses them.
+// LEAD: the three leading groups are loaded together (one memory latency before the
+// first cell instead of two; the persistent form's walks, one per tile and step, gain
+// from it, the span form's do not).
+template <bool LEAD = false>
 __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& tv, const float4* ct,
                                               const float* __restrict__ yin, float* __restrict__ yout,
                                               const uint8_t* __restrict__ code, int ub, int ue, int front,
@@ -399,11 +403,20 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
     zero_pad();
     StepState ss;
     uint4 q[kLoadCols];
-    load_quads(sh, st, yin, g0 - 1, vmax, q);
-    put_quads<4>(st, g0 - 1, vmax, q);
-    load_quads(sh, st, yin, g0, vmax, q);
-    put_quads<0>(st, g0, vmax, q);
-    load_quads(sh, st, yin, g0 + 1, vmax, ss.next);
+    if (LEAD) {
+        uint4 q0[kLoadCols];
+        load_quads(sh, st, yin, g0 - 1, vmax, q);
+        load_quads(sh, st, yin, g0, vmax, q0);
+        load_quads(sh, st, yin, g0 + 1, vmax, ss.next);
+        put_quads<4>(st, g0 - 1, vmax, q);
+        put_quads<0>(st, g0, vmax, q0);
+    } else {
+        load_quads(sh, st, yin, g0 - 1, vmax, q);
+        put_quads<4>(st, g0 - 1, vmax, q);
+        load_quads(sh, st, yin, g0, vmax, q);
+        put_quads<0>(st, g0, vmax, q);
+        load_quads(sh, st, yin, g0 + 1, vmax, ss.next);
+    }
     ss.cq[0] = code4[code_word_g(sh, g0, w.c)];
     ss.cq[1] = 0xffffffffu;  // (g0 is even: the first word covers g0 and g0 + 1)
     __syncthreads();
@@ -785,6 +798,9 @@ __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, c
 // 8) from the occupancy, and the start state (group 0): x0 = 1/|S0| on every metallic
 // start tube, reached. Returns the initialisation flags (start set non-empty, a start
 // tube on the far surface).
+// LEAD: the three leading groups of occupancy are loaded together (the span form's
+// initialisation launch gains from it; the persistent form keeps its registers).
+template <bool LEAD = false>
 __device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& tv, const float4* ct,
                                               const uint32_t* __restrict__ bits, uint8_t* __restrict__ code,
                                               float* __restrict__ y0, int ub, int ue, float x0) {
@@ -801,11 +817,20 @@ __device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& t
     zero_pad();
     InitState is;
     uint32_t raw[4][kLoadCols];
-    load_occ_quad(sh, st, rk, bits, g0 - 1, raw);
-    put_occ_quad<4>(sh, st, rk, g0 - 1, raw);
-    load_occ_quad(sh, st, rk, bits, g0, raw);
-    put_occ_quad<0>(sh, st, rk, g0, raw);
-    load_occ_quad(sh, st, rk, bits, g0 + 1, is.next);
+    if (LEAD) {
+        uint32_t raw0[4][kLoadCols];
+        load_occ_quad(sh, st, rk, bits, g0 - 1, raw);
+        load_occ_quad(sh, st, rk, bits, g0, raw0);
+        load_occ_quad(sh, st, rk, bits, g0 + 1, is.next);
+        put_occ_quad<4>(sh, st, rk, g0 - 1, raw);
+        put_occ_quad<0>(sh, st, rk, g0, raw0);
+    } else {
+        load_occ_quad(sh, st, rk, bits, g0 - 1, raw);
+        put_occ_quad<4>(sh, st, rk, g0 - 1, raw);
+        load_occ_quad(sh, st, rk, bits, g0, raw);
+        put_occ_quad<0>(sh, st, rk, g0, raw);
+        load_occ_quad(sh, st, rk, bits, g0 + 1, is.next);
+    }
     __syncthreads();
     for (int u8 = ub; u8 < ue; u8 += kRingCells) {
         init_cell<0>(sh, st, w, rk, ct, bits, code4, y0, u8, ue, x0, is);
@@ -1160,7 +1185,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
             x0 = n0 > 0 ? 1.0f / (float)n0 : 0.0f;
         }
         const int64_t off = uniform_i64(a.slot_off + b);
-        const uint32_t fl = walk_init(sh, load_tile(sh, k), tl.ct, bits, a.code + off, a.ya + off, ub, ub + E, x0);
+        const uint32_t fl = walk_init<true>(sh, load_tile(sh, k), tl.ct, bits, a.code + off, a.ya + off, ub, ub + E, x0);
         if (ub == 0) flags_to(&a.st[b].flags, fl);
     }
 }
@@ -1483,7 +1508,7 @@ __device__ __forceinline__ void persist_body(const PersistArgs& a) {
                 uint32_t fl = 0;
                 for (int ub = 0; ub < ulim; ub += E)
                     for (int k = 0; k < sh.ntile; ++k)
-                        fl |= walk_step(sh, load_tile(sh, k), tl.ct, yin, yout, code, ub, ub + E, front, front);
+                        fl |= walk_step<true>(sh, load_tile(sh, k), tl.ct, yin, yout, code, ub, ub + E, front, front);
                 __syncthreads();
                 if (threadIdx.x == 0) tl.misc[0] = 0;
                 __syncthreads();
