@@ -403,15 +403,19 @@ __device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& t
     zero_pad();
     StepState ss;
     uint4 q[kLoadCols];
+    // group g0 - 1 lies below the fiber when the walk starts at its base: its words are
+    // written as zero and nothing is loaded (a uniform branch)
+#pragma unroll
+    for (int j = 0; j < kLoadCols; ++j) q[j] = make_uint4(0u, 0u, 0u, 0u);
     if (LEAD) {
         uint4 q0[kLoadCols];
-        load_quads(sh, st, yin, g0 - 1, vmax, q);
+        if (g0 > 0) load_quads(sh, st, yin, g0 - 1, vmax, q);
         load_quads(sh, st, yin, g0, vmax, q0);
         load_quads(sh, st, yin, g0 + 1, vmax, ss.next);
         put_quads<4>(st, g0 - 1, vmax, q);
         put_quads<0>(st, g0, vmax, q0);
     } else {
-        load_quads(sh, st, yin, g0 - 1, vmax, q);
+        if (g0 > 0) load_quads(sh, st, yin, g0 - 1, vmax, q);
         put_quads<4>(st, g0 - 1, vmax, q);
         load_quads(sh, st, yin, g0, vmax, q);
         put_quads<0>(st, g0, vmax, q);
@@ -816,16 +820,17 @@ __device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& t
     __syncthreads();
     zero_pad();
     InitState is;
-    uint32_t raw[4][kLoadCols];
+    // (group g0 - 1 below the fiber: masked to zero, not loaded)
+    uint32_t raw[4][kLoadCols] = {};
     if (LEAD) {
         uint32_t raw0[4][kLoadCols];
-        load_occ_quad(sh, st, rk, bits, g0 - 1, raw);
+        if (g0 > 0) load_occ_quad(sh, st, rk, bits, g0 - 1, raw);
         load_occ_quad(sh, st, rk, bits, g0, raw0);
         load_occ_quad(sh, st, rk, bits, g0 + 1, is.next);
         put_occ_quad<4>(sh, st, rk, g0 - 1, raw);
         put_occ_quad<0>(sh, st, rk, g0, raw0);
     } else {
-        load_occ_quad(sh, st, rk, bits, g0 - 1, raw);
+        if (g0 > 0) load_occ_quad(sh, st, rk, bits, g0 - 1, raw);
         put_occ_quad<4>(sh, st, rk, g0 - 1, raw);
         load_occ_quad(sh, st, rk, bits, g0, raw);
         put_occ_quad<0>(sh, st, rk, g0, raw);
