@@ -1479,11 +1479,12 @@ __device__ __forceinline__ void persist_body(const PersistArgs& a) {
             tl.misc[3] = (uint32_t)(c >> 32);
         }
         __syncthreads();
-        const int64_t j = (int64_t)(((uint64_t)tl.misc[3] << 32) | tl.misc[2]);
-        if (j >= a.n_jobs) {
+        const int64_t q = (int64_t)(((uint64_t)tl.misc[3] << 32) | tl.misc[2]);
+        if (q >= a.n_jobs) {
             if (threadIdx.x == 0 && a.work && work) atomicAdd(a.work, work);
             break;
         }
+        const int64_t j = uniform_i64(a.order + q);  // outputs stay indexed by job
         const Job job = uniform_load(a.jobs + j);
         const DevShape sh = uniform_load(a.shapes + job.shape);
         const uint32_t* bits = job.bits;  // the caller's, or drawn by k_sample_jobs beforehand

@@ -756,9 +756,23 @@ int run_persist_chunk(const std::vector<HostJob>& jobs, int64_t j0, int64_t j1, 
         }
     }
     const int64_t n_draw = (int64_t)h_idx.size();
+    // queue order: longest expected inspections first, so that the launch does not end
+    // with every workgroup on a long one: larger fibers first, then higher p (the
+    // expected step count grows with p up to the threshold and stays high above it);
+    // caller-given occupancy (p unknown) last, in job order
+    std::vector<int64_t> h_order(n);
+    for (int64_t j = 0; j < n; ++j) h_order[j] = j;
+    std::stable_sort(h_order.begin(), h_order.end(), [&](int64_t x, int64_t y) {
+        const HostJob& a = jobs[j0 + x];
+        const HostJob& b = jobs[j0 + y];
+        if (a.lat->d.N != b.lat->d.N) return a.lat->d.N > b.lat->d.N;
+        if ((a.bits == nullptr) != (b.bits == nullptr)) return a.bits == nullptr;
+        return a.thr > b.thr;
+    });
     Arena ar;
     const size_t bytes = Arena::need<float>((size_t)grid * sw) * 2 + Arena::need<uint8_t>((size_t)grid * sw) +
                          Arena::need<uint32_t>(bits_total) + Arena::need<int64_t>(n_draw) + Arena::need<Job>(n) +
+                         Arena::need<int64_t>(n) +
                          Arena::need<DevShape>(S.dev.size()) + Arena::need<unsigned long long>(3) +
                          (two ? Arena::need<float>((size_t)grid * S.need.CP) : 0);
     PERC_TRY(ar.reserve(bytes, s));
@@ -770,6 +784,7 @@ int run_persist_chunk(const std::vector<HostJob>& jobs, int64_t j0, int64_t j1, 
     uint32_t* drawn = ar.take<uint32_t>(bits_total);
     int64_t* d_idx = ar.take<int64_t>(n_draw);
     Job* d_jobs = ar.take<Job>(n);
+    int64_t* d_order = ar.take<int64_t>(n);
     DevShape* d_shapes = ar.take<DevShape>(S.dev.size());
     int64_t boff = 0;
     for (int64_t k = 0; k < n_draw; ++k) {
@@ -792,8 +807,10 @@ int run_persist_chunk(const std::vector<HostJob>& jobs, int64_t j0, int64_t j1, 
     HIP_TRY(hipMemcpyAsync(d_jobs, h_jobs.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_shapes, S.dev.data(), sizeof(DevShape) * S.dev.size(), hipMemcpyHostToDevice, s));
     if (n_draw) HIP_TRY(hipMemcpyAsync(d_idx, h_idx.data(), sizeof(int64_t) * n_draw, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_order, h_order.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
     a.shapes = d_shapes;
     a.jobs = d_jobs;
+    a.order = d_order;
     a.n_jobs = n;
     a.out = out;
     a.out.perc = out.perc + j0;

@@ -317,7 +317,8 @@ struct PersistArgs {
     float* yb;
     uint8_t* code;
     int64_t state_stride;
-    unsigned long long* queue;  // next job to take
+    unsigned long long* queue;  // next position of `order` to take
+    const int64_t* order;       // [n_jobs] the job at each queue position (longest expected first)
     uint32_t* err;              // set when a configuration reached the step cap
     unsigned long long* work;   // tube slots the steps advanced (nullable)
     BatchOut out;
