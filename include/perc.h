@@ -32,10 +32,10 @@
  *    alive until the stream is synchronised.
  *  - Work memory: pieces under 64 MiB are taken stream-ordered from the device's
  *    memory pool; larger work memory comes from one buffer per device that the library
- *    keeps between calls (it grows in 1 GiB steps to the largest need seen, at most
- *    about 48 GiB for the batched forms) and lends to one call at a time, stream-ordered
- *    behind the previous borrower's work; a call that finds it lent to another thread
- *    allocates its own. perc_trim releases it.
+ *    keeps between calls (it grows in 1 GiB steps to the largest need seen; a batch
+ *    runs in waves of at most 128 GiB and half the free memory) and lends to one call
+ *    at a time, stream-ordered behind the previous borrower's work; a call that finds
+ *    it lent to another thread allocates its own. perc_trim releases it.
  *  - Errors: a negative PERC_E* code; perc_last_error() gives a message (per thread,
  *    valid until the next call on that thread). No call aborts the process.
  */
