@@ -232,6 +232,23 @@ int cache_trim() {
     return PERC_OK;
 }
 
+// A device allocation that, when the device is short of memory, releases the idle work
+// buffer (above) and tries once more.
+int device_alloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        if (cache_trim() == PERC_OK) e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? PERC_ENOMEM : PERC_EHIP,
+                    std::string("device allocation of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    }
+    return PERC_OK;
+}
+
 // ---------------------------------------------------------------------------------
 // Work memory of one call: one allocation (the cached buffer when large) carved into
 // aligned pieces.
@@ -256,6 +273,10 @@ struct Arena {
         size = std::max<size_t>(bytes, 256);
         if (size >= kCacheMin && (base = cache_borrow(size, s, &cached))) return PERC_OK;
         hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base), size, s);
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            if (cache_trim() == PERC_OK) e = hipMallocAsync(reinterpret_cast<void**>(&base), size, s);
+        }
         if (e != hipSuccess) {
             base = nullptr;
             return fail(PERC_ENOMEM, std::string("work memory of ") + std::to_string(size) + " bytes: " +
@@ -1189,7 +1210,7 @@ int server_init(perc_server* v, const perc_server_config* cfg, hipStream_t s) {
         if (v->host_only) return fail(PERC_EINVAL, "host_only needs an explicit hbm_bytes");
         size_t free_b = 0, total_b = 0;
         HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-        c.hbm_bytes = std::min<int64_t>((int64_t)(free_b / 2), 64ll << 30);
+        c.hbm_bytes = std::min<int64_t>((int64_t)((free_b + cache_idle_bytes()) / 2), 64ll << 30);
     }
     // pool: per state word 9 bytes (two FP32 buffers, and one byte of code region, of
     // which the four-bit codes use half), occupancy words an eighth of the state words (a
@@ -1233,7 +1254,7 @@ int server_init(perc_server* v, const perc_server_config* cfg, hipStream_t s) {
                           al((int64_t)sizeof(DevShape) * M) + al(4ll * M) + al(8ll * M) + al(8ll * M) +
                           al((int64_t)sizeof(Job) * M) + al(8ll * M) + al(4ll * M) + al((int64_t)sizeof(CfgState) * M) +
                           al(4ll * M) * 2 + al(8ll * (M + 1)) + al(64) + al(4ll * M) + al(M) + al(4ll * M) * 2;
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&v->mem), (size_t)bytes));
+    PERC_TRY(device_alloc(reinterpret_cast<void**>(&v->mem), (size_t)bytes));
     char* p = v->mem;
     v->ya = carve<float>(p, v->state_cap);
     v->yb = carve<float>(p, v->state_cap);
