@@ -298,7 +298,7 @@ int perc_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, vo
 int perc_trim(void);
 
 /* ---- autotuning of the execution settings -------------------------------------- */
-/* Time candidate settings (span form with 32/64/128 cells per work item and one or two
+/* Time candidate settings (span form with 32/64/80/128 cells per work item and one or two
  * block sizes, persistent form with 64/128/256, the two-step forms where the shapes allow
  * them) on the sample `jobs` (as perc_batch; group must be -1; a sample spread over the
  * batch's p values and shapes represents it best) and return the fastest in *best (wall

@@ -426,7 +426,10 @@ int32_t cells_for(const ShapeNeed& nd, int32_t form) {
     // a persistent workgroup walks its configuration alone: long walks (batched W=16
     // L=256 sweep: 32 cells 443 ms, 64 cells 418 ms, 128 cells 408 ms of kernel time)
     if (form == FORM_PERSIST || form == FORM_PERSIST2) return 128;
-    return 64;
+    // span: fewer boundary groups per cell than 64-cell items, still fine-grained enough
+    // for the end of a launch (W=32 L=1024 x 768: 48 cells 3.85 TB/s, 64 3.92, 80 3.95,
+    // 96 3.93 of step kernel)
+    return 80;
 }
 
 int check_walk(const ShapeNeed& nd, int32_t block) {
@@ -1001,7 +1004,7 @@ int autotune(const std::vector<HostJob>& hj, int64_t n_target, perc_options* bes
     collect_shapes(hj, S);
     const int32_t b0 = block_for(S.need);
     std::vector<perc_options> cands;
-    for (int32_t depth : {32, 64, 128}) {
+    for (int32_t depth : {32, 64, 80, 128}) {
         cands.push_back(perc_options{FORM_SPAN, depth, b0, 0, 16});
         if (b0 + 64 <= 1024) cands.push_back(perc_options{FORM_SPAN, depth, b0 + 64, 0, 16});
     }
