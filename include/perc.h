@@ -214,8 +214,11 @@ typedef struct perc_job {
  * persistent launch, or one span launch per step over every job). perc (device,
  * n_jobs bytes), steps and hit (device, n_jobs entries, may be NULL) are indexed by job.
  * group_count (host, n_groups int64) receives the number of percolating jobs of each
- * group; the call is synchronous when n_groups > 0, else async. The batch is packed
- * largest-first and run in the form `opt` names (NULL = automatic). */
+ * group; the call is synchronous when n_groups > 0, else async. The batch runs in the
+ * form `opt` names (NULL = automatic): the span form in waves of consecutive jobs that
+ * fit the work-memory budget (one wave when the whole batch fits), the persistent form
+ * handing out the largest fibers first and, among equal ones, the highest p first (the
+ * longest expected inspections). */
 int perc_batch(const perc_job* jobs, int64_t n_jobs, uint8_t* perc, int32_t* steps, float* hit,
                int64_t* group_count, int32_t n_groups, const perc_options* opt, void* stream);
 
