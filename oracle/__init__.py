@@ -11,9 +11,9 @@ Functions and the passage of the paper each one follows:
   Fig. 1): 12 side contacts at the FCC nearest-neighbour distance, 2 end contacts
   along the column.
 * :func:`philox4x32_10`, :meth:`Lattice.sample` -- Bernoulli(p) occupancy (Sec. II.A)
-  from Philox4x32-10 (Salmon et al., SC'11). Parity unpinned against third-party
-  known-answer vectors; pinned by uniformity tests, host/device equality and a shift
-  identity of the key schedule against the closed forms of its Weyl increments.
+  from Philox4x32-10 (Salmon et al., SC'11), pinned by the generator's published
+  known-answer outputs, uniformity tests, host/device equality and a shift identity of
+  the key schedule against the closed forms of its Weyl increments.
 * :meth:`Lattice.inspect_markov` -- Eq. (1)-(2) with the detector site of Sec. II.B,
   forward FP64 iteration plus the exact support that decides "non-zero probability".
 * :meth:`Lattice.state_after` -- the same iteration for exactly K steps.

@@ -18,10 +18,9 @@
  *                distance predicate.
  *   sampler   -- Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), written from the
  *                published round function; Bernoulli(p) per site (Sec. II.A, <N_m>=Np).
- *                Parity unpinned against third-party known-answer vectors (none are
- *                available offline); pinned by uniformity tests, host/device equality
- *                and a key-schedule shift identity against the closed forms of the
- *                Weyl increments.
+ *                Pinned by the generator's published known-answer outputs, uniformity
+ *                tests, host/device equality and a key-schedule shift identity against
+ *                the closed forms of the Weyl increments.
  *   markov    -- the transition matrix of Eq. (2) built explicitly in CSR over the
  *                metallic sites plus the detector site j1 joined to every metallic site
  *                of the far end surface (Sec. II.B); forward power iteration x <- x P

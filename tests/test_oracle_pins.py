@@ -382,6 +382,20 @@ def test_philox_output_uniform():
     assert not np.array_equal(a, b) and not np.array_equal(a, c)
 
 
+def test_philox_known_answers():
+    """The oracle's Philox4x32-10 reproduces the published known-answer outputs of the
+    generator (tests/golden/philox4x32_10_kat.txt), which fixes its multipliers, Weyl
+    increments, round count and word order; the device sampler is bit-exact against the
+    oracle (GPU tests), so it is pinned too."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        w = [int(x, 16) for x in r]
+        out = oracle.philox4x32_10(w[0:4], w[4:6])
+        assert [int(x) for x in out] == w[6:10], r
+
+
 def test_philox_key_schedule_shift():
     """Pins the round count and key schedule of the oracle's Philox4x32-10 (Salmon et
     al., SC'11) against the closed forms of the published Weyl increments,
