@@ -1136,6 +1136,12 @@ __global__ void __launch_bounds__(256) k_sample_jobs(const DevShape* shapes, con
 // Item layout of the initialisation (all cells of every slot) and the slot states.
 // Slots to initialise: the listed ones (a.ids), else all.
 __device__ __forceinline__ int init_count(const SpanArgs& a) { return a.ids ? a.n_ids : a.n_slot; }
+// Lazy initialisation: the cells an extension adds (whole items, more than the margin),
+// and the cells initialised at first (all of them without lazy initialisation).
+__device__ __forceinline__ int ext_cells(const SpanArgs& a) {
+    return ((a.init_margin + a.depth) / a.depth) * a.depth;
+}
+__device__ __forceinline__ int init_horizon(const SpanArgs& a, int U) { return a.lazy ? min(U, ext_cells(a)) : U; }
 __device__ __forceinline__ int init_slot(const SpanArgs& a, int i) { return a.ids ? a.ids[i] : i; }
 
 __global__ void __launch_bounds__(kMaxBlock) k_span_layout(SpanArgs a) {
@@ -1148,8 +1154,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_layout(SpanArgs a) {
     for (int i = i0; i < i1; ++i) {
         const int b = init_slot(a, i);
         const DevShape& sh = a.shapes[a.slot_shape[b]];
-        mine += items_of(sh, sh.U, a.depth);
-        a.st[b] = CfgState{0, -1, 0, 0u, 0u, 0};  // m = -1: initialised, not yet decided
+        const int hz = init_horizon(a, sh.U);
+        mine += items_of(sh, hz, a.depth);
+        a.st[b] = CfgState{0, -1, 0, 0u, 0u, 0, hz, -1, 0};  // m = -1: initialised, not yet decided
     }
     sums[tid] = mine;
     __syncthreads();
@@ -1163,7 +1170,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_layout(SpanArgs a) {
     for (int i = i0; i < i1; ++i) {
         a.chunk_off[i] = pos;
         const DevShape& sh = a.shapes[a.slot_shape[init_slot(a, i)]];
-        pos += items_of(sh, sh.U, a.depth);
+        pos += items_of(sh, init_horizon(a, sh.U), a.depth);
     }
     if (tid == nt - 1) a.chunk_off[n] = sums[nt - 1];
 }
@@ -1192,6 +1199,32 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_init(SpanArgs a) {
         const int64_t off = uniform_i64(a.slot_off + b);
         const uint32_t fl = walk_init<true>(sh, load_tile(sh, k), tl.ct, bits, a.code + off, a.ya + off, ub, ub + E, x0);
         if (ub == 0) flags_to(&a.st[b].flags, fl);
+    }
+}
+
+// Lazy initialisation: the degree codes of the ranges [hz_from, hz) of the slots the last
+// plan listed (items: listed slot, cell range, tile). Counts its launches in hdr[7], which
+// tells the planner that the ranges listed before it are done.
+__global__ void __launch_bounds__(kMaxBlock) k_span_extend(SpanArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.hdr + 7, 1);
+    const int n = uniform_i32(a.hdr + 6);
+    if (n == 0) return;
+    const Tail tl = lds_tail(a.lds);
+    fill_codes(tl.ct);
+    const int E = a.depth;
+    const ItemRange it = my_items(uniform_i64(a.ext_off + n));
+    int i = it.begin < it.end ? find_entry(a.ext_off, n, it.begin) : 0;
+    for (int64_t g = it.begin; g < it.end; g += it.stride) {
+        i = advance_entry(a.ext_off, n, i, g);
+        const int b = uniform_i32(a.ext_ids + i);
+        const DevShape sh = uniform_load(a.shapes + uniform_i32(a.slot_shape + b));
+        const int base = uniform_i32(&a.st[b].hz_from);
+        const int local = (int)(g - uniform_i64(a.ext_off + i));
+        const int r = local / sh.ntile, k = local - r * sh.ntile;
+        const int ub = base + r * E;  // > 0: the start state is not touched
+        const uint32_t* bits = reinterpret_cast<const uint32_t*>(uniform_i64(reinterpret_cast<const int64_t*>(a.slot_bits + b)));
+        const int64_t off = uniform_i64(a.slot_off + b);
+        (void)walk_init<true>(sh, load_tile(sh, k), tl.ct, bits, a.code + off, a.ya + off, ub, ub + E, 0.0f);
     }
 }
 
@@ -1229,13 +1262,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
     __shared__ int32_t keep_s[kMaxBlock / 64];
     __shared__ int64_t chunk_s[kMaxBlock / 64];
     __shared__ int64_t chunk2_s[kMaxBlock / 64];
+    __shared__ int32_t ext_s[kMaxBlock / 64];
+    __shared__ int64_t exti_s[kMaxBlock / 64];
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int gen = a.lazy ? a.hdr[7] : 0;  // extension launches done so far
     const int n_act = first ? a.n_slot : a.hdr[0];
     const int per = (n_act + nt - 1) / nt;
     const int i0 = min(n_act, tid * per), i1 = min(n_act, i0 + per);
     const int E = a.depth;
-    int32_t keep = 0;
-    int64_t chunks = 0;
+    int32_t keep = 0, ext = 0;
+    int64_t chunks = 0, ext_items = 0;
     for (int i = i0; i < i1; ++i) {
         const int b = first ? i : a.active[i];
         const DevShape& sh = a.shapes[a.slot_shape[b]];
@@ -1280,6 +1316,18 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         } else {
             keep += 1;
             chunks += items_of(sh, min(sh.U, s.front + (a.fused || a.pair ? 3 : 2)), E);
+            if (a.lazy) {
+                if (s.hz_from >= 0 && gen > s.ext_gen) s.hz_from = -1;  // its range is computed
+                if (s.hz_from < 0 && s.hz < sh.U && s.front + a.init_margin >= s.hz) {
+                    s.hz_from = s.hz;
+                    s.hz = min(sh.U, s.hz + ext_cells(a));
+                    s.ext_gen = gen;
+                }
+                if (s.hz_from >= 0) {
+                    ext += 1;
+                    ext_items += items_of(sh, s.hz - s.hz_from, E);
+                }
+            }
         }
         a.st[b] = s;
     }
@@ -1287,6 +1335,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
     int64_t n_chunks;
     int32_t kpos = block_scan(keep, keep_s, &n_keep) - keep;
     int64_t cpos = block_scan(chunks, chunk_s, &n_chunks) - chunks;
+    int32_t n_ext = 0;
+    int64_t n_ext_items = 0;
+    int32_t epos = 0;
+    int64_t eoff = 0;
+    const bool lst = a.lazy && a.list_ext;  // only the plan before an extension launch lists
+    if (lst) {
+        epos = block_scan(ext, ext_s, &n_ext) - ext;
+        eoff = block_scan(ext_items, exti_s, &n_ext_items) - ext_items;
+    }
     // A work list shorter than what the device runs at once (the last, slowest
     // configurations of a batch): items of a half, a quarter or an eighth of the depth
     // (whole octets of cells), as long as the list stays within that size, so that the
@@ -1320,6 +1377,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         cpos += items_of(sh, min(sh.U, s.front + (a.fused || a.pair ? 3 : 2)), Eu);
         // tube slots advanced by one step each; two steps per plan count the window twice
         tubes += (unsigned long long)min(sh.U, s.front + 2) * (unsigned long long)sh.C * (a.fused || a.pair ? 2ull : 1ull);
+        if (lst && s.hz_from >= 0) {  // listed for the next extension launch
+            a.ext_ids[epos] = b;
+            a.ext_off[epos] = eoff;
+            epos += 1;
+            eoff += items_of(sh, s.hz - s.hz_from, E);
+        }
     }
     if (a.work && tubes) atomicAdd(a.work, tubes);
     __syncthreads();
@@ -1329,6 +1392,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_span_plan(SpanArgs a, int first) 
         a.hdr[0] = n_keep;
         a.hdr[1] = (int32_t)min(n_chunks, (int64_t)INT32_MAX);
         a.hdr[5] = Eu;
+        if (lst) {
+            a.hdr[6] = n_ext;
+            a.ext_off[n_ext] = n_ext_items;
+        }
     }
 }
 
@@ -1748,6 +1815,7 @@ hipError_t prepare_kernels(int device) {
     if (e != hipSuccess) return e;
     if (cur != device) return hipErrorInvalidDevice;
     e = allow_lds(k_span_init);
+    if (e == hipSuccess) e = allow_lds(k_span_extend);
     if (e == hipSuccess) e = allow_lds(k_span_step);
     if (e == hipSuccess) e = allow_lds(k_span_step2);
     if (e == hipSuccess) e = allow_lds(k_chunk_step);
@@ -1874,6 +1942,11 @@ hipError_t launch_span_init(const SpanArgs& a, hipStream_t s) {
 hipError_t launch_span_step(const SpanArgs& a, hipStream_t s) {
     if (a.fused) return launch_span_step2(a, s);
     hipLaunchKernelGGL(k_span_step, dim3(a.grid), dim3(a.block), a.lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_span_extend(const SpanArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_span_extend, dim3(a.grid), dim3(a.block), a.lds, s, a);
     return hipGetLastError();
 }
 

@@ -328,6 +328,14 @@ bool profiling() {
 
 SpanArgs second_of(const SpanArgs& a);  // the second launch of a pair
 
+// The plan launch's arguments; the last plan of a run of steps lists the slots for the
+// extension launch that starts the next run.
+SpanArgs last_plan(const SpanArgs& a, bool last) {
+    SpanArgs b = a;
+    b.list_ext = last ? 1 : 0;
+    return b;
+}
+
 class StepTimer {
   public:
     explicit StepTimer(bool on) : on_(on) {}
@@ -634,6 +642,7 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
         const size_t bytes = Arena::need<float>(off) * 2 + Arena::need<uint8_t>(off) + Arena::need<uint32_t>(boff) +
                              Arena::need<CfgState>(nb) + Arena::need<int32_t>(nb) * 4 + Arena::need<int64_t>(nb + 1) * 2 +
                              Arena::need<void*>(nb) + Arena::need<Job>(nb) + Arena::need<int32_t>(16) +
+                             Arena::need<int32_t>(nb) + Arena::need<int64_t>(nb + 1) +
                              (fused ? Arena::need<float>((size_t)nb * S.need.CP) : 0);
         PERC_TRY(ar.reserve(bytes, s));
         SpanArgs a{};
@@ -652,9 +661,16 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
         uint32_t** d_bits = ar.take<uint32_t*>(nb);
         Job* d_jobs = ar.take<Job>(nb);
         a.hdr = ar.take<int32_t>(16);
+        a.ext_ids = ar.take<int32_t>(nb);
+        a.ext_off = ar.take<int64_t>(nb + 1);
         // the span form runs two one-step launches between plans (the planner decides
         // both steps), which halves the planner launches
         a.pair = (!fused && !plain && kSpanPairs) ? 1 : 0;
+        // lazy initialisation (not for the plain form, which polls after every step): a
+        // run of steps between two extension launches is graph_steps plans of two steps
+        // each; the margin covers it, the window past the front and a group
+        a.lazy = plain ? 0 : 1;
+        a.init_margin = 2 * tu.graph_steps + 12;
         if (fused) {
             a.fused = 1;
             a.far1_stride = S.need.CP;
@@ -702,11 +718,11 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
             if (use_graph) {
                 hipGraph_t graph = nullptr;
                 HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                hipError_t ce = hipSuccess;
+                hipError_t ce = a.lazy ? launch_span_extend(a, s) : hipSuccess;
                 for (int i = 0; i < tu.graph_steps && ce == hipSuccess; ++i) {
                     ce = launch_span_step(a, s);
                     if (ce == hipSuccess && a.pair) ce = launch_span_step(second_of(a), s);
-                    if (ce == hipSuccess) ce = launch_span_plan(a, s);
+                    if (ce == hipSuccess) ce = launch_span_plan(last_plan(a, i == tu.graph_steps - 1), s);
                 }
                 hipError_t ee = hipStreamEndCapture(s, &graph);
                 if (ce != hipSuccess) {
@@ -726,9 +742,13 @@ int run_span(const std::vector<HostJob>& jobs, const Shapes& S, BatchOut out, co
                         hipError_t e = hipGraphLaunch(exec, s);
                         if (e != hipSuccess) rc = hip_fail(e, "hipGraphLaunch");
                     } else {
+                        if (a.lazy) {
+                            hipError_t e = launch_span_extend(a, s);
+                            if (e != hipSuccess) rc = hip_fail(e, "span extend");
+                        }
                         for (int i = 0; i < tu.graph_steps && rc == PERC_OK; ++i) {
                             hipError_t e = timer.step(a, s);
-                            if (e == hipSuccess) e = launch_span_plan(a, s);
+                            if (e == hipSuccess) e = launch_span_plan(last_plan(a, i == tu.graph_steps - 1), s);
                             if (e != hipSuccess) rc = hip_fail(e, "span step");
                         }
                     }

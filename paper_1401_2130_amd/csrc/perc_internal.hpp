@@ -210,6 +210,9 @@ struct CfgState {
     uint32_t flags;   // OR of the flags of the last launch (its first step); cleared by the planner
     uint32_t flags2;  // second-step flags of a two-step launch; cleared by the planner
     int32_t par;      // state buffer holding the newest state: 0 = ya, 1 = yb
+    int32_t hz;       // degree codes are computed for cells [0, hz)
+    int32_t hz_from;  // >= 0: cells [hz_from, hz) await the next extension launch
+    int32_t ext_gen;  // extension launches done when hz_from was set
 };
 
 constexpr uint32_t F_GREW = 1u;      // some tube joined the reached set
@@ -275,7 +278,8 @@ struct SpanArgs {
     int32_t* active2;          // scratch for compaction
     int64_t* chunk_off;        // [n_slot + 1] prefix sums of items per active slot
     int32_t* hdr;              // [16]: n_active, total items, error flag, finished count, -,
-                               // cells per item of the planned step (the planner's choice)
+                               // cells per item of the planned step (the planner's choice),
+                               // slots listed for an extension, extension launches done
     unsigned long long* work;  // tube slots scheduled over all steps (planner adds)
     BatchOut out;
     const int32_t* ids;        // slots to initialise (null: all n_slot)
@@ -295,6 +299,15 @@ struct SpanArgs {
     int32_t resident;          // step-kernel workgroups the device holds at once (0: items
                                // always `depth` cells; else the planner shortens the items of
                                // short work lists so that they spread over the device)
+    // Lazy initialisation (1): a slot starts with the codes of its first cells only; a plan
+    // that finds its front within init_margin cells of hz lists it (ext_ids, items prefix
+    // ext_off) and moves hz on; the extension launch at the start of the next run of steps
+    // computes the listed ranges. 0: every cell is initialised at once (hz = U).
+    int32_t lazy;
+    int32_t init_margin;       // > the steps a launch sequence runs between extensions + 3
+    int32_t* ext_ids;          // [n_slot]
+    int64_t* ext_off;          // [n_slot + 1]
+    int32_t list_ext;          // 1: this plan (the last before an extension launch) lists
 };
 
 // Workgroups of k_span_step with this block size and dynamic LDS that the current device
@@ -306,6 +319,7 @@ hipError_t launch_span_init_only(const SpanArgs& a, hipStream_t s);  // codes an
 hipError_t launch_span_step(const SpanArgs& a, hipStream_t s);       // one step (two if a.fused) over the work list
 hipError_t launch_span_step2(const SpanArgs& a, hipStream_t s);      // two steps over the work list
 hipError_t launch_span_plan(const SpanArgs& a, hipStream_t s);       // decide, compact, plan
+hipError_t launch_span_extend(const SpanArgs& a, hipStream_t s);     // codes of the listed ranges
 hipError_t launch_span_finish(const SpanArgs& a, hipStream_t s);     // first-hit probabilities, counts
 
 // Persistent form: one workgroup per job, scratch per resident workgroup.
