@@ -490,3 +490,29 @@ def test_two_step_persistent_form_limits(perc):
     with pytest.raises(perc.PercError) as e:
         perc.perc_inspect_ex(wide, occw, form="persist2")
     assert e.value.code == perc.PERC_EINVAL
+
+
+@pytest.mark.parametrize("form,depth,graph_steps", [("span", 8, 1), ("span", 80, 8), ("span", 16, 64),
+                                                    ("span2", 64, 3)])
+def test_lazy_initialisation_long_fibers(perc, form, depth, graph_steps):
+    """The span forms compute the degree codes of a configuration's cells as its front
+    approaches them (an extension launch at the start of every run of graph_steps
+    plans). On thin fibers of about 1,000 cells whose percolating walks cross many
+    extensions, with runs from 1 to 64 plans and several item depths: bits and steps
+    equal the oracle's breadth-first search, and bits, steps and FP32 first-hit
+    probabilities equal the persistent form's (which initialises every cell at once)."""
+    for W, L, p, seed in ((3, 3000, 0.55, 41), (2, 3001, 0.7, 42), (5, 2999, 0.4, 43)):
+        lat = perc.Lattice(W, L)
+        ref = oracle.Lattice(W, L)
+        n = 48
+        occ = perc.perc_sample(lat, p, seed, n)
+        pg, sg, hg = perc.perc_inspect_ex(lat, occ, n, hit=True, form=form, depth=depth, graph_steps=graph_steps)
+        pp, sp, hp = perc.perc_inspect_ex(lat, occ, n, hit=True, form="persist")
+        torch.cuda.synchronize()
+        pb, sb = ref.inspect_bfs(host_words(occ))
+        np.testing.assert_array_equal(pg.cpu().numpy(), pb)
+        np.testing.assert_array_equal(sg.cpu().numpy(), sb)
+        np.testing.assert_array_equal(pg.cpu().numpy(), pp.cpu().numpy())
+        np.testing.assert_array_equal(sg.cpu().numpy(), sp.cpu().numpy())
+        np.testing.assert_array_equal(hg.cpu().numpy().view(np.uint32), hp.cpu().numpy().view(np.uint32))
+        assert pb.sum() > 0 and sb.max() > 300  # some walks run past several extensions
