@@ -283,7 +283,11 @@ __device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
     w.c = cmp ? tv.ts + (int)threadIdx.x : tv.ts;
     const uint32_t* base = reinterpret_cast<const uint32_t*>(lds);
 #pragma unroll
-    for (int i = 0; i < kSide; ++i) w.nb[i] = base + sh.nboff[i * sh.C + w.c];
+    for (int j = 0; j < kSide / 2; ++j) {
+        const uint32_t v = sh.nboff[j * sh.C + w.c];  // contacts 2j and 2j + 1
+        w.nb[2 * j] = base + (v & 0xffffu);
+        w.nb[2 * j + 1] = base + (v >> 16);
+    }
     w.me = base + ring_word(0, w.c - tv.hs + 1);
     w.top = top_of(sh, w.c);
     return w;
@@ -505,7 +509,11 @@ __device__ __forceinline__ Own own_column_in(const DevShape& sh, const TileV& tv
     const bool cmp = (int)threadIdx.x < tv.te - tv.ts;
     w.c = cmp ? tv.ts + (int)threadIdx.x : tv.ts;
 #pragma unroll
-    for (int i = 0; i < kSide; ++i) w.nb[i] = base + sh.nboff[i * sh.C + w.c];
+    for (int j = 0; j < kSide / 2; ++j) {
+        const uint32_t v = sh.nboff[j * sh.C + w.c];  // contacts 2j and 2j + 1
+        w.nb[2 * j] = base + (v & 0xffffu);
+        w.nb[2 * j + 1] = base + (v >> 16);
+    }
     w.me = base + ring_word(0, w.c - tv.hs + 1);
     w.top = top_of(sh, w.c);
     return w;

@@ -100,6 +100,20 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
                 d.contact[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col - hs + 1) : 0u;
             }
     }
+    // The one-step walks read the table as two 16-bit LDS word offsets per word (contacts
+    // 2j and 2j + 1 of a column in word j): half the loads per work item. Every fiber the
+    // walks accept has a halo range of at most 2,048 columns (two per thread of a
+    // 1,024-thread workgroup), whose offsets stay below 21,000 words; wider cross-sections
+    // are refused before any launch, so their (truncated) packed words are never read.
+    auto pack16 = [C](const std::vector<uint32_t>& t) {
+        std::vector<uint32_t> p((size_t)(kSide / 2) * C);
+        for (int j = 0; j < kSide / 2; ++j)
+            for (int c = 0; c < C; ++c)
+                p[(size_t)j * C + c] =
+                    (t[(size_t)(2 * j) * C + c] & 0xffffu) | ((t[(size_t)(2 * j + 1) * C + c] & 0xffffu) << 16);
+        return p;
+    };
+    d.contact = pack16(d.contact);
     // outer ranges: every column a halo-range column contacts
     d.tile2.assign((size_t)nt * 2, 0);
     d.span2_max = 0;
@@ -123,6 +137,7 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
                 const int32_t col = v >> 2, dcp1 = v & 3;
                 d.contact_whole[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col + 1) : 0u;
             }
+        d.contact_whole16 = pack16(d.contact_whole);
     }
     if (d.span_max <= kMaxSpan2 && d.span2_max <= kMaxSpan2) {
         const size_t sm = (size_t)d.span_max;

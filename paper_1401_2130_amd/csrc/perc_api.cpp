@@ -104,7 +104,8 @@ int column_device(const ColumnSet& cs, int dev, ColumnDevice& out) {
         PERC_TRY(upload(&n.tile2, cs.tile2));
     }
     if (!cs.contact_whole.empty()) {
-        PERC_TRY(upload(&n.nboff_whole, cs.contact_whole));
+        PERC_TRY(upload(&n.nboff_whole, cs.contact_whole16));
+        PERC_TRY(upload(&n.nboff2_whole, cs.contact_whole));
         PERC_TRY(upload(&n.tile_whole, std::vector<int32_t>{0, cs.C, 0, cs.C, 0, cs.C}));
     }
     g_coldev.emplace(std::make_pair(dev, cs.W), n);
@@ -126,7 +127,7 @@ int shape_of(const LatticeDesc& d, DevShape& sh, bool whole = false) {
     sh.tile = whole ? cd.tile_whole : cd.tile;
     sh.rank = cd.rank;
     sh.sig = cd.sig;
-    sh.nboff2 = whole ? cd.nboff_whole : cd.nboff2;
+    sh.nboff2 = whole ? cd.nboff2_whole : cd.nboff2;
     sh.tile2 = whole ? cd.tile_whole + 4 : cd.tile2;
     sh.C = d.C; sh.CP = d.CP; sh.U = d.U; sh.L = d.L;
     sh.ntile = whole ? 1 : d.ntile;

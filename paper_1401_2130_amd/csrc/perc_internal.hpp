@@ -61,7 +61,7 @@ struct ColumnSet {
     std::vector<int32_t> tile;       // [ntile][4]: first col, end col, halo first, halo end
     int32_t span_max = 0;            // widest halo range
     int32_t tile_max = 0;            // widest tile
-    std::vector<uint32_t> contact;   // contact table (layout below)
+    std::vector<uint32_t> contact;   // contact table (layout below), two contacts per word
     // Two steps per pass: the first step is computed on the whole halo range [hs, he) of
     // a tile, which reads the outer range [hs2, he2) (the halo of the halo range).
     std::vector<int32_t> tile2;      // [ntile][2]: outer first, outer end
@@ -75,6 +75,7 @@ struct ColumnSet {
     // [kSide][C], LDS words relative to column 0. It also serves as the two-step table
     // (outer range = halo range = all columns). Empty for wider fibers.
     std::vector<uint32_t> contact_whole;
+    std::vector<uint32_t> contact_whole16;  // the same, two contacts per word (one-step walks)
 };
 constexpr int32_t kMaxSpan2 = 2048;
 constexpr int32_t kWholeCols = 1024;
@@ -133,7 +134,7 @@ PERC_HD_INLINE int32_t ring_word(int32_t row, int32_t lcol) {
 // One lattice shape as the kernels see it (device pointers to the tables of its
 // column set; the far cell of a column follows from sigma and L).
 struct DevShape {
-    const uint32_t* nboff;  // [kSide][C] contact table
+    const uint32_t* nboff;  // [kSide / 2][C] contact table, word j: contacts 2j (low 16 bits), 2j + 1
     const int32_t* tile;    // [ntile][4]
     const int32_t* rank;    // [C]
     const int32_t* sig;     // [C]
@@ -154,7 +155,8 @@ struct ColumnDevice {
     int32_t* sig = nullptr;
     uint32_t* nboff2 = nullptr;
     int32_t* tile2 = nullptr;
-    uint32_t* nboff_whole = nullptr;  // the whole-cross-section tile (null: none)
+    uint32_t* nboff_whole = nullptr;  // the whole-cross-section tile, two contacts per word (null: none)
+    uint32_t* nboff2_whole = nullptr; // the same, one contact per word (its two-step table)
     int32_t* tile_whole = nullptr;    // {0, C, 0, C, 0, C}: tile, then its outer range
 };
 
