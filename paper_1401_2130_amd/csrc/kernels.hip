@@ -188,9 +188,9 @@ __device__ __forceinline__ uint32_t code_of(const uint32_t* __restrict__ code8, 
 // The ring (ring_word in perc_internal.hpp): per staged column, cell u in row
 // (u mod 8) + 1, the slot-7 cell also in row 0 and the slot-0 cell also in row 9, so
 // the cells u-1, u, u+1 sit in consecutive rows for every u; rows are 64 words apart
-// within a block of 64 columns. LDS column 0 is the zero pad column (every missing
-// contact reads its row 0 plus the slot offset: one broadcast address), and staged
-// column lc is LDS column lc + 1.
+// within a block of 64 columns. Block 0 (LDS columns 0..63) is the zero pad: a missing
+// contact reads one of its words, in a bank that no other lane of the wave reads for
+// that contact, and staged column lc is LDS column lc + kPadCols.
 //
 // A walk covers whole groups from an 8-aligned cell, one cell per phase, eight phases
 // unrolled so that every ring slot is a compile-time constant. At the second cell of
@@ -222,15 +222,18 @@ __device__ __forceinline__ Stage stage_columns(const TileV& tv) {
         const int lc = (int)threadIdx.x + j * (int)blockDim.x;
         st.ok[j] = lc < span;
         st.col[j] = st.ok[j] ? tv.hs + lc : tv.hs;
-        st.slot[j] = base + ring_word(0, st.ok[j] ? lc + 1 : 0);
+        st.slot[j] = base + ring_word(0, st.ok[j] ? lc + kPadCols : 0);
     }
     return st;
 }
 
-// The pad column holds zeros.
-__device__ __forceinline__ void zero_pad() {
-    if (threadIdx.x < (unsigned)kRows) reinterpret_cast<uint32_t*>(lds)[ring_word((int)threadIdx.x, 0)] = 0u;
+// The pad block (block 0: every row of LDS columns 0..63) of the ring at r holds zeros.
+// (One word per store: with 16-byte stores the step walk needs more VGPRs than six
+// waves per SIMD allow.)
+__device__ __forceinline__ void zero_pad(uint32_t* r) {
+    for (int i = (int)threadIdx.x; i < kBlkWords; i += (int)blockDim.x) r[i] = 0u;
 }
+__device__ __forceinline__ void zero_pad() { zero_pad(reinterpret_cast<uint32_t*>(lds)); }
 
 // Four ring words v[0..3] of group g into ring slots S0 .. S0+3 (S0 = 0 or 4) of staged
 // column j, with the mirror of the slot-0 or slot-7 cell. Cells outside [0, vmax] hold
@@ -288,7 +291,7 @@ __device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
         w.nb[2 * j] = base + (v & 0xffffu);
         w.nb[2 * j + 1] = base + (v >> 16);
     }
-    w.me = base + ring_word(0, w.c - tv.hs + 1);
+    w.me = base + ring_word(0, w.c - tv.hs + kPadCols);
     w.top = top_of(sh, w.c);
     return w;
 }
@@ -477,7 +480,7 @@ __device__ __forceinline__ StageN<NJ> stage_range(int hs, int he, uint32_t* base
         const int lc = (int)threadIdx.x + j * (int)blockDim.x;
         st.ok[j] = lc < span;
         st.col[j] = st.ok[j] ? hs + lc : hs;
-        st.slot[j] = base + ring_word(0, st.ok[j] ? lc + 1 : 0);
+        st.slot[j] = base + ring_word(0, st.ok[j] ? lc + kPadCols : 0);
     }
     return st;
 }
@@ -497,8 +500,8 @@ __device__ __forceinline__ Prod<NJ> prod_columns(const DevShape& sh, int k, cons
         p.c[j] = tv.hs + l;
 #pragma unroll
         for (int i = 0; i < kSide; ++i) p.nb[j][i] = r0 + tab[i * sh.span_max + l];
-        p.me[j] = r0 + ring_word(0, p.c[j] - os + 1);
-        p.out[j] = r1 + ring_word(0, l + 1);
+        p.me[j] = r0 + ring_word(0, p.c[j] - os + kPadCols);
+        p.out[j] = r1 + ring_word(0, l + kPadCols);
         p.top[j] = top_of(sh, p.c[j]);
     }
     return p;
@@ -514,7 +517,7 @@ __device__ __forceinline__ Own own_column_in(const DevShape& sh, const TileV& tv
         w.nb[2 * j] = base + (v & 0xffffu);
         w.nb[2 * j + 1] = base + (v >> 16);
     }
-    w.me = base + ring_word(0, w.c - tv.hs + 1);
+    w.me = base + ring_word(0, w.c - tv.hs + kPadCols);
     w.top = top_of(sh, w.c);
     return w;
 }
@@ -691,10 +694,8 @@ __device__ __forceinline__ uint32_t walk_step2(const DevShape& sh, int k, const 
     k2.last_q = (sh.U + 3) / 4 - 1;
     const int g0 = ub >> 2, gl = (ue - 1) >> 2;
     __syncthreads();  // the rings may still be read by a previous item
-    if (threadIdx.x < (unsigned)kRows) {
-        r0[ring_word((int)threadIdx.x, 0)] = 0u;
-        r1[ring_word((int)threadIdx.x, 0)] = 0u;
-    }
+    zero_pad(r0);
+    zero_pad(r1);
     Step2State<NJ> ss;
     uint4 q[NJ];
     load_quads(sh, st, yin, g0 - 2, k2.vmax0, q);

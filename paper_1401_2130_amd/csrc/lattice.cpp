@@ -24,6 +24,46 @@ constexpr int kSideOff[kSide][3] = {
     {0, 1, -1}, {-1, 0, -1}, {1, -1, -1},
 };
 
+// Missing contacts read a word of the ring's zero pad block (block 0). t[0 .. n) are
+// the table words of one contact direction for the lanes of one workgroup in order
+// (lane l reads t[l]; lanes n and beyond, up to the next multiple of 64, read t[0]), with
+// kMissing where the contact is missing. The ring's row offsets are multiples of 64
+// words, so a word's bank is its index mod 64 (mod 32 where LDS serves a wave in two
+// halves) in every row. Each missing contact gets the pad word of row 1 in a bank that no
+// real contact of the lanes of its wave (64 lanes) and half-wave (32 lanes) reads, where
+// one is free in both, else one free in the half-wave; the missing contacts of one
+// half-wave share that word (one address: a broadcast).
+constexpr uint32_t kMissing = 0xffffffffu;
+void place_pads(uint32_t* t, int n) {
+    for (int w0 = 0; w0 < n; w0 += 64) {
+        const int w1 = std::min(n, w0 + 64);
+        const bool dup = w1 - w0 < 64 && w0 > 0;  // lanes n.. of this wave read t[0]
+        uint64_t used64 = 0;
+        for (int l = w0; l < w1; ++l)
+            if (t[l] != kMissing) used64 |= 1ull << (t[l] % 64);
+        if (dup && t[0] != kMissing) used64 |= 1ull << (t[0] % 64);
+        for (int h0 = w0; h0 < w0 + 64 && h0 < n; h0 += 32) {
+            const int h1 = std::min(n, h0 + 32);
+            uint32_t used32 = 0;
+            bool pads = false;
+            for (int l = h0; l < h1; ++l) {
+                if (t[l] != kMissing) used32 |= 1u << (t[l] % 32);
+                else pads = true;
+            }
+            if (h1 - h0 < 32 && dup && t[0] != kMissing) used32 |= 1u << (t[0] % 32);
+            if (!pads) continue;
+            int b = -1;
+            for (int c = 0; c < 64 && b < 0; ++c)
+                if (!((used64 >> c) & 1u) && !((used32 >> (c % 32)) & 1u)) b = c;
+            for (int c = 0; c < 32 && b < 0; ++c)
+                if (!((used32 >> c) & 1u)) b = c;
+            if (b < 0) b = 0;
+            for (int l = h0; l < h1; ++l)
+                if (t[l] == kMissing) t[l] = (uint32_t)ring_word(1, b);
+        }
+    }
+}
+
 std::shared_ptr<ColumnSet> build_columns(int32_t W) {
     auto cs = std::make_shared<ColumnSet>();
     ColumnSet& d = *cs;
@@ -94,16 +134,15 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
             for (int i = 0; i < kSide; ++i) {
                 const int32_t v = d.nb[(size_t)i * C + c];
                 const int32_t col = v >> 2, dcp1 = v & 3;  // dcell + 1
-                // LDS word of the contact: column 1 + its place in the staged range; a
-                // missing contact reads row 0 of the zero pad column 0 (one address for
-                // all of them, so such reads broadcast)
-                d.contact[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col - hs + 1) : 0u;
+                // LDS word of the contact: column kPadCols + its place in the staged range
+                d.contact[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col - hs + kPadCols) : kMissing;
             }
+        for (int i = 0; i < kSide; ++i) place_pads(&d.contact[(size_t)i * C + ts], te - ts);
     }
     // The one-step walks read the table as two 16-bit LDS word offsets per word (contacts
     // 2j and 2j + 1 of a column in word j): half the loads per work item. Every fiber the
     // walks accept has a halo range of at most 2,048 columns (two per thread of a
-    // 1,024-thread workgroup), whose offsets stay below 21,000 words; wider cross-sections
+    // 1,024-thread workgroup), whose offsets stay below 21,200 words; wider cross-sections
     // are refused before any launch, so their (truncated) packed words are never read.
     auto pack16 = [C](const std::vector<uint32_t>& t) {
         std::vector<uint32_t> p((size_t)(kSide / 2) * C);
@@ -135,8 +174,9 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
             for (int i = 0; i < kSide; ++i) {
                 const int32_t v = d.nb[(size_t)i * C + c];
                 const int32_t col = v >> 2, dcp1 = v & 3;
-                d.contact_whole[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col + 1) : 0u;
+                d.contact_whole[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col + kPadCols) : kMissing;
             }
+        for (int i = 0; i < kSide; ++i) place_pads(&d.contact_whole[(size_t)i * C], C);
         d.contact_whole16 = pack16(d.contact_whole);
     }
     if (d.span_max <= kMaxSpan2 && d.span2_max <= kMaxSpan2) {
@@ -149,8 +189,9 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
                     const int32_t v = d.nb[(size_t)i * C + c];
                     const int32_t col = v >> 2, dcp1 = v & 3;
                     d.contact2[((size_t)k * kSide + i) * sm + (size_t)(c - hs)] =
-                        col < C ? (uint32_t)ring_word(dcp1, col - os + 1) : 0u;
+                        col < C ? (uint32_t)ring_word(dcp1, col - os + kPadCols) : kMissing;
                 }
+            for (int i = 0; i < kSide; ++i) place_pads(&d.contact2[((size_t)k * kSide + i) * sm], he - hs);
         }
     }
     return cs;

@@ -115,20 +115,23 @@ inline int64_t state_words(const LatticeDesc& d) { return (int64_t)((d.U + 3) / 
 // grouped in blocks of 64; a block stores its ten rows of 64 words one after another,
 // so word (row, lcol) is at (lcol / 64) * 640 + row * 64 + lcol % 64. Lanes reading
 // consecutive columns then hit consecutive banks whatever the row, and a row offset
-// is a compile-time multiple of 64 words.
+// is a compile-time multiple of 64 words. Block 0 is the zero pad: its words are zero
+// whenever a walk reads the ring, and a missing contact reads one of them.
 constexpr int kRows = 10;
 constexpr int kRingCells = 8;
 constexpr int kBlkCols = 64;
 constexpr int kBlkWords = kRows * kBlkCols;
+constexpr int kPadCols = kBlkCols;  // LDS column of the first staged column
 PERC_HD_INLINE int32_t ring_word(int32_t row, int32_t lcol) {
     return (lcol / kBlkCols) * kBlkWords + row * kBlkCols + lcol % kBlkCols;
 }
 
 // Contact table (ColumnSet::contact): for side contact i of column c (in tile k), the
 // LDS word ring_word(1 + dcell, lcol) of that contact for a tube in ring slot 0, lcol
-// being 1 + its column within the tile's staged range [halo first, halo end); word 0
-// (row 0 of the zero pad column 0) for a missing contact. A tube in slot s reads it s
-// rows (64 s words) further.
+// being kPadCols + its column within the tile's staged range [halo first, halo end). A
+// tube in slot s reads it s rows (64 s words) further. A missing contact reads a word
+// of the zero pad block, ring_word(1, b), with the bank b chosen so that it shares no
+// bank with the other contacts of that direction its wave reads (no bank conflict).
 
 
 // One lattice shape as the kernels see it (device pointers to the tables of its
@@ -160,19 +163,19 @@ struct ColumnDevice {
     int32_t* tile_whole = nullptr;    // {0, C, 0, C, 0, C}: tile, then its outer range
 };
 
-// Dynamic LDS of the walking kernels: the ring from address 0, 1 + span columns (pad
-// column, staged range) in whole blocks, then a fixed tail (the last kLdsTail bytes of
+// Dynamic LDS of the walking kernels: the ring from address 0, kPadCols + span columns
+// (zero pad block, staged range) in whole blocks, then a fixed tail (the last kLdsTail bytes of
 // the launch's allocation): the code table (16 x 16 bytes: 1/deg, reach floor, self
 // weight per degree code), misc (16 words), part (256 floats).
 constexpr uint32_t kLdsTail = 256u + 64u + 1024u;
 PERC_HD inline uint32_t lds_total(int32_t span) {
-    const uint32_t blocks = (uint32_t)(span + 1 + kBlkCols - 1) / kBlkCols;
+    const uint32_t blocks = (uint32_t)(span + kPadCols + kBlkCols - 1) / kBlkCols;
     return blocks * kBlkWords * 4u + kLdsTail;
 }
 // Two steps per pass: the outer ring (outer range) from address 0, the inner ring (halo
 // range) from word lds_ring2_words(span2), then the tail.
 PERC_HD inline uint32_t lds_ring2_words(int32_t span2) {
-    return (uint32_t)((span2 + 1 + kBlkCols - 1) / kBlkCols) * kBlkWords;
+    return (uint32_t)((span2 + kPadCols + kBlkCols - 1) / kBlkCols) * kBlkWords;
 }
 PERC_HD inline uint32_t lds_total2(int32_t span, int32_t span2) {
     return lds_ring2_words(span2) * 4u + lds_total(span);
