@@ -42,8 +42,6 @@ namespace {
 constexpr int kMaxBlock = 1024;
 constexpr int kXcds = 8;         // MI355X: workgroups are dealt round-robin over 8 XCDs
 constexpr int kLoadCols = 2;     // staged columns per thread: span <= 2 * blockDim
-// Smallest positive FP32 value (denormal): the mass a reached tube keeps at least.
-constexpr float kReachFloor = 1.40129846e-45f;
 
 extern __shared__ __align__(16) unsigned char lds[];
 
@@ -51,13 +49,13 @@ __device__ __forceinline__ void lds_put_u32(uint32_t off, uint32_t v) { *reinter
 
 // Fixed tail of the dynamic LDS of a launch of `total` bytes.
 struct Tail {
-    float4* ct;  // the code table
+    float* ct;  // the code table
     uint32_t* misc;
     float* part;
 };
 __device__ __forceinline__ Tail lds_tail(int total) {
     const uint32_t t = (uint32_t)total - kLdsTail;  // a multiple of 16
-    return Tail{reinterpret_cast<float4*>(lds + t), reinterpret_cast<uint32_t*>(lds + t + 256),
+    return Tail{reinterpret_cast<float*>(lds + t), reinterpret_cast<uint32_t*>(lds + t + 256),
                 reinterpret_cast<float*>(lds + t + 320)};
 }
 
@@ -104,16 +102,14 @@ __device__ __forceinline__ uint32_t sample_word(int64_t w, int64_t N, uint64_t g
 
 __device__ __forceinline__ uint32_t shape_tag(const DevShape& sh) { return ((uint32_t)sh.W << 16) | (uint32_t)sh.L; }
 
-// Per degree code d, one 16-byte entry {1/deg, reach floor, self weight, 0}:
-//   1/deg  the correctly rounded FP32 reciprocal for d = 1..14; 1 for d = 0 (a metallic
-//          tube without metallic contact keeps its mass); 0 for 15 (insulating);
-//   floor  the smallest positive FP32 value for a metallic tube, 0 for an insulating one;
-//   self   1 for d = 0 (the self-loop adds the tube's own mass), else 0.
-__device__ __forceinline__ void fill_codes(float4* ct) {
+// Per degree code d, one word (consecutive words: the lanes of a half-wave reading
+// different codes hit different LDS banks): the correctly rounded FP32 reciprocal 1/d
+// for d = 1..14; 1 for d = 0 (a metallic tube without metallic contact keeps its mass);
+// 0 for 15 (insulating). A tube's self weight and reach floor follow from its code.
+__device__ __forceinline__ void fill_codes(float* ct) {
     if (threadIdx.x < 16) {
         const int d = threadIdx.x;
-        ct[d] = make_float4(d == 0 ? 1.0f : (d == 15 ? 0.0f : 1.0f / (float)d), d < 15 ? kReachFloor : 0.0f,
-                            d == 0 ? 1.0f : 0.0f, 0.0f);
+        ct[d] = d == 0 ? 1.0f : (d == 15 ? 0.0f : 1.0f / (float)d);
     }
 }
 
@@ -138,6 +134,7 @@ __device__ __forceinline__ int top_of(const DevShape& sh, int c) {
 
 struct TileV {
     int ts, te, hs, he;
+    int lm;  // first lane of the tile in the lane tables
 };
 // A value every lane of the workgroup reads from the same address, moved into scalar
 // registers (the compiler cannot prove such loads uniform when the kernel also
@@ -161,7 +158,7 @@ __device__ __forceinline__ T uniform_load(const T* p) {
 
 __device__ __forceinline__ TileV load_tile(const DevShape& sh, int k) {
     const int32_t* p = sh.tile + 4 * k;
-    return TileV{uniform_i32(p), uniform_i32(p + 1), uniform_i32(p + 2), uniform_i32(p + 3)};
+    return TileV{uniform_i32(p), uniform_i32(p + 1), uniform_i32(p + 2), uniform_i32(p + 3), k * sh.lane_stride};
 }
 
 // ------------------------------------------------------------------------------
@@ -271,29 +268,33 @@ __device__ __forceinline__ void put_quads(const StageN<NJ>& st, int g, int vmax,
     }
 }
 
-// Per-thread view of its own column: the 12 contacts and its own ring words. Threads
-// beyond the tile take the tile's first column: they compute (and store) exactly what
-// thread 0 does, so no compute or store needs a lane predicate.
+// Per-thread view of its own column: the 12 contacts and its own ring words. The lane
+// tables give each thread its column; an idle lane repeats a column of the tile (so does
+// every thread beyond the tables): it computes (and stores) exactly what that column's
+// lane does, so no compute or store needs a lane predicate.
 struct Own {
     const uint32_t* nb[kSide];
     const uint32_t* me;
     int c, top;
 };
 
-__device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
+__device__ __forceinline__ Own own_column_in(const DevShape& sh, const TileV& tv, const uint32_t* base) {
     Own w;
-    const bool cmp = (int)threadIdx.x < tv.te - tv.ts;
-    w.c = cmp ? tv.ts + (int)threadIdx.x : tv.ts;
-    const uint32_t* base = reinterpret_cast<const uint32_t*>(lds);
+    const int l = tv.lm + min((int)threadIdx.x, sh.lane_stride - 1);
+    const int nl = sh.ntile * sh.lane_stride;
 #pragma unroll
     for (int j = 0; j < kSide / 2; ++j) {
-        const uint32_t v = sh.nboff[j * sh.C + w.c];  // contacts 2j and 2j + 1
+        const uint32_t v = sh.nboff[j * nl + l];  // contacts 2j and 2j + 1
         w.nb[2 * j] = base + (v & 0xffffu);
         w.nb[2 * j + 1] = base + (v >> 16);
     }
+    w.c = tv.ts + (int)sh.lanes[l];
     w.me = base + ring_word(0, w.c - tv.hs + kPadCols);
     w.top = top_of(sh, w.c);
     return w;
+}
+__device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
+    return own_column_in(sh, tv, reinterpret_cast<const uint32_t*>(lds));
 }
 
 // The update of one tube (Eq. 3 on the stored words y = x / deg): the 12 side contacts
@@ -301,7 +302,7 @@ __device__ __forceinline__ Own own_column(const DevShape& sh, const TileV& tv) {
 // layer pairs, then the end contacts), then the table entry of the tube's degree code.
 // Every walk calls this, so a tube gets the same bits whichever kernel computes it.
 __device__ __forceinline__ uint32_t tube_update(const uint32_t (&n)[kSide], uint32_t dn, uint32_t up, uint32_t own,
-                                                int32_t ends, const float4* ct, uint32_t cd) {
+                                                int32_t ends, const float* ct, uint32_t cd) {
     const float s01 = mag(n[0]) + mag(n[1]);
     const float s23 = mag(n[2]) + mag(n[3]);
     const float s45 = mag(n[4]) + mag(n[5]);
@@ -312,7 +313,7 @@ __device__ __forceinline__ uint32_t tube_update(const uint32_t (&n)[kSide], uint
     const float sum = ((s01 + s23) + (s45 + s67)) + ((s89 + sab) + sud);
     // the table entry's 1/deg from LDS; its self weight (1 for degree 0) and reach floor
     // (2^-149, bits 1, for a metallic tube) follow from the code itself
-    const float rcp = ct[cd].x;
+    const float rcp = ct[cd];
     const float self = cd == 0u ? 1.0f : 0.0f;
     const uint32_t floor_bits = cd < 15u ? 1u : 0u;
     // a metallic tube of degree 0 has no metallic contact (sum == 0): it keeps its own
@@ -339,7 +340,7 @@ struct StepState {
 
 // Cell u = u8 + K (ring slot K) of a step walk.
 template <int K>
-__device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, const Own& w, const float4* ct,
+__device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, const Own& w, const float* ct,
                                           const float* __restrict__ yin, float* __restrict__ yout,
                                           const uint32_t* __restrict__ code4, int u8, int ue, int front, int vmax,
                                           int top_min, StepState& ss) {
@@ -394,7 +395,7 @@ __device__ __forceinline__ void step_cell(const DevShape& sh, const Stage& st, c
 // first cell instead of two; the persistent form's walks, one per tile and step, gain
 // from it, the span form's do not).
 template <bool LEAD = false>
-__device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& tv, const float4* ct,
+__device__ __forceinline__ uint32_t walk_step(const DevShape& sh, const TileV& tv, const float* ct,
                                               const float* __restrict__ yin, float* __restrict__ yout,
                                               const uint8_t* __restrict__ code, int ub, int ue, int front,
                                               int front_chk) {
@@ -507,21 +508,6 @@ __device__ __forceinline__ Prod<NJ> prod_columns(const DevShape& sh, int k, cons
     return p;
 }
 
-__device__ __forceinline__ Own own_column_in(const DevShape& sh, const TileV& tv, const uint32_t* base) {
-    Own w;
-    const bool cmp = (int)threadIdx.x < tv.te - tv.ts;
-    w.c = cmp ? tv.ts + (int)threadIdx.x : tv.ts;
-#pragma unroll
-    for (int j = 0; j < kSide / 2; ++j) {
-        const uint32_t v = sh.nboff[j * sh.C + w.c];  // contacts 2j and 2j + 1
-        w.nb[2 * j] = base + (v & 0xffffu);
-        w.nb[2 * j + 1] = base + (v >> 16);
-    }
-    w.me = base + ring_word(0, w.c - tv.hs + kPadCols);
-    w.top = top_of(sh, w.c);
-    return w;
-}
-
 template <int NJ>
 struct Step2State {
     uint4 next[NJ];        // staged outer quads of the group after the current one
@@ -537,7 +523,7 @@ struct Step2State {
 // to the same slot of R1 (with the mirror row of slots 0 and 7). Words outside [0, vmax1]
 // are set to zero: those cells hold no mass after the first step.
 template <int K, int NJ>
-__device__ __forceinline__ void first_cell(const DevShape& sh, const Prod<NJ>& p, const float4* ct, int u, int vmax1,
+__device__ __forceinline__ void first_cell(const DevShape& sh, const Prod<NJ>& p, const float* ct, int u, int vmax1,
                                            int front, float* __restrict__ far1, Step2State<NJ>& ss) {
     constexpr int k = K & 3, par = K >> 2;
 #pragma unroll
@@ -582,7 +568,7 @@ __device__ __forceinline__ void store_first0(const Prod<NJ>& p, const Step2State
 // Second step of cell u (ring slot K of R1) for this thread's tile column; at the last
 // cell of the group its quad goes to HBM.
 template <int K, int NJ>
-__device__ __forceinline__ void second_cell(const DevShape& sh, const Own& w, const float4* ct, int u, int front,
+__device__ __forceinline__ void second_cell(const DevShape& sh, const Own& w, const float* ct, int u, int front,
                                             int top_min, float* __restrict__ yout, Step2State<NJ>& ss) {
     constexpr int k = K & 3, par = K >> 2;
     const uint32_t cd = (ss.cq2[par] >> (4 * K)) & 0xfu;
@@ -612,7 +598,7 @@ struct Walk2 {
     const StageN<NJ>* st;
     const Prod<NJ>* p;
     const Own* w;
-    const float4* ct;
+    const float* ct;
     const float* yin;
     float* yout;
     const uint32_t* code4;
@@ -665,7 +651,7 @@ __device__ __forceinline__ void half2(const DevShape& sh, const Walk2<NJ>& k2, i
 // and stores the second step's in *fl2. NJ: column slots per thread of the halo and
 // outer ranges (1 when the workgroup has a thread per column of the whole tile).
 template <int NJ>
-__device__ __forceinline__ uint32_t walk_step2(const DevShape& sh, int k, const TileV& tv, const float4* ct,
+__device__ __forceinline__ uint32_t walk_step2(const DevShape& sh, int k, const TileV& tv, const float* ct,
                                                const float* __restrict__ yin, float* __restrict__ yout,
                                                const uint8_t* __restrict__ code, float* __restrict__ far1, int ub,
                                                int ue, int front, int r1_off, uint32_t* fl2) {
@@ -773,7 +759,7 @@ struct InitState {
 
 template <int K>
 __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, const Own& w,
-                                          const int (&rk)[kLoadCols], const float4* ct,
+                                          const int (&rk)[kLoadCols], const float* ct,
                                           const uint32_t* __restrict__ bits, uint32_t* __restrict__ code4,
                                           float* __restrict__ y0, int u8, int ue, float x0, InitState& is) {
     constexpr int k = K & 3, par = K >> 2;
@@ -791,7 +777,7 @@ __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, c
     const uint32_t cd = me ? deg : 15u;
     is.cq |= cd << (4 * K);
     if (u == 0 && me) {
-        is.y0 = x0 * ct[cd].x;
+        is.y0 = x0 * ct[cd];
         is.fl |= F_NONEMPTY;
         if (u == w.top) is.fl |= F_FAR;
     }
@@ -814,7 +800,7 @@ __device__ __forceinline__ void init_cell(const DevShape& sh, const Stage& st, c
 // LEAD: the three leading groups of occupancy are loaded together (the span form's
 // initialisation launch gains from it; the persistent form keeps its registers).
 template <bool LEAD = false>
-__device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& tv, const float4* ct,
+__device__ __forceinline__ uint32_t walk_init(const DevShape& sh, const TileV& tv, const float* ct,
                                               const uint32_t* __restrict__ bits, uint8_t* __restrict__ code,
                                               float* __restrict__ y0, int ub, int ue, float x0) {
     ue = min(ue, sh.U);

@@ -24,44 +24,94 @@ constexpr int kSideOff[kSide][3] = {
     {0, 1, -1}, {-1, 0, -1}, {1, -1, -1},
 };
 
-// Missing contacts read a word of the ring's zero pad block (block 0). t[0 .. n) are
-// the table words of one contact direction for the lanes of one workgroup in order
-// (lane l reads t[l]; lanes n and beyond, up to the next multiple of 64, read t[0]), with
-// kMissing where the contact is missing. The ring's row offsets are multiples of 64
-// words, so a word's bank is its index mod 64 (mod 32 where LDS serves a wave in two
-// halves) in every row. Each missing contact gets the pad word of row 1 in a bank that no
-// real contact of the lanes of its wave (64 lanes) and half-wave (32 lanes) reads, where
-// one is free in both, else one free in the half-wave; the missing contacts of one
-// half-wave share that word (one address: a broadcast).
+// Contact tables are built column by column with kMissing for a missing contact, then
+// laid out for the lanes that read them (the LDS bank rules are with ring_word).
 constexpr uint32_t kMissing = 0xffffffffu;
-void place_pads(uint32_t* t, int n) {
-    for (int w0 = 0; w0 < n; w0 += 64) {
-        const int w1 = std::min(n, w0 + 64);
-        const bool dup = w1 - w0 < 64 && w0 > 0;  // lanes n.. of this wave read t[0]
-        uint64_t used64 = 0;
-        for (int l = w0; l < w1; ++l)
-            if (t[l] != kMissing) used64 |= 1ull << (t[l] % 64);
-        if (dup && t[0] != kMissing) used64 |= 1ull << (t[0] % 64);
-        for (int h0 = w0; h0 < w0 + 64 && h0 < n; h0 += 32) {
-            const int h1 = std::min(n, h0 + 32);
-            uint32_t used32 = 0;
-            bool pads = false;
-            for (int l = h0; l < h1; ++l) {
-                if (t[l] != kMissing) used32 |= 1u << (t[l] % 32);
-                else pads = true;
+constexpr int kHalf = 32;  // lanes of a half-wave = LDS banks
+
+// Lanes of the walk of the tile [ts, te) over at most B lanes: column ts + lanes[l] on
+// lane l. tab[i * C + c] is the LDS word of contact i of column c (kMissing: none).
+// Columns go to lanes in order; a column whose real contacts would add a second word to
+// a bank of its half-wave (for the same direction) waits behind an idle lane that
+// repeats the previous column (the repeat reads the same words), while the budget leaves
+// room for the remaining columns. Lanes after the last column repeat it.
+std::vector<uint16_t> lane_map(const std::vector<uint32_t>& tab, int C, int ts, int te, int B) {
+    std::vector<uint16_t> lanes;
+    lanes.reserve((size_t)B);
+    uint32_t word[kSide][kHalf];
+    for (int c = ts; c < te;) {
+        const int l = (int)lanes.size();
+        if (l % kHalf == 0)
+            for (auto& row : word)
+                for (uint32_t& w : row) w = kMissing;
+        bool fits = true;
+        for (int i = 0; i < kSide && fits; ++i) {
+            const uint32_t a = tab[(size_t)i * C + c];
+            if (a != kMissing && word[i][a % kHalf] != kMissing && word[i][a % kHalf] != a) fits = false;
+        }
+        if (fits || l % kHalf == 0 || l + 1 + (te - c) > B) {
+            for (int i = 0; i < kSide; ++i) {
+                const uint32_t a = tab[(size_t)i * C + c];
+                if (a != kMissing) word[i][a % kHalf] = a;
             }
-            if (h1 - h0 < 32 && dup && t[0] != kMissing) used32 |= 1u << (t[0] % 32);
-            if (!pads) continue;
-            int b = -1;
-            for (int c = 0; c < 64 && b < 0; ++c)
-                if (!((used64 >> c) & 1u) && !((used32 >> (c % 32)) & 1u)) b = c;
-            for (int c = 0; c < 32 && b < 0; ++c)
-                if (!((used32 >> c) & 1u)) b = c;
-            if (b < 0) b = 0;
-            for (int l = h0; l < h1; ++l)
-                if (t[l] == kMissing) t[l] = (uint32_t)ring_word(1, b);
+            lanes.push_back((uint16_t)(c - ts));
+            ++c;
+        } else {
+            lanes.push_back(lanes.back());
         }
     }
+    while ((int)lanes.size() < B) lanes.push_back(lanes.back());
+    return lanes;
+}
+
+// Missing contacts of direction i (t: that direction's words by column, from column
+// `base`; lane l reads column base + lanes[l]) get the pad word of row 1 in a bank that no
+// real contact of their half-wave reads; the missing contacts of one half-wave share it
+// (one address: a broadcast).
+void place_pads(uint32_t* t, int base, const std::vector<uint16_t>& lanes) {
+    const int n = (int)lanes.size();
+    for (int h0 = 0; h0 < n; h0 += kHalf) {
+        const int h1 = std::min(n, h0 + kHalf);
+        uint32_t used = 0;
+        bool pads = false;
+        for (int l = h0; l < h1; ++l) {
+            const uint32_t a = t[base + lanes[(size_t)l]];
+            if (a != kMissing) used |= 1u << (a % kHalf);
+            else pads = true;
+        }
+        if (!pads) continue;
+        int b = 0;
+        while (b < kHalf - 1 && ((used >> b) & 1u)) ++b;
+        for (int l = h0; l < h1; ++l) {
+            uint32_t& a = t[base + lanes[(size_t)l]];
+            if (a == kMissing) a = (uint32_t)ring_word(1, b);
+        }
+    }
+}
+
+// Lanes 0 .. n-1 on columns 0 .. n-1 and the rest of the last wave on column 0 (the walks
+// that stage a range give every surplus lane its first column).
+std::vector<uint16_t> identity_lanes(int n) {
+    std::vector<uint16_t> lanes((size_t)((n + 63) / 64) * 64, 0);
+    for (int l = 0; l < n; ++l) lanes[(size_t)l] = (uint16_t)l;
+    return lanes;
+}
+
+// The one-step walks read a table as two 16-bit LDS word offsets per word, by lane:
+// word [j][k * B + l] holds contacts 2j (low 16 bits) and 2j + 1 of lane l of tile k (half
+// the loads of one word per contact). Every fiber the walks accept has a halo range of at
+// most 2,048 columns (two per thread of a 1,024-thread workgroup), whose offsets stay
+// below 21,200 words; wider cross-sections are refused before any launch, so their
+// (truncated) packed words are never read.
+void pack_lanes(const std::vector<uint32_t>& tab, int C, int ts, const std::vector<uint16_t>& lanes, int k,
+                int nt, std::vector<uint32_t>& out) {
+    const size_t B = lanes.size(), stride = (size_t)nt * B;
+    for (int j = 0; j < kSide / 2; ++j)
+        for (size_t l = 0; l < B; ++l) {
+            const int c = ts + lanes[l];
+            out[(size_t)j * stride + (size_t)k * B + l] =
+                (tab[(size_t)(2 * j) * C + c] & 0xffffu) | ((tab[(size_t)(2 * j + 1) * C + c] & 0xffffu) << 16);
+        }
 }
 
 std::shared_ptr<ColumnSet> build_columns(int32_t W) {
@@ -126,7 +176,12 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
         d.tile_max = std::max(d.tile_max, te - ts);
     }
     // contact table: LDS word of each side contact within its tile's staged range
-    d.contact.assign((size_t)kSide * C, 0u);
+    // (kPadCols + its place in the range), then the lanes of each tile and, by lane, the
+    // packed table
+    std::vector<uint32_t> tab((size_t)kSide * C, kMissing);
+    d.lane_stride = ((d.tile_max + 63) / 64) * 64;
+    d.lanes.assign((size_t)nt * d.lane_stride, 0);
+    d.contact.assign((size_t)(kSide / 2) * nt * d.lane_stride, 0u);
     for (int k = 0; k < nt; ++k) {
         const int ts = d.tile[k * 4 + 0], te = d.tile[k * 4 + 1];
         const int hs = d.tile[k * 4 + 2];
@@ -134,25 +189,13 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
             for (int i = 0; i < kSide; ++i) {
                 const int32_t v = d.nb[(size_t)i * C + c];
                 const int32_t col = v >> 2, dcp1 = v & 3;  // dcell + 1
-                // LDS word of the contact: column kPadCols + its place in the staged range
-                d.contact[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col - hs + kPadCols) : kMissing;
+                if (col < C) tab[(size_t)i * C + c] = (uint32_t)ring_word(dcp1, col - hs + kPadCols);
             }
-        for (int i = 0; i < kSide; ++i) place_pads(&d.contact[(size_t)i * C + ts], te - ts);
+        const std::vector<uint16_t> lanes = lane_map(tab, C, ts, te, d.lane_stride);
+        for (int i = 0; i < kSide; ++i) place_pads(&tab[(size_t)i * C], ts, lanes);
+        std::copy(lanes.begin(), lanes.end(), d.lanes.begin() + (size_t)k * d.lane_stride);
+        pack_lanes(tab, C, ts, lanes, k, nt, d.contact);
     }
-    // The one-step walks read the table as two 16-bit LDS word offsets per word (contacts
-    // 2j and 2j + 1 of a column in word j): half the loads per work item. Every fiber the
-    // walks accept has a halo range of at most 2,048 columns (two per thread of a
-    // 1,024-thread workgroup), whose offsets stay below 21,200 words; wider cross-sections
-    // are refused before any launch, so their (truncated) packed words are never read.
-    auto pack16 = [C](const std::vector<uint32_t>& t) {
-        std::vector<uint32_t> p((size_t)(kSide / 2) * C);
-        for (int j = 0; j < kSide / 2; ++j)
-            for (int c = 0; c < C; ++c)
-                p[(size_t)j * C + c] =
-                    (t[(size_t)(2 * j) * C + c] & 0xffffu) | ((t[(size_t)(2 * j + 1) * C + c] & 0xffffu) << 16);
-        return p;
-    };
-    d.contact = pack16(d.contact);
     // outer ranges: every column a halo-range column contacts
     d.tile2.assign((size_t)nt * 2, 0);
     d.span2_max = 0;
@@ -169,15 +212,23 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
         d.span2_max = std::max(d.span2_max, oe - os);
     }
     if (C <= kWholeCols) {
-        d.contact_whole.assign((size_t)kSide * C, 0u);
+        std::vector<uint32_t> tw((size_t)kSide * C, kMissing);
         for (int c = 0; c < C; ++c)
             for (int i = 0; i < kSide; ++i) {
                 const int32_t v = d.nb[(size_t)i * C + c];
                 const int32_t col = v >> 2, dcp1 = v & 3;
-                d.contact_whole[(size_t)i * C + c] = col < C ? (uint32_t)ring_word(dcp1, col + kPadCols) : kMissing;
+                if (col < C) tw[(size_t)i * C + c] = (uint32_t)ring_word(dcp1, col + kPadCols);
             }
-        for (int i = 0; i < kSide; ++i) place_pads(&d.contact_whole[(size_t)i * C], C);
-        d.contact_whole16 = pack16(d.contact_whole);
+        // the two-step walks' first step reads it by column, one column per lane in order
+        d.contact_whole = tw;
+        const std::vector<uint16_t> ident = identity_lanes(C);
+        for (int i = 0; i < kSide; ++i) place_pads(&d.contact_whole[(size_t)i * C], 0, ident);
+        // the one-step walks (and the second step) by lane
+        d.lane_stride_whole = ((C + 63) / 64) * 64;
+        d.lanes_whole = lane_map(tw, C, 0, C, d.lane_stride_whole);
+        for (int i = 0; i < kSide; ++i) place_pads(&tw[(size_t)i * C], 0, d.lanes_whole);
+        d.contact_whole16.assign((size_t)(kSide / 2) * d.lane_stride_whole, 0u);
+        pack_lanes(tw, C, 0, d.lanes_whole, 0, 1, d.contact_whole16);
     }
     if (d.span_max <= kMaxSpan2 && d.span2_max <= kMaxSpan2) {
         const size_t sm = (size_t)d.span_max;
@@ -191,7 +242,8 @@ std::shared_ptr<ColumnSet> build_columns(int32_t W) {
                     d.contact2[((size_t)k * kSide + i) * sm + (size_t)(c - hs)] =
                         col < C ? (uint32_t)ring_word(dcp1, col - os + kPadCols) : kMissing;
                 }
-            for (int i = 0; i < kSide; ++i) place_pads(&d.contact2[((size_t)k * kSide + i) * sm], he - hs);
+            const std::vector<uint16_t> ident = identity_lanes(he - hs);
+            for (int i = 0; i < kSide; ++i) place_pads(&d.contact2[((size_t)k * kSide + i) * sm], 0, ident);
         }
     }
     return cs;

@@ -96,6 +96,7 @@ int column_device(const ColumnSet& cs, int dev, ColumnDevice& out) {
     }
     ColumnDevice n;
     PERC_TRY(upload(&n.nboff, cs.contact));
+    PERC_TRY(upload(&n.lanes, cs.lanes));
     PERC_TRY(upload(&n.tile, cs.tile));
     PERC_TRY(upload(&n.rank, cs.rank));
     PERC_TRY(upload(&n.sig, cs.sig));
@@ -105,6 +106,7 @@ int column_device(const ColumnSet& cs, int dev, ColumnDevice& out) {
     }
     if (!cs.contact_whole.empty()) {
         PERC_TRY(upload(&n.nboff_whole, cs.contact_whole16));
+        PERC_TRY(upload(&n.lanes_whole, cs.lanes_whole));
         PERC_TRY(upload(&n.nboff2_whole, cs.contact_whole));
         PERC_TRY(upload(&n.tile_whole, std::vector<int32_t>{0, cs.C, 0, cs.C, 0, cs.C}));
     }
@@ -124,6 +126,8 @@ int shape_of(const LatticeDesc& d, DevShape& sh, bool whole = false) {
     PERC_TRY(column_device(*d.cs, dev, cd));
     if (whole && !cd.nboff_whole) return fail(PERC_EINVAL, "the fiber has more columns than one tile holds");
     sh.nboff = whole ? cd.nboff_whole : cd.nboff;
+    sh.lanes = whole ? cd.lanes_whole : cd.lanes;
+    sh.lane_stride = whole ? d.cs->lane_stride_whole : d.cs->lane_stride;
     sh.tile = whole ? cd.tile_whole : cd.tile;
     sh.rank = cd.rank;
     sh.sig = cd.sig;
@@ -1769,6 +1773,7 @@ int noalloc_impl(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cf
     Carver cv{reinterpret_cast<char*>(region), region_bytes};
     DevShape* d_shape = cv.take<DevShape>(1);
     uint32_t* d_nboff = cv.take<uint32_t>(cs.contact.size());
+    uint16_t* d_lanes = cv.take<uint16_t>(cs.lanes.size());
     int32_t* d_tile = cv.take<int32_t>(cs.tile.size());
     int32_t* d_rank = cv.take<int32_t>(cs.rank.size());
     int32_t* d_sig = cv.take<int32_t>(cs.sig.size());
@@ -1795,6 +1800,8 @@ int noalloc_impl(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cf
     const int64_t per_wave = lo;
     DevShape sh;
     sh.nboff = d_nboff;
+    sh.lanes = d_lanes;
+    sh.lane_stride = cs.lane_stride;
     sh.tile = d_tile;
     sh.rank = d_rank;
     sh.sig = d_sig;
@@ -1807,6 +1814,7 @@ int noalloc_impl(const perc_lattice* lat, const uint32_t* occ_bits, int64_t n_cf
     sh.N = d.N; sh.words = d.words;
     HIP_TRY(hipMemcpyAsync(d_shape, &sh, sizeof(DevShape), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_nboff, cs.contact.data(), sizeof(uint32_t) * cs.contact.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_lanes, cs.lanes.data(), sizeof(uint16_t) * cs.lanes.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_tile, cs.tile.data(), sizeof(int32_t) * cs.tile.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_rank, cs.rank.data(), sizeof(int32_t) * cs.rank.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_sig, cs.sig.data(), sizeof(int32_t) * cs.sig.size(), hipMemcpyHostToDevice, s));

@@ -61,7 +61,11 @@ struct ColumnSet {
     std::vector<int32_t> tile;       // [ntile][4]: first col, end col, halo first, halo end
     int32_t span_max = 0;            // widest halo range
     int32_t tile_max = 0;            // widest tile
-    std::vector<uint32_t> contact;   // contact table (layout below), two contacts per word
+    // Lanes of the tile walks (layout below): lane l of the walk of tile k computes column
+    // tile[4k] + lanes[k * lane_stride + l]; lane_stride = the tile width rounded up to 64.
+    int32_t lane_stride = 64;
+    std::vector<uint16_t> lanes;     // [ntile][lane_stride]
+    std::vector<uint32_t> contact;   // contact table (layout below), two contacts per word, by lane
     // Two steps per pass: the first step is computed on the whole halo range [hs, he) of
     // a tile, which reads the outer range [hs2, he2) (the halo of the halo range).
     std::vector<int32_t> tile2;      // [ntile][2]: outer first, outer end
@@ -75,7 +79,10 @@ struct ColumnSet {
     // [kSide][C], LDS words relative to column 0. It also serves as the two-step table
     // (outer range = halo range = all columns). Empty for wider fibers.
     std::vector<uint32_t> contact_whole;
-    std::vector<uint32_t> contact_whole16;  // the same, two contacts per word (one-step walks)
+    // the one-step walks' view of that tile: its lanes and, by lane, two contacts per word
+    int32_t lane_stride_whole = 64;
+    std::vector<uint16_t> lanes_whole;      // [lane_stride_whole]
+    std::vector<uint32_t> contact_whole16;  // [kSide / 2][lane_stride_whole]
 };
 constexpr int32_t kMaxSpan2 = 2048;
 constexpr int32_t kWholeCols = 1024;
@@ -126,18 +133,31 @@ PERC_HD_INLINE int32_t ring_word(int32_t row, int32_t lcol) {
     return (lcol / kBlkCols) * kBlkWords + row * kBlkCols + lcol % kBlkCols;
 }
 
-// Contact table (ColumnSet::contact): for side contact i of column c (in tile k), the
-// LDS word ring_word(1 + dcell, lcol) of that contact for a tube in ring slot 0, lcol
-// being kPadCols + its column within the tile's staged range [halo first, halo end). A
-// tube in slot s reads it s rows (64 s words) further. A missing contact reads a word
-// of the zero pad block, ring_word(1, b), with the bank b chosen so that it shares no
-// bank with the other contacts of that direction its wave reads (no bank conflict).
+// Contact table: for side contact i of column c (in tile k), the LDS word
+// ring_word(1 + dcell, lcol) of that contact for a tube in ring slot 0, lcol being
+// kPadCols + its column within the tile's staged range [halo first, halo end). A tube in
+// slot s reads it s rows (64 s words) further. A missing contact reads a word of the
+// zero pad block, ring_word(1, b).
+//
+// LDS serves the 32-bit reads of a wave in two halves of 32 lanes, over 32 banks (bank =
+// word mod 32; the ring's row offsets are multiples of 64 words, so a contact's bank is
+// the same in every row). The lanes of a tile walk are laid out so that no half-wave
+// reads two different words of one bank for one contact direction: columns go to lanes
+// in order, and where the next column's contacts would share a bank with a different
+// word its half-wave already reads (the q-row boundaries of the hexagon shift the
+// contact columns by one or two), the previous column is repeated on an idle lane first
+// (ColumnSet::lanes; the repeat computes and stores exactly what the first does). A
+// missing contact takes the pad word of a bank no other contact of its direction in its
+// half-wave reads. The one-step table is stored by lane:
+// word [j][k * lane_stride + l] holds contacts 2j (low 16 bits) and 2j + 1 of lane l of
+// tile k.
 
 
 // One lattice shape as the kernels see it (device pointers to the tables of its
 // column set; the far cell of a column follows from sigma and L).
 struct DevShape {
-    const uint32_t* nboff;  // [kSide / 2][C] contact table, word j: contacts 2j (low 16 bits), 2j + 1
+    const uint32_t* nboff;  // [kSide / 2][ntile * lane_stride] contact table by lane
+    const uint16_t* lanes;  // [ntile][lane_stride] column (within its tile) of each lane
     const int32_t* tile;    // [ntile][4]
     const int32_t* rank;    // [C]
     const int32_t* sig;     // [C]
@@ -147,26 +167,29 @@ struct DevShape {
     int32_t ntile, span_max, tile_max, W;
     int32_t ends;           // 1 with end contacts (modified lattice), 0 regular FCC
     int32_t span2_max;      // widest outer range (two-step form)
+    int32_t lane_stride;    // lanes per tile in `lanes` (a multiple of 64)
     int64_t N, words;
 };
 
 // Device copies of the tables of one column set on one HIP device (kept for the process).
 struct ColumnDevice {
     uint32_t* nboff = nullptr;
+    uint16_t* lanes = nullptr;
     int32_t* tile = nullptr;
     int32_t* rank = nullptr;
     int32_t* sig = nullptr;
     uint32_t* nboff2 = nullptr;
     int32_t* tile2 = nullptr;
     uint32_t* nboff_whole = nullptr;  // the whole-cross-section tile, two contacts per word (null: none)
+    uint16_t* lanes_whole = nullptr;  // its lanes
     uint32_t* nboff2_whole = nullptr; // the same, one contact per word (its two-step table)
     int32_t* tile_whole = nullptr;    // {0, C, 0, C, 0, C}: tile, then its outer range
 };
 
 // Dynamic LDS of the walking kernels: the ring from address 0, kPadCols + span columns
 // (zero pad block, staged range) in whole blocks, then a fixed tail (the last kLdsTail bytes of
-// the launch's allocation): the code table (16 x 16 bytes: 1/deg, reach floor, self
-// weight per degree code), misc (16 words), part (256 floats).
+// the launch's allocation): the code table (1/deg per degree code: 16 words in a
+// 256-byte slot), misc (16 words), part (256 floats).
 constexpr uint32_t kLdsTail = 256u + 64u + 1024u;
 PERC_HD inline uint32_t lds_total(int32_t span) {
     const uint32_t blocks = (uint32_t)(span + kPadCols + kBlkCols - 1) / kBlkCols;
