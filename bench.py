@@ -34,7 +34,7 @@ BYTES_PER_TUBE_STEP = 8.375  # x read + write (4 + 4 B), occupancy bit, reach bi
 HBM_PEAK_GBS = 8000.0
 STEP_KERNEL = "k_span_step"
 STEP_KERNELS = {"span": "k_span_step", "plain": "k_span_step", "span2": "k_span_step2", "persist": "k_persist",
-                "persist2": "k_persist2"}
+                "persist2": "k_persist2", "mixed": "k_persist + k_span_step"}
 
 
 def log(*a):
@@ -117,12 +117,19 @@ def parity(groups, counts) -> dict:
             "mismatches": [i for i, (a, b) in enumerate(zip(got, want)) if a != b][:10]}
 
 
-def kernel_roofline(prof, kernel: str) -> dict:
-    """The step kernel's algorithmic bandwidth over its HIP-event time."""
-    ms, tubes = prof["step_ms"], prof["tube_steps"]
+def kernel_roofline(prof, kernel: str, part: str = "all") -> dict:
+    """The step kernel's algorithmic bandwidth over its HIP-event time: of every timed
+    launch, or of the persistent launches or the others alone (a mixed batch)."""
+    ms, tubes, launches = prof["step_ms"], prof["tube_steps"], prof["step_launches"]
+    if part == "persist":
+        ms, tubes, launches = prof["persist_ms"], prof["persist_tube_steps"], prof["persist_launches"]
+    elif part == "span":
+        ms -= prof["persist_ms"]
+        tubes -= prof["persist_tube_steps"]
+        launches -= prof["persist_launches"]
     gbs = tubes * BYTES_PER_TUBE_STEP / (ms / 1e3) / 1e9 if ms > 0 else None
     return {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS if gbs else None, "launches": prof["step_launches"], "kernel_ms": ms,
+            "frac": gbs / HBM_PEAK_GBS if gbs else None, "launches": launches, "kernel_ms": ms,
             "tube_steps": tubes, "bytes_per_tube_step": BYTES_PER_TUBE_STEP}
 
 
@@ -247,9 +254,11 @@ def uneven_leg(perc, workloads, stream, forced=None):
     from paper_1401_2130_amd import fss
     wl = workloads.UNEVEN
     lats = [perc.Lattice(*sh) for sh in wl.shapes]
-    # the tuning sample spans the sweep: 16 configurations of every shape at both p
+    # the tuning sample spans the sweep: 64 configurations of every shape at both p (6 %
+    # of the batch; smaller samples favour the span form over the mixed one, which wins on
+    # the whole batch)
     import numpy as np
-    sample = np.concatenate([perc.philox_jobs(lat, p, wl.seed, 16) for lat in lats for p in wl.ps])
+    sample = np.concatenate([perc.philox_jobs(lat, p, wl.seed, 64) for lat in lats for p in wl.ps])
     tuned = leg_settings(perc, sample, 0, stream, forced)
     opts = {k: tuned[k] for k in ("form", "depth", "block", "graph_steps")}
     torch_sync()
@@ -269,6 +278,13 @@ def uneven_leg(perc, workloads, stream, forced=None):
            "kernel_roofline": kernel_roofline(prof, STEP_KERNELS[tuned["form"]]),
            "pc_inf": ana.get("pc_inf"), "eq8": ana.get("eq8"),
            "shapes_with_pc": sum(1 for r in ana["shapes"] if r["pc"] is not None)}
+    if tuned["form"] == "mixed":
+        # the span part's step kernel dominates; the persistent part (fibers of at most four
+        # column tiles, beside it on a second stream) has its own line
+        out["kernel_roofline"] = kernel_roofline(prof, "k_span_step", "span")
+        out["persist_roofline"] = kernel_roofline(prof, "k_persist", "persist")
+        out["persist_roofline"]["note"] = ("the persistent launch also initialises its configurations and sums their "
+                                           "first-hit probability: its rate is a lower bound")
     gw = golden_workloads()
     if gw:
         keys = [(g["W"], g["L"], g["p"]) for g in gw["uneven"]["groups"]]
@@ -547,7 +563,7 @@ def main():
     ap.add_argument("--small", type=int, default=1, help="small plain workload leg (W=4 L=16 x 1000, one at a time)")
     ap.add_argument("--only", default="", choices=["", "small", "batched", "uneven", "serving"],
                     help="run this leg alone and print its JSON (profiling runs); not the benchmark line")
-    ap.add_argument("--leg-form", default="", choices=["", "span", "span2", "persist", "persist2"],
+    ap.add_argument("--leg-form", default="", choices=["", "span", "span2", "persist", "persist2", "mixed"],
                     help="batched and uneven legs: this form instead of the autotuner's choice (profiling runs)")
     ap.add_argument("--leg-depth", type=int, default=0, help="cells per work item with --leg-form")
     ap.add_argument("--batched", type=int, default=1, help="batched Pi(p) leg (W=16 L=256, 21 p x 4096)")

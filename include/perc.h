@@ -60,7 +60,10 @@ enum {
 
 /* Execution forms of an inspection batch (all give identical results). */
 enum {
-    PERC_FORM_AUTO = 0,    /* chosen from the shape and batch size (autotuned if cached) */
+    PERC_FORM_AUTO = 0,    /* chosen from the shape and batch size (autotuned if cached);
+                              a batch with at least 2048 jobs on fibers of at most four
+                              column tiles and some on wider fibers runs as
+                              PERC_FORM_MIXED */
     PERC_FORM_PLAIN = 1,   /* one configuration at a time; the host checks the stop flags
                               after every step (the paper's per-configuration loop) */
     PERC_FORM_SPAN = 2,    /* many configurations at once, each spread over workgroups;
@@ -75,11 +78,16 @@ enum {
                               computed from it, one pass over the state per two steps.
                               PERC_EINVAL for fibers whose outer range (the halo of the
                               halo range) exceeds two columns per thread or LDS */
-    PERC_FORM_PERSIST2 = 5 /* the persistent form advancing two steps per pass: one
+    PERC_FORM_PERSIST2 = 5, /* the persistent form advancing two steps per pass: one
                               workgroup holds the whole cross-section (one thread per
                               column, no halo), keeps the first step in LDS and writes the
                               second; PERC_EINVAL for fibers of more than 1024 columns
                               (W > 17). Reports PERC_ECAP as the persistent form */
+    PERC_FORM_MIXED = 6    /* per fiber: jobs on fibers of at most four column tiles
+                              (W <= 25) in the persistent form, the others in the span form
+                              (depth, block, grid and graph_steps apply to the span part),
+                              the two parts one after the other on the stream; outputs and
+                              group counts as for one batch */
 };
 
 typedef struct perc_options {
@@ -270,9 +278,12 @@ int perc_steps_hist(const uint8_t* perc, const int32_t* steps, int64_t n, int32_
 /* ---- profiling of the step kernel (span and plain forms) ------------------------- */
 
 typedef struct perc_profile {
-    int64_t step_launches; /* step-kernel launches timed */
-    double step_ms;        /* sum of their durations (HIP events on the launching stream) */
-    int64_t tube_steps;    /* tube slots those launches advanced by one step */
+    int64_t step_launches;      /* step-kernel launches timed */
+    double step_ms;             /* sum of their durations (HIP events on the launching stream) */
+    int64_t tube_steps;         /* tube slots those launches advanced by one step */
+    int64_t persist_launches;   /* the persistent launches among them */
+    double persist_ms;          /* their part of step_ms */
+    int64_t persist_tube_steps; /* their part of tube_steps */
 } perc_profile;
 
 /* Process-wide switch; resets the counters. While on, the span form and the server's
@@ -282,7 +293,8 @@ typedef struct perc_profile {
  * caller's (server's) stream, and count the tube slots the planner schedules; the
  * persistent form times its one persistent launch (initialisation and finishing
  * included, so its rate is a lower bound; sampling is a launch of its own) and counts
- * the tube slots of its steps, and runs synchronously. */
+ * the tube slots of its steps, and runs synchronously (the two parts of a mixed batch
+ * then run one after the other). */
 int perc_profile_enable(int32_t on);
 int perc_profile_read(perc_profile* out);
 
@@ -303,7 +315,8 @@ int perc_trim(void);
 /* ---- autotuning of the execution settings -------------------------------------- */
 /* Time candidate settings (span form with 32/64/80/128 cells per work item and one or two
  * block sizes, persistent form with 64/128/256, the two-step forms where the shapes allow
- * them) on the sample `jobs` (as perc_batch; group must be -1; a sample spread over the
+ * them, the mixed form with 64/80 cells per span item when the sample holds fibers of both
+ * kinds) on the sample `jobs` (as perc_batch; group must be -1; a sample spread over the
  * batch's p values and shapes represents it best) and return the fastest in *best (wall
  * time of the whole sample, ms, in *best_ms; either may be NULL). If every job has the
  * same (W, L), the choice is also

@@ -24,9 +24,9 @@ LIB_PATH = os.path.join(_PKG, "_build", "libperc.so")
 
 PERC_OK, PERC_EINVAL, PERC_ENOMEM, PERC_EHIP, PERC_EBUSY, PERC_ECANCELED, PERC_ECAP = 0, -1, -2, -3, -4, -5, -6
 PERC_LATTICE_NO_END_CONTACTS = 1
-FORM_AUTO, FORM_PLAIN, FORM_SPAN, FORM_PERSIST, FORM_SPAN2, FORM_PERSIST2 = 0, 1, 2, 3, 4, 5
+FORM_AUTO, FORM_PLAIN, FORM_SPAN, FORM_PERSIST, FORM_SPAN2, FORM_PERSIST2, FORM_MIXED = 0, 1, 2, 3, 4, 5, 6
 _FORMS = {"auto": FORM_AUTO, "plain": FORM_PLAIN, "span": FORM_SPAN, "persist": FORM_PERSIST, "span2": FORM_SPAN2,
-          "persist2": FORM_PERSIST2}
+          "persist2": FORM_PERSIST2, "mixed": FORM_MIXED}
 
 
 class PercError(RuntimeError):
@@ -41,7 +41,8 @@ class perc_options(C.Structure):
 
 
 class perc_profile(C.Structure):
-    _fields_ = [("step_launches", C.c_int64), ("step_ms", C.c_double), ("tube_steps", C.c_int64)]
+    _fields_ = [("step_launches", C.c_int64), ("step_ms", C.c_double), ("tube_steps", C.c_int64),
+                ("persist_launches", C.c_int64), ("persist_ms", C.c_double), ("persist_tube_steps", C.c_int64)]
 
 
 class perc_job(C.Structure):
@@ -428,7 +429,8 @@ def perc_profile_read() -> dict:
     out = perc_profile()
     _check(_lib.perc_profile_read(C.byref(out)))
     return {"step_launches": int(out.step_launches), "step_ms": float(out.step_ms),
-            "tube_steps": int(out.tube_steps)}
+            "tube_steps": int(out.tube_steps), "persist_launches": int(out.persist_launches),
+            "persist_ms": float(out.persist_ms), "persist_tube_steps": int(out.persist_tube_steps)}
 
 
 def perc_state_after(lat: Lattice, occ: torch.Tensor, K: int, x=None, reach=None, stream=None):

@@ -1749,6 +1749,18 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, int6
         p[i] = v;
 }
 
+__global__ void __launch_bounds__(256) k_scatter_out(int64_t n, const int64_t* __restrict__ idx,
+                                                     const uint8_t* __restrict__ perc, const int32_t* __restrict__ steps,
+                                                     const float* __restrict__ hit, uint8_t* __restrict__ perc_out,
+                                                     int32_t* __restrict__ steps_out, float* __restrict__ hit_out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = idx[i];
+        perc_out[j] = perc[i];
+        steps_out[j] = steps[i];
+        if (hit) hit_out[j] = hit[i];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_count(const uint8_t* __restrict__ perc, int64_t n,
                                                unsigned long long* count) {
     __shared__ unsigned long long red;
@@ -1880,6 +1892,16 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_out(int64_t n, const int64_t* idx, const uint8_t* perc, const int32_t* steps,
+                              const float* hit, uint8_t* perc_out, int32_t* steps_out, float* hit_out,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_scatter_out, dim3(grid), dim3(256), 0, s, n, idx, perc, steps, hit, perc_out, steps_out,
+                       hit_out);
     return hipGetLastError();
 }
 

@@ -168,24 +168,49 @@ struct WorkCache {
     hipEvent_t done = nullptr;  // recorded on the last borrower's stream when returned
     bool pending = false;
 };
-WorkCache g_cache[kCacheDevices];
+// Per device: the buffer of the callers' streams, and one for the library's side stream
+// (below), whose work runs beside a caller's.
+WorkCache g_cache[kCacheDevices][2];
 
-// The bytes of the cached buffer a new call could borrow (counted as free memory by
+// A second stream per device for the persistent part of a mixed batch (created on first
+// use, default priority, kept for the process).
+std::mutex g_side_mu;
+hipStream_t g_side[kCacheDevices] = {};
+int side_stream(hipStream_t* out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kCacheDevices) return fail(PERC_EINVAL, "device index beyond the library's table");
+    std::lock_guard<std::mutex> g(g_side_mu);
+    if (!g_side[dev]) HIP_TRY(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
+    *out = g_side[dev];
+    return PERC_OK;
+}
+
+bool is_side_stream(int dev, hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_side_mu);
+    return s && s == g_side[dev];
+}
+
+// The bytes of the cached buffers a new call could borrow (counted as free memory by
 // the budgets, since hipMemGetInfo reports them as used).
 size_t cache_idle_bytes() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kCacheDevices) return 0;
-    WorkCache& c = g_cache[dev];
-    std::lock_guard<std::mutex> g(c.mu);
-    return c.busy ? 0 : c.size;
+    size_t idle = 0;
+    for (WorkCache& c : g_cache[dev]) {
+        std::lock_guard<std::mutex> g(c.mu);
+        idle += c.busy ? 0 : c.size;
+    }
+    return idle;
 }
 
-// Borrow at least `bytes` of the device's buffer for work on stream s; nullptr when it
-// is lent out, the device is out of range or it cannot grow (the caller then allocates).
+// Borrow at least `bytes` of the device's buffer for work on stream s (the side stream's
+// own buffer for work on it); nullptr when it is lent out, the device is out of range or
+// it cannot grow (the caller then allocates).
 char* cache_borrow(size_t bytes, hipStream_t s, WorkCache** owner) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kCacheDevices) return nullptr;
-    WorkCache& c = g_cache[dev];
+    WorkCache& c = g_cache[dev][is_side_stream(dev, s) ? 1 : 0];
     std::lock_guard<std::mutex> g(c.mu);
     if (c.busy) return nullptr;
     if (!c.done && hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess) {
@@ -226,14 +251,15 @@ int cache_trim() {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= kCacheDevices) return PERC_OK;
-    WorkCache& c = g_cache[dev];
-    std::lock_guard<std::mutex> g(c.mu);
-    if (c.busy) return fail(PERC_EBUSY, "the work buffer is in use by a call");
-    if (c.pending) HIP_TRY(hipEventSynchronize(c.done));
-    c.pending = false;
-    if (c.base) HIP_TRY(hipFree(c.base));
-    c.base = nullptr;
-    c.size = 0;
+    for (WorkCache& c : g_cache[dev]) {
+        std::lock_guard<std::mutex> g(c.mu);
+        if (c.busy) return fail(PERC_EBUSY, "the work buffer is in use by a call");
+        if (c.pending) HIP_TRY(hipEventSynchronize(c.done));
+        c.pending = false;
+        if (c.base) HIP_TRY(hipFree(c.base));
+        c.base = nullptr;
+        c.size = 0;
+    }
     return PERC_OK;
 }
 
@@ -323,6 +349,9 @@ struct Profiler {
     int64_t launches = 0;
     double ms = 0.0;
     int64_t tube_steps = 0;
+    int64_t p_launches = 0;  // the persistent launches' part
+    double p_ms = 0.0;
+    int64_t p_tube_steps = 0;
 };
 Profiler g_prof;
 
@@ -899,6 +928,9 @@ int run_persist_chunk(const std::vector<HostJob>& jobs, int64_t j0, int64_t j1, 
     g_prof.launches += 1;
     g_prof.ms += ms;
     g_prof.tube_steps += (int64_t)tubes;
+    g_prof.p_launches += 1;
+    g_prof.p_ms += ms;
+    g_prof.p_tube_steps += (int64_t)tubes;
     return PERC_OK;
 }
 
@@ -935,7 +967,90 @@ int validate_lat(const perc_lattice* lat) {
 }
 
 // Run a list of jobs with outputs indexed by job (device pointers; steps required).
+int run_jobs(const std::vector<HostJob>& jobs, BatchOut out, const perc_options* opt, hipStream_t s);
+
+// The mixed form: the jobs on fibers of at most kMixedTiles column tiles in the persistent
+// form, the others in the span form (opt's depth, block, grid and graph steps apply to
+// the span part). The persistent part is one launch on a second stream, which runs beside
+// the span part's steps on the caller's stream (the span form's short walks leave the
+// device room); each part writes its outputs to a buffer of its own, scattered to the
+// jobs' places on the caller's stream once both are done; group counts and the step-cap
+// flag accumulate in the batch's own. A persistent workgroup walks its configuration's
+// tiles one after another, so it suits fibers of few tiles; the span form spreads the
+// tiles of wide fibers over workgroups.
+int run_mixed(const std::vector<HostJob>& jobs, BatchOut out, const perc_options* opt, hipStream_t s) {
+    std::vector<HostJob> part[2];
+    std::vector<int64_t> idx;
+    idx.reserve(jobs.size());
+    for (int k = 0; k < 2; ++k)
+        for (int64_t i = 0; i < (int64_t)jobs.size(); ++i)
+            if ((jobs[i].lat->d.ntile > kMixedTiles) == (k == 1)) {
+                part[k].push_back(jobs[i]);
+                idx.push_back(i);
+            }
+    perc_options o[2] = {perc_options{FORM_PERSIST, 0, 0, 0, 0}, opt ? *opt : perc_options{}};
+    o[1].form = FORM_SPAN;
+    if (part[0].empty() || part[1].empty()) return run_jobs(jobs, out, &o[part[0].empty() ? 1 : 0], s);
+    const int64_t n = (int64_t)jobs.size();
+    Arena ar;
+    PERC_TRY(ar.reserve(Arena::need<int64_t>(n) + Arena::need<uint8_t>(n) + Arena::need<int32_t>(n) +
+                            (out.hit ? Arena::need<float>(n) : 0), s));
+    int64_t* d_idx = ar.take<int64_t>(n);
+    uint8_t* t_perc = ar.take<uint8_t>(n);
+    int32_t* t_steps = ar.take<int32_t>(n);
+    float* t_hit = out.hit ? ar.take<float>(n) : nullptr;
+    PERC_TRY(ar.check());
+    HIP_TRY(hipMemcpyAsync(d_idx, idx.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+    hipStream_t side = nullptr;
+    PERC_TRY(side_stream(&side));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (hipEvent_t& e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    BatchOut po[2] = {out, out};
+    po[0].perc = t_perc;
+    po[0].steps = t_steps;
+    po[0].hit = t_hit;
+    const int64_t n0 = (int64_t)part[0].size();
+    po[1].perc = t_perc + n0;
+    po[1].steps = t_steps + n0;
+    po[1].hit = t_hit ? t_hit + n0 : nullptr;
+    int rc[2] = {PERC_OK, PERC_OK};
+    // the persistent part on the side stream, after everything enqueued so far on s
+    hipError_t e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, ev[0], 0);
+    if (e == hipSuccess) {
+        rc[0] = run_jobs(part[0], po[0], &o[0], side);
+        e = hipEventRecord(ev[1], side);
+        // the span part on s meanwhile; s then waits for the side stream
+        if (e == hipSuccess && (rc[0] == PERC_OK || rc[0] == PERC_ECAP)) rc[1] = run_jobs(part[1], po[1], &o[1], s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ev[1], 0);
+        if (e != hipSuccess) (void)hipStreamSynchronize(side);  // no event: wait here instead
+    }
+    for (hipEvent_t ee : ev) (void)hipEventDestroy(ee);
+    HIP_TRY(e);
+    for (int k = 0; k < 2; ++k)
+        if (rc[k] != PERC_OK && rc[k] != PERC_ECAP) return rc[k];
+    HIP_TRY(launch_scatter_out(n, d_idx, t_perc, t_steps, t_hit, out.perc, out.steps, out.hit, s));
+    return rc[0] != PERC_OK ? rc[0] : rc[1];
+}
+
+// Jobs on fibers of at most kMixedTiles tiles, and the others.
+void count_kinds(const std::vector<HostJob>& jobs, int64_t& n_narrow, int64_t& n_wide) {
+    n_narrow = n_wide = 0;
+    for (const HostJob& j : jobs) (j.lat->d.ntile > kMixedTiles ? n_wide : n_narrow) += 1;
+}
+
 int run_jobs(const std::vector<HostJob>& jobs, BatchOut out, const perc_options* opt, hipStream_t s) {
+    if (opt && opt->form == FORM_MIXED) return run_mixed(jobs, out, opt, s);
+    if (!opt || opt->form == FORM_AUTO) {
+        // a batch of both kinds with many narrow fibers: each kind in its own form
+        int64_t n_narrow, n_wide;
+        count_kinds(jobs, n_narrow, n_wide);
+        if (n_narrow >= 2048 && n_wide > 0) {
+            perc_options o = opt ? *opt : perc_options{};
+            o.form = FORM_MIXED;
+            return run_mixed(jobs, out, &o, s);
+        }
+    }
     Shapes S;
     collect_shapes(jobs, S);
     TuneKey key{0, 0, 0};
@@ -1038,6 +1153,10 @@ int autotune(const std::vector<HostJob>& hj, int64_t n_target, perc_options* bes
         for (int32_t depth : {64, 128}) cands.push_back(perc_options{FORM_PERSIST2, depth, 0, 0, 0});
     if (two_step_fits(S.need, b0))
         for (int32_t depth : {64, 128}) cands.push_back(perc_options{FORM_SPAN2, depth, b0, 0, 16});
+    int64_t n_narrow, n_wide;
+    count_kinds(hj, n_narrow, n_wide);
+    if (n_narrow > 0 && n_wide > 0)
+        for (int32_t depth : {64, 80}) cands.push_back(perc_options{FORM_MIXED, depth, 0, 0, 16});
     const int64_t n = (int64_t)hj.size();
     Arena ar;
     PERC_TRY(ar.reserve(Arena::align((size_t)n) + Arena::align(4 * (size_t)n), s));
@@ -1961,6 +2080,9 @@ int perc_profile_enable(int32_t on) {
     g_prof.launches = 0;
     g_prof.ms = 0.0;
     g_prof.tube_steps = 0;
+    g_prof.p_launches = 0;
+    g_prof.p_ms = 0.0;
+    g_prof.p_tube_steps = 0;
     return PERC_OK;
 }
 
@@ -1970,6 +2092,9 @@ int perc_profile_read(perc_profile* out) {
     out->step_launches = g_prof.launches;
     out->step_ms = g_prof.ms;
     out->tube_steps = g_prof.tube_steps;
+    out->persist_launches = g_prof.p_launches;
+    out->persist_ms = g_prof.p_ms;
+    out->persist_tube_steps = g_prof.p_tube_steps;
     return PERC_OK;
 }
 

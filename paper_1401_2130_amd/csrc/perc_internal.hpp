@@ -216,7 +216,10 @@ enum Form : int32_t {
     FORM_SPAN2 = 4,    // the span form with two steps per launch (one pass over HBM)
     FORM_PERSIST2 = 5, // the persistent form with two steps per pass over the whole
                        // cross-section (fibers of at most kWholeCols columns)
+    FORM_MIXED = 6,    // per fiber: the persistent form for fibers of at most kMixedTiles
+                       // column tiles, the span form for wider ones (two runs in turn)
 };
+constexpr int32_t kMixedTiles = 4;
 
 struct Tuning {
     int32_t form = FORM_AUTO;
@@ -398,6 +401,11 @@ hipError_t launch_export(const DevShape& sh, const float* y, const uint8_t* code
 // Count of percolating configurations (integer, deterministic).
 hipError_t launch_count(const uint8_t* perc, int64_t n, unsigned long long* count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+// Outputs of job i of a part (perc, steps and, if non-null, hit) to the places of job
+// idx[i] of the batch.
+hipError_t launch_scatter_out(int64_t n, const int64_t* idx, const uint8_t* perc, const int32_t* steps,
+                              const float* hit, uint8_t* perc_out, int32_t* steps_out, float* hit_out,
+                              hipStream_t s);
 
 int persist_resident_per_cu(int block, int lds_bytes);
 

@@ -40,6 +40,47 @@ def test_autotune_mixed_shapes(perc):
         perc.perc_autotune([])
 
 
+def test_mixed_form_equals_span(perc):
+    """The mixed form (fibers of at most four column tiles in the persistent form, wider
+    ones in the span form, outputs scattered back to the jobs' places) and the automatic
+    form, which picks it for this batch, give every bit, step count and FP32 first-hit
+    probability of the span form and the same group counts; the wide fibers' bits equal
+    the oracle's breadth-first search."""
+    import oracle
+    narrow, wide = perc.Lattice(8, 16), perc.Lattice(26, 7)  # 217 columns; 2,107 columns = 5 tiles
+    jobs = np.concatenate([perc.philox_jobs(narrow, 0.25, 5, 2100, group=0),
+                           perc.philox_jobs(wide, 0.17, 6, 40, group=1),
+                           perc.philox_jobs(narrow, 0.3, 7, 100, group=2)])
+    jobs = jobs[np.random.default_rng(1).permutation(len(jobs))]  # the two kinds interleaved
+    outs = {f: perc.perc_batch(jobs, n_groups=3, hit=True, form=f) for f in ("span", "mixed", "auto")}
+    torch.cuda.synchronize()
+    p0, s0, h0, c0 = outs["span"]
+    for f in ("mixed", "auto"):
+        p1, s1, h1, c1 = outs[f]
+        assert torch.equal(p0, p1) and torch.equal(s0, s1), f
+        assert torch.equal(h0.view(torch.int32), h1.view(torch.int32)), f
+        assert list(c0) == list(c1), f
+    # profiled, the two parts run one after the other; the persistent launches are
+    # counted apart from the span form's step launches
+    perc.perc_profile_enable(True)
+    try:
+        p2, s2, h2, c2 = perc.perc_batch(jobs, n_groups=3, hit=True, form="mixed")
+        torch.cuda.synchronize()
+        prof = perc.perc_profile_read()
+    finally:
+        perc.perc_profile_enable(False)
+    assert torch.equal(p0, p2) and torch.equal(s0, s2) and list(c0) == list(c2)
+    assert 1 <= prof["persist_launches"] < prof["step_launches"]
+    assert 0.0 < prof["persist_ms"] < prof["step_ms"]
+    assert 0 < prof["persist_tube_steps"] < prof["tube_steps"]
+    sel = np.nonzero(jobs["group"] == 1)[0]
+    sel = sel[np.argsort(jobs["cfg"][sel])]
+    ref = oracle.Lattice(26, 7)
+    pb, _ = ref.inspect_bfs(ref.sample(0.17, 6, 40))
+    np.testing.assert_array_equal(p0.cpu().numpy()[sel], pb)
+    assert c0[1] == int(pb.sum())
+
+
 def test_pi_table_matches_pi_ex(perc):
     from paper_1401_2130_amd import fss
     shapes, ps, n, seed = [(4, 16), (3, 10), (0, 9)], [0.2, 0.45, 0.9], 200, 77
