@@ -279,8 +279,8 @@ def uneven_leg(perc, workloads, stream, forced=None):
            "pc_inf": ana.get("pc_inf"), "eq8": ana.get("eq8"),
            "shapes_with_pc": sum(1 for r in ana["shapes"] if r["pc"] is not None)}
     if tuned["form"] == "mixed":
-        # the span part's step kernel dominates; the persistent part (fibers of at most four
-        # column tiles, beside it on a second stream) has its own line
+        # the span part's step kernel dominates; the persistent part (short-walk fibers,
+        # beside it on a second stream) has its own line
         out["kernel_roofline"] = kernel_roofline(prof, "k_span_step", "span")
         out["persist_roofline"] = kernel_roofline(prof, "k_persist", "persist")
         out["persist_roofline"]["note"] = ("the persistent launch also initialises its configurations and sums their "

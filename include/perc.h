@@ -61,9 +61,8 @@ enum {
 /* Execution forms of an inspection batch (all give identical results). */
 enum {
     PERC_FORM_AUTO = 0,    /* chosen from the shape and batch size (autotuned if cached);
-                              a batch with at least 2048 jobs on fibers of at most four
-                              column tiles and some on wider fibers runs as
-                              PERC_FORM_MIXED */
+                              a batch with at least 2048 jobs on short-walk fibers (below)
+                              and some on others runs as PERC_FORM_MIXED */
     PERC_FORM_PLAIN = 1,   /* one configuration at a time; the host checks the stop flags
                               after every step (the paper's per-configuration loop) */
     PERC_FORM_SPAN = 2,    /* many configurations at once, each spread over workgroups;
@@ -83,11 +82,12 @@ enum {
                               column, no halo), keeps the first step in LDS and writes the
                               second; PERC_EINVAL for fibers of more than 1024 columns
                               (W > 17). Reports PERC_ECAP as the persistent form */
-    PERC_FORM_MIXED = 6    /* per fiber: jobs on fibers of at most four column tiles
-                              (W <= 25) in the persistent form, the others in the span form
-                              (depth, block, grid and graph_steps apply to the span part),
-                              the two parts one after the other on the stream; outputs and
-                              group counts as for one batch */
+    PERC_FORM_MIXED = 6    /* per fiber: jobs on short-walk fibers (column tiles of at most
+                              512 columns x unit cells ceil(L/3) <= 600) in the persistent
+                              form on a second stream of the library's, the others in the
+                              span form on `stream` beside it (depth, block, grid and
+                              graph_steps apply to the span part); outputs and group counts
+                              as for one batch, complete when `stream` reaches them */
 };
 
 typedef struct perc_options {

@@ -969,22 +969,29 @@ int validate_lat(const perc_lattice* lat) {
 // Run a list of jobs with outputs indexed by job (device pointers; steps required).
 int run_jobs(const std::vector<HostJob>& jobs, BatchOut out, const perc_options* opt, hipStream_t s);
 
-// The mixed form: the jobs on fibers of at most kMixedTiles column tiles in the persistent
-// form, the others in the span form (opt's depth, block, grid and graph steps apply to
-// the span part). The persistent part is one launch on a second stream, which runs beside
-// the span part's steps on the caller's stream (the span form's short walks leave the
-// device room); each part writes its outputs to a buffer of its own, scattered to the
-// jobs' places on the caller's stream once both are done; group counts and the step-cap
-// flag accumulate in the batch's own. A persistent workgroup walks its configuration's
-// tiles one after another, so it suits fibers of few tiles; the span form spreads the
-// tiles of wide fibers over workgroups.
+// Fibers the mixed form runs in the span form: those whose step over every tile and cell,
+// which a persistent workgroup walks alone, is long (column tiles x unit cells above
+// kMixedWork). On the aspect-ratio sweep (W = 8..32, L = W..64 W) limits of 600 to 3,600
+// gave the same time within 2 %, 4-6 % below the span form alone; the near-cubic
+// ablation fibers (at most 112) stay persistent, 27 % faster than split by width.
+bool wide_fiber(const LatticeDesc& d) { return (int64_t)d.ntile * d.U > kMixedWork; }
+
+// The mixed form: the jobs on short-walk fibers (wide_fiber false) in the persistent form,
+// the others in the span form (opt's depth, block, grid and graph steps apply to the span
+// part). The persistent part is one launch on a second stream, which runs beside the
+// span part's steps on the caller's stream (the span form's short walks leave the device
+// room); each part writes its outputs to a buffer of its own, scattered to the jobs'
+// places on the caller's stream once both are done; group counts and the step-cap flag
+// accumulate in the batch's own. A persistent workgroup walks its configuration's tiles
+// and cells one after another, so it suits short walks; the span form spreads the tiles
+// and cell ranges of long ones over workgroups.
 int run_mixed(const std::vector<HostJob>& jobs, BatchOut out, const perc_options* opt, hipStream_t s) {
     std::vector<HostJob> part[2];
     std::vector<int64_t> idx;
     idx.reserve(jobs.size());
     for (int k = 0; k < 2; ++k)
         for (int64_t i = 0; i < (int64_t)jobs.size(); ++i)
-            if ((jobs[i].lat->d.ntile > kMixedTiles) == (k == 1)) {
+            if (wide_fiber(jobs[i].lat->d) == (k == 1)) {
                 part[k].push_back(jobs[i]);
                 idx.push_back(i);
             }
@@ -1033,10 +1040,10 @@ int run_mixed(const std::vector<HostJob>& jobs, BatchOut out, const perc_options
     return rc[0] != PERC_OK ? rc[0] : rc[1];
 }
 
-// Jobs on fibers of at most kMixedTiles tiles, and the others.
+// Jobs on short-walk fibers, and the others.
 void count_kinds(const std::vector<HostJob>& jobs, int64_t& n_narrow, int64_t& n_wide) {
     n_narrow = n_wide = 0;
-    for (const HostJob& j : jobs) (j.lat->d.ntile > kMixedTiles ? n_wide : n_narrow) += 1;
+    for (const HostJob& j : jobs) (wide_fiber(j.lat->d) ? n_wide : n_narrow) += 1;
 }
 
 int run_jobs(const std::vector<HostJob>& jobs, BatchOut out, const perc_options* opt, hipStream_t s) {

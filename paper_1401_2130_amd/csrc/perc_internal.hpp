@@ -216,10 +216,10 @@ enum Form : int32_t {
     FORM_SPAN2 = 4,    // the span form with two steps per launch (one pass over HBM)
     FORM_PERSIST2 = 5, // the persistent form with two steps per pass over the whole
                        // cross-section (fibers of at most kWholeCols columns)
-    FORM_MIXED = 6,    // per fiber: the persistent form for fibers of at most kMixedTiles
-                       // column tiles, the span form for wider ones (two runs in turn)
+    FORM_MIXED = 6,    // per fiber: the persistent form for short walks (column tiles x
+                       // unit cells at most kMixedWork), the span form beside it for the rest
 };
-constexpr int32_t kMixedTiles = 4;
+constexpr int64_t kMixedWork = 600;
 
 struct Tuning {
     int32_t form = FORM_AUTO;

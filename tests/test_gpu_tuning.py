@@ -41,13 +41,14 @@ def test_autotune_mixed_shapes(perc):
 
 
 def test_mixed_form_equals_span(perc):
-    """The mixed form (fibers of at most four column tiles in the persistent form, wider
-    ones in the span form, outputs scattered back to the jobs' places) and the automatic
-    form, which picks it for this batch, give every bit, step count and FP32 first-hit
-    probability of the span form and the same group counts; the wide fibers' bits equal
-    the oracle's breadth-first search."""
+    """The mixed form (short-walk fibers in the persistent form, the others in the span
+    form beside it, outputs scattered back to the jobs' places) and the automatic form,
+    which picks it for this batch, give every bit, step count and FP32 first-hit
+    probability of the span form and the same group counts; the long-walk fibers' bits
+    equal the oracle's breadth-first search."""
     import oracle
-    narrow, wide = perc.Lattice(8, 16), perc.Lattice(26, 7)  # 217 columns; 2,107 columns = 5 tiles
+    # 1 tile x 6 cells; 2,107 columns = 5 tiles x 134 cells (above 600: the span part)
+    narrow, wide = perc.Lattice(8, 16), perc.Lattice(26, 400)
     jobs = np.concatenate([perc.philox_jobs(narrow, 0.25, 5, 2100, group=0),
                            perc.philox_jobs(wide, 0.17, 6, 40, group=1),
                            perc.philox_jobs(narrow, 0.3, 7, 100, group=2)])
@@ -75,7 +76,7 @@ def test_mixed_form_equals_span(perc):
     assert 0 < prof["persist_tube_steps"] < prof["tube_steps"]
     sel = np.nonzero(jobs["group"] == 1)[0]
     sel = sel[np.argsort(jobs["cfg"][sel])]
-    ref = oracle.Lattice(26, 7)
+    ref = oracle.Lattice(26, 400)
     pb, _ = ref.inspect_bfs(ref.sample(0.17, 6, 40))
     np.testing.assert_array_equal(p0.cpu().numpy()[sel], pb)
     assert c0[1] == int(pb.sum())
