@@ -82,9 +82,10 @@ enum {
                               column, no halo), keeps the first step in LDS and writes the
                               second; PERC_EINVAL for fibers of more than 1024 columns
                               (W > 17). Reports PERC_ECAP as the persistent form */
-    PERC_FORM_MIXED = 6    /* per fiber: jobs on short-walk fibers (column tiles of at most
-                              512 columns x unit cells ceil(L/3) <= 600) in the persistent
-                              form on a second stream of the library's, the others in the
+    PERC_FORM_MIXED = 6    /* per fiber: jobs on short-walk fibers (one column tile of at
+                              most 512 columns, or column tiles x unit cells ceil(L/3) <=
+                              600) in the persistent form on a second stream of the
+                              library's, the others in the
                               span form on `stream` beside it (depth, block, grid and
                               graph_steps apply to the span part); outputs and group counts
                               as for one batch, complete when `stream` reaches them */

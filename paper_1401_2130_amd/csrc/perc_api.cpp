@@ -969,12 +969,14 @@ int validate_lat(const perc_lattice* lat) {
 // Run a list of jobs with outputs indexed by job (device pointers; steps required).
 int run_jobs(const std::vector<HostJob>& jobs, BatchOut out, const perc_options* opt, hipStream_t s);
 
-// Fibers the mixed form runs in the span form: those whose step over every tile and cell,
-// which a persistent workgroup walks alone, is long (column tiles x unit cells above
-// kMixedWork). On the aspect-ratio sweep (W = 8..32, L = W..64 W) limits of 600 to 3,600
-// gave the same time within 2 %, 4-6 % below the span form alone; the near-cubic
-// ablation fibers (at most 112) stay persistent, 27 % faster than split by width.
-bool wide_fiber(const LatticeDesc& d) { return (int64_t)d.ntile * d.U > kMixedWork; }
+// Fibers the mixed form runs in the span form: those of several column tiles whose step
+// over every tile and cell, which a persistent workgroup walks alone, is long (tiles x
+// unit cells above kMixedWork). On the aspect-ratio sweep (W = 8..32, L = W..64 W) limits
+// of 600 to 3,600 gave the same time within 2 %, 4-6 % below the span form alone; the
+// near-cubic ablation fibers (at most 112) stay persistent, 27 % faster than split by
+// width; so do fibers of one tile, however long (W = 3, L up to 3,072: 20 % faster than
+// with their long ones in the span form, whose items of a 37-column tile are too small).
+bool wide_fiber(const LatticeDesc& d) { return d.ntile > 1 && (int64_t)d.ntile * d.U > kMixedWork; }
 
 // The mixed form: the jobs on short-walk fibers (wide_fiber false) in the persistent form,
 // the others in the span form (opt's depth, block, grid and graph steps apply to the span
