@@ -1000,6 +1000,8 @@ int run_mixed(const std::vector<HostJob>& jobs, BatchOut out, const perc_options
     perc_options o[2] = {perc_options{FORM_PERSIST, 0, 0, 0, 0}, opt ? *opt : perc_options{}};
     o[1].form = FORM_SPAN;
     if (part[0].empty() || part[1].empty()) return run_jobs(jobs, out, &o[part[0].empty() ? 1 : 0], s);
+    // the span part synchronises; checked before the side stream is tied to s
+    if (stream_capturing(s)) return fail(PERC_EINVAL, "the mixed form synchronises; not capturable");
     const int64_t n = (int64_t)jobs.size();
     Arena ar;
     PERC_TRY(ar.reserve(Arena::need<int64_t>(n) + Arena::need<uint8_t>(n) + Arena::need<int32_t>(n) +
