@@ -101,3 +101,42 @@ def test_threads_share_the_buffer(perc):
         for n, b, s in got[c]:
             assert n == ref[c][0]
             assert torch.equal(b, ref[c][1]) and torch.equal(s, ref[c][2])
+
+
+def test_threads_share_the_side_stream(perc):
+    """Two host threads running mixed batches at once (each batch's short-walk part on the
+    library's one side stream and its work buffer, the long-walk part on the thread's own
+    stream): every result equals its serial run."""
+    import numpy as np
+    narrow, wide = perc.Lattice(8, 16), perc.Lattice(26, 400)
+    batches = [np.concatenate([perc.philox_jobs(narrow, p, seed, 2100, group=0),
+                               perc.philox_jobs(wide, 0.17, seed + 1, 24, group=1)])
+               for p, seed in ((0.25, 41), (0.3, 43))]
+    ref = []
+    for jobs in batches:
+        pr, sr, _, cr = perc.perc_batch(jobs, n_groups=2, form="mixed")
+        torch.cuda.synchronize()
+        ref.append((pr.cpu(), sr.cpu(), list(cr)))
+    got, errors = {}, []
+
+    def worker(i):
+        try:
+            st = torch.cuda.Stream()
+            for _ in range(2):
+                pr, sr, _, cr = perc.perc_batch(batches[i], n_groups=2, form="mixed", stream=st)
+                st.synchronize()
+                got.setdefault(i, []).append((pr.cpu(), sr.cpu(), list(cr)))
+        except Exception as e:  # reported below
+            errors.append(repr(e))
+
+    th = [threading.Thread(target=worker, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not errors, errors
+    for i in range(2):
+        assert len(got[i]) == 2
+        for pr, sr, cr in got[i]:
+            assert torch.equal(pr, ref[i][0]) and torch.equal(sr, ref[i][1]) and cr == ref[i][2]
+
