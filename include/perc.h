@@ -35,7 +35,9 @@
  *    keeps between calls (it grows in 1 GiB steps to the largest need seen; a batch
  *    runs in waves of at most 128 GiB and half the free memory) and lends to one call
  *    at a time, stream-ordered behind the previous borrower's work; a call that finds
- *    it lent to another thread allocates its own. perc_trim releases it.
+ *    it lent to another thread allocates its own. The persistent part of a mixed batch
+ *    runs on a second stream the library keeps per device, with a second such buffer.
+ *    perc_trim releases both buffers.
  *  - Errors: a negative PERC_E* code; perc_last_error() gives a message (per thread,
  *    valid until the next call on that thread). No call aborts the process.
  */
@@ -308,8 +310,8 @@ int perc_profile_read(perc_profile* out);
 int perc_stream_copy(const void* src, void* dst, int64_t bytes, int32_t grid, void* stream);
 
 /* ---- work memory ----------------------------------------------------------------- */
-/* Release the work buffer the library keeps on the current device (waiting for the work
- * of its last borrower first). PERC_EBUSY if a call is using it; the next call that
+/* Release the work buffers the library keeps on the current device (waiting for the work
+ * of their last borrowers first). PERC_EBUSY if a call is using one; the next call that
  * needs large work memory allocates it again. */
 int perc_trim(void);
 
