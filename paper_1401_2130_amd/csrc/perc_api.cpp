@@ -251,16 +251,20 @@ int cache_trim() {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= kCacheDevices) return PERC_OK;
+    bool busy = false;  // the idle buffers are released even when another is lent out
     for (WorkCache& c : g_cache[dev]) {
         std::lock_guard<std::mutex> g(c.mu);
-        if (c.busy) return fail(PERC_EBUSY, "the work buffer is in use by a call");
+        if (c.busy) {
+            busy = true;
+            continue;
+        }
         if (c.pending) HIP_TRY(hipEventSynchronize(c.done));
         c.pending = false;
         if (c.base) HIP_TRY(hipFree(c.base));
         c.base = nullptr;
         c.size = 0;
     }
-    return PERC_OK;
+    return busy ? fail(PERC_EBUSY, "a work buffer is in use by a call") : PERC_OK;
 }
 
 // A device allocation that, when the device is short of memory, releases the idle work
@@ -269,7 +273,7 @@ int device_alloc(void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
     if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
-        if (cache_trim() == PERC_OK) e = hipMalloc(p, bytes);
+        if (cache_trim() != PERC_EHIP) e = hipMalloc(p, bytes);  // whatever it could release
     }
     if (e != hipSuccess) {
         *p = nullptr;
@@ -306,7 +310,7 @@ struct Arena {
         hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base), size, s);
         if (e == hipErrorOutOfMemory) {
             (void)hipGetLastError();
-            if (cache_trim() == PERC_OK) e = hipMallocAsync(reinterpret_cast<void**>(&base), size, s);
+            if (cache_trim() != PERC_EHIP) e = hipMallocAsync(reinterpret_cast<void**>(&base), size, s);
         }
         if (e != hipSuccess) {
             base = nullptr;
