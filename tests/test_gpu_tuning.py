@@ -62,18 +62,20 @@ def test_mixed_form_equals_span(perc):
         assert torch.equal(h0.view(torch.int32), h1.view(torch.int32)), f
         assert list(c0) == list(c1), f
     # profiled, the two parts run one after the other; the persistent launches are
-    # counted apart from the span form's step launches
-    perc.perc_profile_enable(True)
-    try:
-        p2, s2, h2, c2 = perc.perc_batch(jobs, n_groups=3, hit=True, form="mixed")
-        torch.cuda.synchronize()
-        prof = perc.perc_profile_read()
-    finally:
-        perc.perc_profile_enable(False)
-    assert torch.equal(p0, p2) and torch.equal(s0, s2) and list(c0) == list(c2)
-    assert 1 <= prof["persist_launches"] < prof["step_launches"]
-    assert 0.0 < prof["persist_ms"] < prof["step_ms"]
-    assert 0 < prof["persist_tube_steps"] < prof["tube_steps"]
+    # counted apart from the span form's step launches (for the automatic form too, which
+    # shows that it took the mixed form: a persistent launch and span steps)
+    for f in ("mixed", "auto"):
+        perc.perc_profile_enable(True)
+        try:
+            p2, s2, h2, c2 = perc.perc_batch(jobs, n_groups=3, hit=True, form=f)
+            torch.cuda.synchronize()
+            prof = perc.perc_profile_read()
+        finally:
+            perc.perc_profile_enable(False)
+        assert torch.equal(p0, p2) and torch.equal(s0, s2) and list(c0) == list(c2), f
+        assert 1 <= prof["persist_launches"] < prof["step_launches"], f
+        assert 0.0 < prof["persist_ms"] < prof["step_ms"], f
+        assert 0 < prof["persist_tube_steps"] < prof["tube_steps"], f
     sel = np.nonzero(jobs["group"] == 1)[0]
     sel = sel[np.argsort(jobs["cfg"][sel])]
     ref = oracle.Lattice(26, 400)
